@@ -1,0 +1,223 @@
+"""Benchmark: weighted model counts per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid24]
+                    [--precision fp64|fp32] [--block B] [--no-cpu-baseline]
+
+A step is one whole solve of the hot path (leaf fill, every pairwise
+contraction of the plan, slice accumulation, result back on the host) for
+one seeded synthetic formula already planned and resident on the device.
+Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import wmc_workloads as wl  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def workload(name: str):
+    """(formula, plan kwargs, description) for a named workload."""
+    if name == "grid24":
+        f = wl.grid_cnf(24, 24, 0.10, seed=0)
+        return f, dict(kind="order", order=wl.row_major_order(24, 24)), \
+            "grid CNF 24x24 lattice (576 vars, 2 planted-sign binary clauses per edge + 110 local ternary), " \
+            "w~U(0.1,0.9), seed 0, row-major sweep tree"
+    if name == "grid12":
+        f = wl.grid_cnf(12, 24, 0.10, seed=1)
+        return f, dict(kind="order", order=wl.row_major_order(12, 24)), "grid CNF 12x24, seed 1, row-major sweep"
+    if name == "config1":
+        f = wl.random_kcnf(20, 85, seed=2)
+        return f, dict(kind="minfill", seed=0), "random 3-CNF 20 vars 85 clauses, seed 2, min-fill tree"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for s in ("wmc_device.hip", "wmc_desc.h"):
+        with open(os.path.join(ROOT, "paper_2006_15512_amd", "csrc", s), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(wname: str, precision: str, block: int):
+    """Counter-derived HBM bytes per launch of the dominant kernel, if the
+    committed profile was taken from the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    key = f"{wname}/{precision}/block{block}"
+    ent = data.get(key)
+    if not ent or ent.get("kernel_sources") != source_digest():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(name: str):
+    """The oracle (FP64 bucket elimination) on a bounded sample of the same
+    workload, scaled to solves/s of the full workload."""
+    import oracle
+    if name.startswith("grid"):
+        rows_full = 24 if name == "grid24" else 12
+        rows = 4
+        f = wl.grid_cnf(rows, 24, 0.10, seed=0)
+        t0 = time.perf_counter()
+        oracle.bucket(f, order=wl.row_major_order(rows, 24))
+        dt = time.perf_counter() - t0
+        per_solve = dt * rows_full / rows
+        sample = (f"oracle bucket elimination on a {rows}x24 strip of the same lattice recipe "
+                  f"(width 25, {rows * 24} vars) in {dt:.1f}s, scaled by {rows_full}/{rows} rows")
+    else:
+        f, _, _ = workload(name)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 5.0:
+            oracle.bucket(f)
+            k += 1
+        dt = time.perf_counter() - t0
+        per_solve = dt / k
+        sample = f"oracle bucket elimination, {k} full solves in {dt:.1f}s"
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid24")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--block", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="a few solves, no timing output (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the slice loop would be split across "
+                                   "GPUs (see the design notes) but no multi-GPU path is built",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2006_15512_amd as W
+
+    torch.cuda.set_device(0)
+    f, pkw, desc = workload(args.workload)
+    net = W.Network.from_formula(f)
+    t0 = time.perf_counter()
+    plan = W.Plan(net, precision=args.precision, block=args.block, **pkw)
+    plan_s = time.perf_counter() - t0
+    st = plan.stats()
+    ws = W.workspace(plan)
+    stream = torch.cuda.current_stream()
+
+    if args.profile_only:
+        for _ in range(max(args.steps, 1)):
+            v = W.wmc_contract(plan, None, ws, stream)
+        torch.cuda.synchronize()
+        print(f"profile-only: {args.steps} solves, W = {v.mantissa} * 2^{v.exp2}", flush=True)
+        return
+
+    for _ in range(args.warmup):
+        v = W.wmc_contract(plan, None, ws, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        v = W.wmc_contract(plan, None, ws, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solves_s = args.steps / dt
+
+    # per-launch timing with HIP events on the launch stream (outside the timed region)
+    bytes_l, flops_l, cls_l = W.plan_launches(plan)
+    reps = 3
+    ms = np.zeros(len(bytes_l))
+    for _ in range(reps):
+        _, m = W.wmc_contract_profile(plan, None, ws, stream)
+        ms += m
+    ms /= reps
+    n_slices = st["n_slices"]
+    by_class = {}
+    for k in range(len(bytes_l)):
+        c = int(cls_l[k])
+        e = by_class.setdefault(c, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0})
+        e["ms"] += float(ms[k])
+        e["bytes"] += float(bytes_l[k]) * n_slices
+        e["flops"] += float(flops_l[k]) * n_slices
+        e["launches"] += n_slices
+    dom = max((c for c in by_class if c >= 0), key=lambda c: by_class[c]["ms"])
+    d = by_class[dom]
+    ach_gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    ach_tf = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    peak_tf = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
+    bound = "hbm" if ach_gbs / HBM_PEAK_GBS >= ach_tf / peak_tf else "mfma"
+    traffic = traffic_for(args.workload, args.precision, args.block)
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+    else:
+        roof = {"bound": "mfma", "achieved": round(ach_tf, 2), "peak": peak_tf, "unit": "TFLOP/s",
+                "frac": round(ach_tf / peak_tf, 4), "traffic": traffic}
+    roof["kernel"] = "k_nodes (" + W.CLASS_NAMES[dom] + " nodes)"
+    roof["launches_per_solve"] = d["launches"]
+    roof["bytes_per_launch"] = d["bytes"] / d["launches"]
+    roof["ms_per_launch"] = d["ms"] / d["launches"]
+    roof["share_of_solve"] = round(d["ms"] / float(ms.sum()), 4)
+
+    total_flops = st["flops_per_slice"] * n_slices
+    total_bytes = st["bytes_per_slice"] * n_slices
+    ms_step = dt / args.steps * 1e3
+    out = {
+        "metric": "WMC solves/s + contraction TFLOP/s (FP64 vs scaled FP32), p50/p99 latency",
+        "value": round(solves_s, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 storage, f64 accumulate",
+        "data": "synthetic",
+        "config": {"workload": desc, "precision": args.precision, "block": args.block,
+                   "max_rank": st["max_rank"], "n_nodes": st["n_nodes"], "n_slices": n_slices,
+                   "class_hist": st["class_hist"], "plan_seconds": round(plan_s, 3)},
+        "contraction_tflops": round(total_flops / (ms_step * 1e-3) / 1e12, 3),
+        "algorithmic_gbs": round(total_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "result": {"mantissa": v.mantissa, "exp2": v.exp2, "log2": v.log2_abs},
+        "roofline": roof,
+    }
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    gname = {"grid24": "grid24x24_t0.10_s0", "grid12": "grid12x24_t0.10_s1"}.get(args.workload)
+    if gname and os.path.exists(gpath):
+        with open(gpath) as fh:
+            g = json.load(fh).get(gname)
+        if g:
+            from fractions import Fraction
+            ref = Fraction(float.fromhex(g["mantissa_hex"])) * Fraction(2) ** g["exp2"]
+            got = Fraction(v.mantissa) * Fraction(2) ** v.exp2
+            out["rel_err_vs_oracle"] = float(abs(got - ref) / abs(ref)) if ref else float(abs(got))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * wmc.h - C ABI of the MI355X tensor-network weighted model counter.
+ *
+ * The library computes the literal-weighted model count of a CNF formula
+ * (Definition 1 of Dudek & Vardi, "Parallel Weighted Model Counting with
+ * Tensor Networks"):
+ *
+ *     W(phi) = sum over tau in {0,1}^X of phi(tau) * prod_x W(x, tau(x))
+ *
+ * by the paper's three stages (Algorithm 1): the formula is reduced to a
+ * tensor network (Theorem 2: one clause tensor B_C per clause, one
+ * COPY/weight tensor A_x per variable, over binary indices), a contraction
+ * tree is planned (Definition of a contraction tree; index slicing under a
+ * memory bound, Algorithm 3), and the network is contracted pairwise along
+ * the tree on the GPU (Algorithm 2), summing the slices (the slicing
+ * theorem).
+ *
+ * Conventions
+ *  - Every call returns wmc_status; nothing throws across the ABI.  On a
+ *    non-OK status wmc_last_error() returns a thread-local message.
+ *  - Inputs are copied at call time; the caller keeps ownership of every
+ *    pointer it passes.  Handles are owned by the caller and released with
+ *    the matching *_destroy (NULL is accepted and ignored).
+ *  - Networks and plans are immutable after creation and may be shared
+ *    between threads.  wmc_contract is reentrant given distinct workspaces.
+ *  - Device memory belongs to the caller: wmc_contract runs entirely inside
+ *    a caller-supplied device workspace of wmc_plan_info.workspace_bytes.
+ *  - Streams are hipStream_t passed as void* (NULL = the default stream).
+ *  - Variables are numbered 1..n_vars; literals are DIMACS signed integers.
+ */
+#ifndef WMC_H
+#define WMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WMC_OK = 0,
+    WMC_ERR_INVALID_ARGUMENT = 1, /* bad literal, NaN/Inf weight, malformed order/tree, NULL */
+    WMC_ERR_OUT_OF_MEMORY = 2,    /* host allocation failed, or workspace too small */
+    WMC_ERR_CAP_UNREACHABLE = 3,  /* slicing cannot meet the memory / rank cap */
+    WMC_ERR_DEVICE = 4,           /* a HIP call failed; message in wmc_last_error() */
+    WMC_ERR_BUSY = 5,             /* server queue full */
+    WMC_ERR_UNSUPPORTED = 6       /* clause longer than WMC_MAX_CLAUSE, rank too large */
+} wmc_status;
+
+typedef enum { WMC_FP64 = 0, WMC_FP32_SCALED = 1 } wmc_precision;
+
+typedef enum {
+    WMC_TREE_MINFILL = 0,  /* seeded min-fill elimination order -> bucket tree */
+    WMC_TREE_ORDER = 1,    /* caller-supplied elimination order -> bucket tree */
+    WMC_TREE_EXPLICIT = 2  /* caller-supplied contraction tree (parent array) */
+} wmc_tree_kind;
+
+#define WMC_MAX_CLAUSE 24   /* distinct variables per clause */
+#define WMC_MAX_RANK 34     /* largest storage rank of any intermediate */
+#define WMC_MAX_SLICED 40   /* largest number of sliced variables */
+
+/* A result: W = mantissa * 2^exp2 with |mantissa| in [0.5, 1), or exactly 0.
+ * value = ldexp(mantissa, exp2) (may under- or overflow to 0 / inf);
+ * log2_abs = log2|W| (-inf for 0). */
+typedef struct {
+    double mantissa;
+    int64_t exp2;
+    double value;
+    double log2_abs;
+} wmc_value;
+
+typedef struct wmc_network wmc_network;
+typedef struct wmc_plan_t wmc_plan_t;
+
+/* ------------------------------------------------------------------ */
+/* Reduction stage (Theorem 2)                                          */
+/* ------------------------------------------------------------------ */
+
+/* Build the tensor network of Theorem 2 from a CNF and literal weights.
+ *   clause_ptr: n_clauses+1 offsets into lits (CSR), host memory
+ *   lits:       DIMACS literals in 1..n_vars or -n_vars..-1, host memory
+ *   weights:    2*n_vars doubles {W(x,0), W(x,1)} for x = 1..n_vars (finite)
+ * Repeated literals collapse; a clause holding x and not-x is always true;
+ * an empty clause makes W = 0; a variable in no clause contributes
+ * W(x,0)+W(x,1).  Clauses with more than WMC_MAX_CLAUSE distinct variables
+ * return WMC_ERR_UNSUPPORTED.  The COPY tensors A_x are kept symbolically
+ * (degree, W(x,0), W(x,1)) and never materialised. */
+wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
+                             const int32_t *lits, const double *weights, wmc_network **out);
+
+/* Size of the Theorem-2 network: n_tensors = n_vars + n_clauses tensors,
+ * n_indices = number of (variable, clause) incidences (distinct per clause). */
+wmc_status wmc_network_info(const wmc_network *net, int64_t *n_tensors, int64_t *n_indices);
+
+void wmc_network_destroy(wmc_network *net);
+
+/* ------------------------------------------------------------------ */
+/* Planning stage: contraction tree + index slicing (Algorithm 3)       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t kind;            /* wmc_tree_kind */
+    int32_t precision;       /* wmc_precision */
+    uint64_t seed;           /* WMC_TREE_MINFILL tie-break seed */
+    const int32_t *order;    /* WMC_TREE_ORDER: permutation of 1..n_vars (host) */
+    int32_t order_len;
+    int32_t block;           /* variables eliminated together per bucket step (>=1; 0 = 1) */
+    const int64_t *parent;   /* WMC_TREE_EXPLICIT: parent of each tree vertex, -1 at the root.
+                                Vertices 0..n-1 are A_x (x = i+1), n..n+m-1 are B_C (clause
+                                i-n), n+m..2(n+m)-2 are internal; every internal vertex has
+                                exactly two children. */
+    int64_t n_tree_nodes;    /* = 2(n+m)-1 */
+    uint64_t mem_cap_bytes;  /* Algorithm 3 bound m on the peak live tensor bytes; 0 = none */
+    int32_t rank_cap;        /* bound on the largest storage rank; 0 = none */
+    int32_t reserved[7];
+} wmc_plan_options;
+
+/* Node classes of the histogram in wmc_plan_info. */
+enum { WMC_CLASS_SMALL = 0, WMC_CLASS_STREAM = 1, WMC_CLASS_GEMM = 2, WMC_N_CLASSES = 4 };
+
+typedef struct {
+    int32_t n_vars;
+    int32_t precision;
+    int64_t n_clauses;
+    int64_t n_tensors;          /* leaves + internal nodes of the tree */
+    int64_t n_nodes;            /* internal nodes = pairwise contractions */
+    int32_t max_rank;           /* largest storage rank (distinct variables) per slice */
+    int32_t max_rank_unsliced;  /* the same before slicing */
+    int32_t max_index_rank;     /* largest rank counting Theorem-2 indices (unsliced) */
+    int32_t n_sliced;           /* |I| */
+    int64_t n_slices;           /* 2^|I| */
+    int32_t sliced_vars[WMC_MAX_SLICED];
+    double flops_per_slice;     /* sum over nodes of 2*b*m*n*k */
+    double bytes_per_slice;     /* sum over nodes of elem_size*(|A|+|B|+|C|) */
+    double peak_live_bytes;     /* MemCost: peak of live tensor bytes over the schedule */
+    uint64_t arena_bytes;       /* static arena after placement */
+    uint64_t workspace_bytes;   /* device workspace wmc_contract needs */
+    int64_t class_hist[WMC_N_CLASSES];
+    int64_t n_launches;         /* kernel launches per slice */
+    double max_node_bytes;      /* largest single-node traffic */
+} wmc_plan_info;
+
+wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *opts, wmc_plan_t **out);
+wmc_status wmc_plan_stats(const wmc_plan_t *plan, wmc_plan_info *out);
+void wmc_plan_destroy(wmc_plan_t *plan);
+
+/* Plan inspection, for tools and tests (host only, any pointer may be NULL).
+ * Tensors are numbered 0..n_tensors-1 in creation order.
+ *   wmc_plan_tensor: kind 0 = clause leaf (src = clause index), 1 = weight
+ *     leaf A_x (src = variable), 2 = internal (src = -1); rank and vars give the
+ *     storage layout after slicing, least-significant bit first (vars needs
+ *     room for WMC_MAX_RANK entries).
+ *   wmc_plan_node: node i (launch order) contracts tensors a and b into c.
+ *   wmc_plan_image: the raw device descriptors as they are uploaded
+ *     ([leaf descriptors][node descriptors][launch list]); with dst == NULL it
+ *     only reports *needed and info[0..10] = {n_leaves, n_nodes, n_launches,
+ *     arena_elems, root, root_offset, n_tensors, elem_bytes, leaf_desc_bytes,
+ *     node_desc_bytes, launch_bytes}. */
+wmc_status wmc_plan_tensor(const wmc_plan_t *plan, int64_t t, int32_t *kind, int32_t *src,
+                           int32_t *rank, int32_t *vars);
+wmc_status wmc_plan_node(const wmc_plan_t *plan, int64_t i, int64_t *a, int64_t *b, int64_t *c,
+                         int32_t *node_class);
+wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t dst_bytes, uint64_t *needed,
+                          int64_t *info /* 11 entries */);
+
+/* ------------------------------------------------------------------ */
+/* Execution stage (Algorithm 2 over the slices of Algorithm 3)         */
+/* ------------------------------------------------------------------ */
+
+/* Contract the planned network on the current HIP device.
+ *   weights:   2*n_vars host doubles replacing the network's weights, or NULL
+ *   workspace: device pointer of at least wmc_plan_info.workspace_bytes,
+ *              256-byte aligned, owned by the caller; clobbered
+ *   stream:    hipStream_t (void*), NULL for the default stream
+ * Blocks until the result is on the host.  Errors: INVALID_ARGUMENT (NULL,
+ * misaligned or non-finite weights), OUT_OF_MEMORY (workspace too small),
+ * DEVICE (HIP failure). */
+wmc_status wmc_contract(const wmc_plan_t *plan, const double *weights, void *workspace,
+                        uint64_t workspace_bytes, void *stream, wmc_value *out);
+
+/* As wmc_contract, restricted to the slices eta in [slice_begin, slice_end)
+ * (the slicing theorem: their sum is a partial sum of W).  If per_slice is
+ * not NULL it receives one value per slice in that range. */
+wmc_status wmc_contract_slices(const wmc_plan_t *plan, const double *weights, void *workspace,
+                               uint64_t workspace_bytes, void *stream, int64_t slice_begin,
+                               int64_t slice_end, wmc_value *out, wmc_value *per_slice);
+
+/* Per-launch accounting for measurement.  Launch k of one slice, in the
+ * order wmc_contract issues them: 0 = meta reset, 1 = leaf fill, then the
+ * node launches, last = slice accumulation.  wmc_plan_launches gives each
+ * launch's algorithmic bytes (elem_size * (|A|+|B|+|C|) summed over its
+ * nodes), flops (2*b*m*n*k) and node class (-1 for non-node launches); with
+ * all arrays NULL it only reports *n_out.  wmc_contract_profile is
+ * wmc_contract with a HIP event recorded on `stream` after every launch;
+ * ms[k] (k < n_out - 1... one entry per launch) receives the duration of
+ * launch k summed over the slices. */
+wmc_status wmc_plan_launches(const wmc_plan_t *plan, double *bytes, double *flops, int32_t *cls,
+                             int64_t cap, int64_t *n_out);
+wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double *weights, void *workspace,
+                                uint64_t workspace_bytes, void *stream, float *ms, int64_t cap,
+                                wmc_value *out);
+
+/* Thread-local description of the last non-OK status on this thread. */
+const char *wmc_last_error(void);
+
+/* Library version string. */
+const char *wmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WMC_H */

@@ -1,0 +1,344 @@
+"""Python binding of libwmc (the MI355X tensor-network weighted model counter).
+
+Argument marshalling only: every step of the reduction, planning and
+contraction runs in the C/HIP library.  PyTorch is used for device memory
+(the caller-owned workspace) and streams.  The functions keep the C-ABI
+names: ``wmc_build_network``, ``wmc_plan``, ``wmc_contract``; ``Network``,
+``Plan`` and ``contract`` are convenience wrappers around them.
+
+If the library has not been built the import still succeeds (so the build
+step can run), but every call raises :class:`WmcLibraryMissing`: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, NamedTuple, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwmc.so")
+
+WMC_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAP_UNREACHABLE",
+                4: "DEVICE", 5: "BUSY", 6: "UNSUPPORTED"}
+FP64, FP32_SCALED = 0, 1
+TREE_MINFILL, TREE_ORDER, TREE_EXPLICIT = 0, 1, 2
+MAX_RANK = 34
+MAX_SLICED = 40
+N_CLASSES = 4
+CLASS_NAMES = ["small", "stream", "gemm", "other"]
+
+
+class WmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class WmcLibraryMissing(RuntimeError):
+    pass
+
+
+class wmc_value(ctypes.Structure):
+    _fields_ = [("mantissa", ctypes.c_double), ("exp2", ctypes.c_int64),
+                ("value", ctypes.c_double), ("log2_abs", ctypes.c_double)]
+
+
+class wmc_plan_options(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("order", ctypes.POINTER(ctypes.c_int32)), ("order_len", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("parent", ctypes.POINTER(ctypes.c_int64)),
+                ("n_tree_nodes", ctypes.c_int64), ("mem_cap_bytes", ctypes.c_uint64),
+                ("rank_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class wmc_plan_info(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_clauses", ctypes.c_int64),
+                ("n_tensors", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("max_rank", ctypes.c_int32),
+                ("max_rank_unsliced", ctypes.c_int32), ("max_index_rank", ctypes.c_int32),
+                ("n_sliced", ctypes.c_int32), ("n_slices", ctypes.c_int64),
+                ("sliced_vars", ctypes.c_int32 * MAX_SLICED), ("flops_per_slice", ctypes.c_double),
+                ("bytes_per_slice", ctypes.c_double), ("peak_live_bytes", ctypes.c_double),
+                ("arena_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
+                ("class_hist", ctypes.c_int64 * N_CLASSES), ("n_launches", ctypes.c_int64),
+                ("max_node_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libwmc.so (raises WmcLibraryMissing if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise WmcLibraryMissing(f"{LIB_PATH} not built: run `python -m paper_2006_15512_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        sigs = {
+            "wmc_build_network": [i32, i64, P, P, P, P],
+            "wmc_network_info": [P, P, P],
+            "wmc_plan": [P, ctypes.POINTER(wmc_plan_options), P],
+            "wmc_plan_stats": [P, ctypes.POINTER(wmc_plan_info)],
+            "wmc_plan_tensor": [P, i64, P, P, P, P],
+            "wmc_plan_node": [P, i64, P, P, P, P],
+            "wmc_plan_image": [P, P, u64, P, P],
+            "wmc_contract": [P, P, P, u64, P, ctypes.POINTER(wmc_value)],
+            "wmc_contract_slices": [P, P, P, u64, P, i64, i64, ctypes.POINTER(wmc_value), P],
+            "wmc_plan_launches": [P, P, P, P, i64, P],
+            "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        for name in ("wmc_network_destroy", "wmc_plan_destroy"):
+            getattr(L, name).argtypes = [P]
+            getattr(L, name).restype = None
+        L.wmc_last_error.restype = ctypes.c_char_p
+        L.wmc_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int) -> None:
+    if st != WMC_OK:
+        raise WmcError(st, lib().wmc_last_error().decode())
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None or a.size == 0 else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Value(NamedTuple):
+    mantissa: float
+    exp2: int
+    value: float
+    log2_abs: float
+
+    @staticmethod
+    def of(v: wmc_value) -> "Value":
+        return Value(v.mantissa, int(v.exp2), v.value, v.log2_abs)
+
+
+# ---------------------------------------------------------------------------
+# reduction
+# ---------------------------------------------------------------------------
+class Network:
+    """wmc_build_network over a CNF (list of DIMACS clauses) and weights (n, 2)."""
+
+    def __init__(self, n: int, clauses: Sequence[Sequence[int]], weights):
+        ptr = np.zeros(len(clauses) + 1, dtype=np.int64)
+        for i, c in enumerate(clauses):
+            ptr[i + 1] = ptr[i] + len(c)
+        lits = np.array([l for c in clauses for l in c], dtype=np.int32)
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        if w.size != 2 * n:
+            raise ValueError("weights must have 2*n entries")
+        h = ctypes.c_void_p()
+        _check(lib().wmc_build_network(int(n), len(clauses), _p(ptr) if len(clauses) else None,
+                                       _p(lits), _p(w), ctypes.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.m = len(clauses)
+
+    @classmethod
+    def from_formula(cls, f) -> "Network":
+        return cls(f.n, f.clauses, f.weights)
+
+    def info(self) -> Dict[str, int]:
+        nt, ni = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().wmc_network_info(self._h, ctypes.byref(nt), ctypes.byref(ni)))
+        return {"n_tensors": nt.value, "n_indices": ni.value}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.wmc_network_destroy(h)
+            self._h = None
+
+
+def wmc_build_network(n, clauses, weights) -> Network:
+    return Network(n, clauses, weights)
+
+
+# ---------------------------------------------------------------------------
+# planning
+# ---------------------------------------------------------------------------
+class Plan:
+    """wmc_plan: contraction tree + slicing + layouts for one network."""
+
+    def __init__(self, net: Network, kind: str = "minfill", seed: int = 0,
+                 order: Optional[Sequence[int]] = None, parent: Optional[Sequence[int]] = None,
+                 mem_cap_bytes: int = 0, rank_cap: int = 0, precision: str = "fp64", block: int = 1):
+        o = wmc_plan_options()
+        o.kind = {"minfill": TREE_MINFILL, "order": TREE_ORDER, "explicit": TREE_EXPLICIT}[kind]
+        o.precision = {"fp64": FP64, "fp32": FP32_SCALED, "fp32_scaled": FP32_SCALED}[precision]
+        o.seed = int(seed)
+        o.block = int(block)
+        self._order = self._parent = None
+        if order is not None:
+            self._order = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+            o.order = self._order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            o.order_len = int(self._order.size)
+        if parent is not None:
+            self._parent = np.ascontiguousarray(np.asarray(parent, dtype=np.int64))
+            o.parent = self._parent.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            o.n_tree_nodes = int(self._parent.size)
+        o.mem_cap_bytes = int(mem_cap_bytes)
+        o.rank_cap = int(rank_cap)
+        h = ctypes.c_void_p()
+        _check(lib().wmc_plan(net._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.net = net
+        self.precision = precision
+        self._info = wmc_plan_info()
+        _check(lib().wmc_plan_stats(self._h, ctypes.byref(self._info)))
+
+    def stats(self) -> Dict:
+        i = self._info
+        d = {name: getattr(i, name) for name, _ in wmc_plan_info._fields_}
+        d["sliced_vars"] = list(i.sliced_vars)[: i.n_sliced]
+        d["class_hist"] = {CLASS_NAMES[k]: int(i.class_hist[k]) for k in range(N_CLASSES)}
+        return d
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._info.workspace_bytes)
+
+    @property
+    def n_slices(self) -> int:
+        return int(self._info.n_slices)
+
+    def tensor(self, t: int):
+        kind, src, rank = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        vars_ = (ctypes.c_int32 * (MAX_RANK + 1))()
+        _check(lib().wmc_plan_tensor(self._h, int(t), ctypes.byref(kind), ctypes.byref(src),
+                                     ctypes.byref(rank), vars_))
+        return kind.value, src.value, list(vars_)[: rank.value]
+
+    def node(self, i: int):
+        a, b, c, cls = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().wmc_plan_node(self._h, int(i), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                   ctypes.byref(cls)))
+        return a.value, b.value, c.value, cls.value
+
+    def export(self):
+        """(tensors, nodes, sliced_vars): tensors[t] = (kind, src, layout),
+        nodes[i] = (a, b, c, class) in launch order."""
+        s = self.stats()
+        tensors = [self.tensor(t) for t in range(s["n_tensors"])]
+        nodes = [self.node(i) for i in range(s["n_nodes"])]
+        return tensors, nodes, s["sliced_vars"]
+
+    def image(self):
+        """Raw descriptor image: (bytes, info dict) as uploaded to the device."""
+        need = ctypes.c_uint64()
+        info = (ctypes.c_int64 * 11)()
+        _check(lib().wmc_plan_image(self._h, None, 0, ctypes.byref(need), info))
+        buf = (ctypes.c_uint8 * max(int(need.value), 1))()
+        _check(lib().wmc_plan_image(self._h, buf, int(need.value), ctypes.byref(need), info))
+        keys = ["n_leaves", "n_nodes", "n_launches", "arena_elems", "root", "root_off", "n_tensors",
+                "elem", "leaf_desc_bytes", "node_desc_bytes", "launch_bytes"]
+        return bytes(buf)[: int(need.value)], dict(zip(keys, list(info)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.wmc_plan_destroy(h)
+            self._h = None
+
+
+def wmc_plan(net: Network, **kw) -> Plan:
+    return Plan(net, **kw)
+
+
+# ---------------------------------------------------------------------------
+# execution
+# ---------------------------------------------------------------------------
+def workspace(plan: Plan, device: str = "cuda:0"):
+    """A caller-owned device workspace for ``plan`` (a torch uint8 tensor)."""
+    import torch
+    n = max(plan.workspace_bytes, 256)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def wmc_contract(plan: Plan, weights=None, ws=None, stream=None) -> Value:
+    """Contract ``plan`` on the GPU; ``ws`` is a device tensor of at least
+    plan.workspace_bytes (allocated here if omitted)."""
+    if ws is None:
+        ws = workspace(plan)
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        if w.size != 2 * plan.net.n:
+            raise ValueError("weights must have 2*n entries")
+    out = wmc_value()
+    _check(lib().wmc_contract(plan._h, _p(w), ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                              _stream_ptr(stream), ctypes.byref(out)))
+    return Value.of(out)
+
+
+def wmc_contract_slices(plan: Plan, begin: int, end: int, weights=None, ws=None, stream=None,
+                        per_slice: bool = False):
+    """Sum of slices [begin, end); with per_slice=True also each slice's value."""
+    if ws is None:
+        ws = workspace(plan)
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    out = wmc_value()
+    arr = (wmc_value * max(end - begin, 1))() if per_slice else None
+    _check(lib().wmc_contract_slices(plan._h, _p(w), ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel() * ws.element_size(), _stream_ptr(stream), int(begin), int(end),
+                                     ctypes.byref(out), arr))
+    if per_slice:
+        return Value.of(out), [Value.of(arr[i]) for i in range(end - begin)]
+    return Value.of(out)
+
+
+contract = wmc_contract
+
+
+def plan_launches(plan: Plan):
+    """Per-launch algorithmic (bytes, flops, class) of one slice, in issue order."""
+    n = ctypes.c_int64()
+    _check(lib().wmc_plan_launches(plan._h, None, None, None, 0, ctypes.byref(n)))
+    k = int(n.value)
+    b = np.zeros(k)
+    f = np.zeros(k)
+    c = np.zeros(k, dtype=np.int32)
+    _check(lib().wmc_plan_launches(plan._h, _p(b), _p(f), _p(c), k, ctypes.byref(n)))
+    return b, f, c
+
+
+def wmc_contract_profile(plan: Plan, weights=None, ws=None, stream=None):
+    """wmc_contract with HIP events between launches: (value, ms per launch)."""
+    if ws is None:
+        ws = workspace(plan)
+    b, _, _ = plan_launches(plan)
+    ms = np.zeros(len(b), dtype=np.float32)
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    out = wmc_value()
+    _check(lib().wmc_contract_profile(plan._h, _p(w), ctypes.c_void_p(ws.data_ptr()),
+                                      ws.numel() * ws.element_size(), _stream_ptr(stream), _p(ms), len(ms),
+                                      ctypes.byref(out)))
+    return Value.of(out), ms
+
+
+def version() -> str:
+    return lib().wmc_version().decode()

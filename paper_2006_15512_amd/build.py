@@ -1,0 +1,56 @@
+"""Build libwmc.so in-tree for gfx950.
+
+    python -m paper_2006_15512_amd.build
+
+The host planner (C++17) is compiled with g++, the kernels with hipcc for
+gfx950 only; packed-FP32 instructions are disabled for all device code.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libwmc.so")
+BUILD_DIR = os.path.join(ROOT, "_build")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+HOST_SOURCES = ["wmc_host.cpp"]
+DEVICE_SOURCES = ["wmc_device.hip"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build(verbose: bool = False, debug: bool = False) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    inc = ["-I", CSRC, "-I", os.path.join(ROOT, "include")]
+    opt = ["-O0", "-g"] if debug else ["-O3"]
+    objs = []
+    for s in HOST_SOURCES:
+        o = os.path.join(BUILD_DIR, s + ".o")
+        _run(["g++", "-std=c++17", *opt, "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter", *inc, "-c",
+              os.path.join(CSRC, s), "-o", o], verbose)
+        objs.append(o)
+    for s in DEVICE_SOURCES:
+        o = os.path.join(BUILD_DIR, s + ".o")
+        _run([HIPCC, "-std=c++17", *opt, "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-Wall",
+              "-Wno-unused-command-line-argument", *inc, "-c", os.path.join(CSRC, s), "-o", o], verbose)
+        objs.append(o)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv, debug="--debug" in sys.argv))

@@ -1,0 +1,418 @@
+// Execution stage on gfx950: the pairwise contractions of Algorithm 2 over
+// the slices of Algorithm 3, all on the device.
+//
+// Numerics.  Every tensor t carries an exponent: its true entries are
+// stored * 2^exp.  A node reads the largest magnitude of each operand (kept
+// by the producer with an integer atomicMax on the IEEE bits), scales the
+// operand by the power of two that brings that maximum into [0.5, 1) while
+// it contracts (exact for normal numbers), and adds both shifts to the
+// output's exponent.  Sums are formed in double for both storage
+// precisions; the FP32 path rounds once when it stores.  Slices are summed
+// in double as (s + c) * 2^e with Neumaier compensation, in slice order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "wmc_internal.h"
+
+#define WMC_BLOCK 256
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int scale_exp(unsigned long long maxbits) {
+    double m = __longlong_as_double((long long)maxbits);
+    if (!(m > 0.0)) return 0;
+    int e;
+    frexp(m, &e);
+    return e;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WMC_WAVE));
+    return v;
+}
+
+__device__ __forceinline__ void publish_max(wmc_meta *meta, int t, double v) {
+    v = wave_max(v);
+    if ((threadIdx.x & (WMC_WAVE - 1)) == 0 && v > 0.0)
+        atomicMax(&meta[t].maxbits, (unsigned long long)__double_as_longlong(v));
+}
+
+// bit extraction of r along runs (src bit, length, dst bit)
+__device__ __forceinline__ unsigned long long pext_runs(unsigned long long r, const unsigned char (*runs)[3], int nr) {
+    unsigned long long out = 0;
+    for (int q = 0; q < nr; ++q) {
+        unsigned s = runs[q][0], l = runs[q][1], d = runs[q][2];
+        out |= ((r >> s) & ((1ull << l) - 1ull)) << d;
+    }
+    return out;
+}
+
+template <typename T>
+__device__ __forceinline__ double ld(const T *p) { return (double)*p; }
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void k_begin(wmc_meta *meta, int nt, wmc_acc *acc, int reset) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nt) {
+        meta[i].maxbits = 0ull;
+        meta[i].exp = 0;
+    }
+    if (i == 0 && reset) {
+        acc->s = 0.0;
+        acc->c = 0.0;
+        acc->e = 0;
+        acc->n_added = 0;
+        acc->last_m = 0.0;
+        acc->last_e = 0;
+    }
+}
+
+// Leaf fill (Theorem 2): clause tables B_C restricted to the slice, weight
+// vectors [W(x,0), W(x,1)], or W(x,0)+W(x,1) for a variable in no clause.
+template <typename T>
+__global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict__ L, int nl, long long work,
+                                                      const double *__restrict__ w, T *__restrict__ arena,
+                                                      wmc_meta *meta, unsigned long long eta) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
+        int lo = 0, hi = nl - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (L[mid].work_begin <= g) lo = mid; else hi = mid - 1;
+        }
+        const LeafDesc &d = L[lo];
+        const long long e = g - d.work_begin;
+        const bool valid = e < (1ll << d.rank);
+        double v = 0.0;
+        if (valid) {
+            if (d.kind == WMC_LEAF_CLAUSE) {
+                unsigned a = 0;
+                for (int q = 0; q < d.k; ++q) {
+                    int p = d.pos[q];
+                    unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((eta >> (-p - 1)) & 1ull);
+                    a |= bit << q;
+                }
+                v = (d.taut || a != d.falsify) ? 1.0 : 0.0;
+            } else if (d.kind == WMC_LEAF_WEIGHT) {
+                int p = d.pos[0];
+                unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((eta >> (-p - 1)) & 1ull);
+                v = w[2 * d.var + bit];
+            } else {
+                v = w[2 * d.var] + w[2 * d.var + 1];
+            }
+            T s = (T)v;
+            arena[d.out + e] = s;
+            v = fabs((double)s);
+        }
+        publish_max(meta, d.tensor, v);
+    }
+}
+
+// Pairwise contraction, any shape: one output entry per thread,
+// C[r] = 2^-(sA+sB) * sum_j A[(pext_A(r) << nk) | j] * B[(pext_B(r) << nk) | j].
+// A launch covers a run of nodes; each node's outputs are padded to a wave
+// multiple so that a wave never straddles two nodes.
+template <typename T>
+__global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict__ D, int nd, long long work,
+                                                     T *__restrict__ arena, wmc_meta *meta) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
+        int lo = 0, hi = nd - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (D[mid].work_begin <= g) lo = mid; else hi = mid - 1;
+        }
+        const NodeDesc &d = D[lo];
+        const unsigned long long r = (unsigned long long)(g - d.work_begin);
+        const bool valid = r < (1ull << d.rc);
+        const int sA = scale_exp(meta[d.ta].maxbits);
+        const int sB = scale_exp(meta[d.tb].maxbits);
+        double v = 0.0;
+        if (valid) {
+            const T *A = arena + d.a + (pext_runs(r, d.ra, d.nra) << d.nk);
+            const T *B = arena + d.b + (pext_runs(r, d.rb, d.nrb) << d.nk);
+            const int K = 1 << d.nk;
+            double acc = 0.0;
+            for (int j = 0; j < K; ++j) acc = fma(ld(A + j), ld(B + j), acc);
+            T s = (T)ldexp(acc, -(sA + sB));
+            arena[d.c + (long long)r] = s;
+            v = fabs((double)s);
+        }
+        publish_max(meta, d.tc, v);
+        if (r == 0) meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
+    }
+}
+
+// Root of one slice: fold its value into the running sum (s + c) * 2^e.
+template <typename T>
+__global__ void k_finish(const T *__restrict__ arena, long long root_off, const wmc_meta *meta, int root,
+                         wmc_acc *acc) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double v = (double)arena[root_off];
+    long long e = meta[root].exp;
+    if (v != 0.0) {
+        int k;
+        v = frexp(v, &k);
+        e += k;
+    } else {
+        e = 0;
+    }
+    acc->last_m = v;
+    acc->last_e = e;
+    if (v == 0.0) return;
+    if (acc->s == 0.0 && acc->c == 0.0) {
+        acc->s = v;
+        acc->c = 0.0;
+        acc->e = e;
+    } else {
+        if (e > acc->e) {
+            long long d = acc->e - e;
+            int di = d < -4000 ? -4000 : (int)d;
+            acc->s = ldexp(acc->s, di);
+            acc->c = ldexp(acc->c, di);
+            acc->e = e;
+        }
+        long long d = e - acc->e;
+        double t = ldexp(v, d < -4000 ? -4000 : (int)d);
+        double s = acc->s + t;
+        if (fabs(acc->s) >= fabs(t)) acc->c += (acc->s - s) + t;
+        else acc->c += (t - s) + acc->s;
+        acc->s = s;
+        if (acc->s != 0.0) {
+            int k;
+            acc->s = frexp(acc->s, &k);
+            acc->c = ldexp(acc->c, -k);
+            acc->e += k;
+        }
+    }
+    acc->n_added += 1;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static wmc_value make_value(double m, long long e) {
+    wmc_value v;
+    if (m == 0.0 || !std::isfinite(m)) {
+        v.mantissa = m == 0.0 ? 0.0 : m;
+        v.exp2 = 0;
+        v.value = m;
+        v.log2_abs = m == 0.0 ? -INFINITY : NAN;
+        return v;
+    }
+    int k;
+    double mm = std::frexp(m, &k);
+    v.mantissa = mm;
+    v.exp2 = e + k;
+    long long ee = v.exp2;
+    v.value = std::ldexp(mm, ee > 5000 ? 5000 : (ee < -5000 ? -5000 : (int)ee));
+    v.log2_abs = std::log2(std::fabs(mm)) + (double)v.exp2;
+    return v;
+}
+
+static unsigned grid_for(long long work) {
+    long long b = (work + WMC_BLOCK - 1) / WMC_BLOCK;
+    if (b < 1) b = 1;
+    if (b > (1ll << 20)) b = 1ll << 20;
+    return (unsigned)b;
+}
+
+#define HIP_TRY(call)                                                                     \
+    do {                                                                                  \
+        hipError_t _e = (call);                                                           \
+        if (_e != hipSuccess) {                                                           \
+            wmc_set_error("%s failed: %s", #call, hipGetErrorString(_e));                 \
+            return WMC_ERR_DEVICE;                                                        \
+        }                                                                                 \
+    } while (0)
+
+// Optional per-launch timing: an event is recorded on the stream after every
+// launch; ms[k] accumulates launch k's duration over the slices.
+struct LaunchTimer {
+    std::vector<hipEvent_t> ev;
+    float *ms = nullptr;
+    int64_t cap = 0;
+    size_t k = 0;
+    hipStream_t st = nullptr;
+    void mark() {
+        if (!ms) return;
+        if (k < ev.size()) (void)hipEventRecord(ev[k], st);
+        ++k;
+    }
+};
+
+template <typename T>
+static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long long b, long long e,
+                             wmc_value *per_slice, LaunchTimer *tm = nullptr) {
+    wmc_meta *meta = (wmc_meta *)(ws + P.off_meta);
+    wmc_acc *acc = (wmc_acc *)(ws + P.off_acc);
+    const double *w = (const double *)(ws + P.off_w);
+    const LeafDesc *L = (const LeafDesc *)(ws + P.off_leaf);
+    const NodeDesc *D = (const NodeDesc *)(ws + P.off_node);
+    T *arena = (T *)(ws + P.off_arena);
+    const int nt = (int)P.T.size();
+    for (long long eta = b; eta < e; ++eta) {
+        if (tm) {
+            tm->k = 0;
+            tm->mark();
+        }
+        hipLaunchKernelGGL(k_begin, dim3((nt + WMC_BLOCK - 1) / WMC_BLOCK), dim3(WMC_BLOCK), 0, st, meta, nt, acc,
+                           eta == b ? 1 : 0);
+        if (tm) tm->mark();
+        if (!P.leaves.empty())
+            hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(P.leaf_work)), dim3(WMC_BLOCK), 0, st, L,
+                               (int)P.leaves.size(), (long long)P.leaf_work, w, arena, meta,
+                               (unsigned long long)eta);
+        if (tm) tm->mark();
+        for (size_t k = 1; k < P.launches.size(); ++k) {
+            const Launch &Ln = P.launches[k];
+            hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first, Ln.count,
+                               (long long)Ln.work, arena, meta);
+            if (tm) tm->mark();
+        }
+        hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(1), 0, st, arena, (long long)P.T[(size_t)P.root].off, meta,
+                           P.root, acc);
+        if (tm) tm->mark();
+        HIP_TRY(hipGetLastError());
+        if (tm) {
+            HIP_TRY(hipEventSynchronize(tm->ev[tm->k - 1]));
+            for (size_t q = 1; q < tm->k && (int64_t)(q - 1) < tm->cap; ++q) {
+                float t = 0.f;
+                HIP_TRY(hipEventElapsedTime(&t, tm->ev[q - 1], tm->ev[q]));
+                tm->ms[q - 1] += t;
+            }
+        }
+        if (per_slice) {
+            wmc_acc h;
+            HIP_TRY(hipMemcpyAsync(&h, acc, sizeof h, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            per_slice[eta - b] = make_value(h.last_m, h.last_e);
+        }
+    }
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_contract_slices(const wmc_plan_t *plan, const double *weights, void *workspace,
+                                          uint64_t workspace_bytes, void *stream, int64_t slice_begin,
+                                          int64_t slice_end, wmc_value *out, wmc_value *per_slice) {
+    if (!plan || !out) {
+        wmc_set_error("wmc_contract: NULL plan or out");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    const wmc_plan_t &P = *plan;
+    const int64_t ns = (int64_t)1 << P.sliced.size();
+    if (slice_begin < 0 || slice_end > ns || slice_begin > slice_end) {
+        wmc_set_error("wmc_contract: slice range [%lld, %lld) outside [0, %lld)", (long long)slice_begin,
+                      (long long)slice_end, (long long)ns);
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (weights)
+        for (int64_t i = 0; i < 2 * (int64_t)P.n; ++i)
+            if (!std::isfinite(weights[i])) {
+                wmc_set_error("wmc_contract: weight %lld is not finite", (long long)i);
+                return WMC_ERR_INVALID_ARGUMENT;
+            }
+    if (P.root < 0) {  // no variables and no clauses: the empty product
+        *out = make_value(1.0, 0);
+        if (per_slice)
+            for (int64_t s = slice_begin; s < slice_end; ++s) per_slice[s - slice_begin] = *out;
+        return WMC_OK;
+    }
+    if (!workspace || ((uintptr_t)workspace & 255u)) {
+        wmc_set_error("wmc_contract: workspace is NULL or not 256-byte aligned");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (workspace_bytes < P.workspace_bytes) {
+        wmc_set_error("wmc_contract: workspace has %llu bytes, plan needs %llu", (unsigned long long)workspace_bytes,
+                      (unsigned long long)P.workspace_bytes);
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    if (slice_begin == slice_end) {
+        *out = make_value(0.0, 0);
+        return WMC_OK;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    const double *w = weights ? weights : P.w.data();
+    if (P.n > 0) HIP_TRY(hipMemcpyAsync(ws + P.off_w, w, sizeof(double) * 2 * (size_t)P.n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ws + P.off_leaf, P.desc_image.data(), P.desc_bytes, hipMemcpyHostToDevice, st));
+    wmc_status s = P.precision == WMC_FP64 ? run_slices<double>(P, ws, st, slice_begin, slice_end, per_slice)
+                                           : run_slices<float>(P, ws, st, slice_begin, slice_end, per_slice);
+    if (s != WMC_OK) return s;
+    wmc_acc h;
+    HIP_TRY(hipMemcpyAsync(&h, ws + P.off_acc, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h.s == 0.0 && h.c == 0.0) {
+        *out = make_value(0.0, 0);
+    } else {
+        *out = make_value(h.s + h.c, h.e);
+    }
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_contract(const wmc_plan_t *plan, const double *weights, void *workspace,
+                                   uint64_t workspace_bytes, void *stream, wmc_value *out) {
+    if (!plan) {
+        wmc_set_error("wmc_contract: NULL plan");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    return wmc_contract_slices(plan, weights, workspace, workspace_bytes, stream, 0,
+                               (int64_t)1 << plan->sliced.size(), out, nullptr);
+}
+
+// wmc_contract with per-launch timing: ms[k] (k < n_launches of
+// wmc_plan_launches) receives the summed duration of launch k over all
+// slices, measured with HIP events recorded on `stream` between launches.
+extern "C" wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double *weights, void *workspace,
+                                           uint64_t workspace_bytes, void *stream, float *ms, int64_t cap,
+                                           wmc_value *out) {
+    if (!plan || !out || !ms) {
+        wmc_set_error("wmc_contract_profile: NULL argument");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    const wmc_plan_t &P = *plan;
+    const int64_t n = (int64_t)P.launches.size() + 2;
+    if (cap < n - 1) {
+        wmc_set_error("wmc_contract_profile: need %lld slots", (long long)(n - 1));
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    if (P.root < 0 || !workspace || workspace_bytes < P.workspace_bytes)
+        return wmc_contract(plan, weights, workspace, workspace_bytes, stream, out);
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    LaunchTimer tm;
+    tm.ms = ms;
+    tm.cap = cap;
+    tm.st = st;
+    tm.ev.resize((size_t)n + 1);
+    for (auto &e : tm.ev) HIP_TRY(hipEventCreate(&e));
+    for (int64_t k = 0; k < cap; ++k) ms[k] = 0.f;
+    const double *w = weights ? weights : P.w.data();
+    wmc_status s = WMC_OK;
+    if (P.n > 0 && hipMemcpyAsync(ws + P.off_w, w, sizeof(double) * 2 * (size_t)P.n, hipMemcpyHostToDevice, st) != hipSuccess)
+        s = WMC_ERR_DEVICE;
+    if (s == WMC_OK && hipMemcpyAsync(ws + P.off_leaf, P.desc_image.data(), P.desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        s = WMC_ERR_DEVICE;
+    const long long ns = 1ll << P.sliced.size();
+    if (s == WMC_OK)
+        s = P.precision == WMC_FP64 ? run_slices<double>(P, ws, st, 0, ns, nullptr, &tm)
+                                    : run_slices<float>(P, ws, st, 0, ns, nullptr, &tm);
+    wmc_acc h;
+    if (s == WMC_OK && (hipMemcpyAsync(&h, ws + P.off_acc, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess))
+        s = WMC_ERR_DEVICE;
+    for (auto &e : tm.ev) (void)hipEventDestroy(e);
+    if (s != WMC_OK) {
+        if (s == WMC_ERR_DEVICE) wmc_set_error("wmc_contract_profile: HIP failure");
+        return s;
+    }
+    *out = (h.s == 0.0 && h.c == 0.0) ? make_value(0.0, 0) : make_value(h.s + h.c, h.e);
+    return WMC_OK;
+}

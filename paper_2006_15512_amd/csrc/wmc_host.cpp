@@ -1,0 +1,1032 @@
+// Host side of the weighted model counter: the reduction of Theorem 2, the
+// planning stage (contraction tree, index slicing of Algorithm 3, storage
+// layouts, launch schedule, static arena) and the inspection entry points.
+// Everything here is integer bookkeeping; all arithmetic on tensor entries
+// runs in the HIP kernels (wmc_device.hip).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "wmc_internal.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void wmc_set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+extern "C" const char *wmc_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *wmc_version(void) { return "wmc-mi355x 0.1 (gfx950)"; }
+
+#define WMC_FAIL(code, ...)              \
+    do {                                 \
+        wmc_set_error(__VA_ARGS__);      \
+        return code;                     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Reduction (Theorem 2).  B_C is stored as (variables, falsifying assignment,
+// tautology flag); A_x is symbolic: its degree and the two weights.
+// ---------------------------------------------------------------------------
+extern "C" wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
+                                        const int32_t *lits, const double *weights,
+                                        wmc_network **out) {
+    if (!out) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: out is NULL");
+    *out = nullptr;
+    if (n_vars < 0 || n_clauses < 0)
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: negative size");
+    if (n_clauses > 0 && !clause_ptr)
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: clause_ptr is NULL");
+    if (n_vars > 0 && !weights) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: weights is NULL");
+    if (n_clauses > 0) {
+        for (int64_t c = 0; c < n_clauses; ++c)
+            if (clause_ptr[c + 1] < clause_ptr[c] || clause_ptr[c] < 0)
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: clause_ptr not non-decreasing at %lld",
+                         (long long)c);
+        if (clause_ptr[n_clauses] > clause_ptr[0] && !lits)
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: lits is NULL");
+    }
+    for (int64_t i = 0; i < 2 * (int64_t)n_vars; ++i)
+        if (!std::isfinite(weights[i]))
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: weight %lld is not finite", (long long)i);
+    try {
+        wmc_network *net = new wmc_network();
+        net->n = n_vars;
+        net->w.assign(weights, weights + 2 * (size_t)n_vars);
+        net->degree.assign((size_t)n_vars, 0);
+        net->clauses.resize((size_t)n_clauses);
+        std::vector<int8_t> sign((size_t)n_vars + 1, 0);  // bit0: positive seen, bit1: negative seen
+        for (int64_t c = 0; c < n_clauses; ++c) {
+            WClause &cl = net->clauses[(size_t)c];
+            for (int64_t j = clause_ptr[c]; j < clause_ptr[c + 1]; ++j) {
+                int32_t l = lits[j];
+                if (l == 0 || l > n_vars || l < -n_vars) {
+                    delete net;
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: literal %d out of range in clause %lld",
+                             (int)l, (long long)c);
+                }
+                int32_t v = l > 0 ? l : -l;
+                if (!sign[v]) cl.vars.push_back(v);
+                sign[v] |= (l > 0) ? 1 : 2;
+            }
+            std::sort(cl.vars.begin(), cl.vars.end());
+            if (cl.vars.size() > WMC_MAX_CLAUSE) {
+                for (int32_t v : cl.vars) sign[v] = 0;
+                delete net;
+                WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_build_network: clause %lld has %zu distinct variables (max %d)",
+                         (long long)c, cl.vars.size(), WMC_MAX_CLAUSE);
+            }
+            for (size_t i = 0; i < cl.vars.size(); ++i) {
+                int32_t v = cl.vars[i];
+                if (sign[v] == 3) cl.taut = true;
+                // a positive literal is falsified by 0, a negative one by 1
+                if (sign[v] == 2) cl.falsify |= 1u << i;
+                sign[v] = 0;
+                net->degree[(size_t)v - 1]++;
+            }
+            net->n_indices += (int64_t)cl.vars.size();
+        }
+        *out = net;
+    } catch (std::bad_alloc &) {
+        WMC_FAIL(WMC_ERR_OUT_OF_MEMORY, "wmc_build_network: host allocation failed");
+    }
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_network_info(const wmc_network *net, int64_t *n_tensors, int64_t *n_indices) {
+    if (!net) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_network_info: net is NULL");
+    if (n_tensors) *n_tensors = (int64_t)net->n + (int64_t)net->clauses.size();
+    if (n_indices) *n_indices = net->n_indices;
+    return WMC_OK;
+}
+
+extern "C" void wmc_network_destroy(wmc_network *net) { delete net; }
+
+// ---------------------------------------------------------------------------
+// Seeded min-fill elimination order on the primal graph (variables adjacent
+// when they share a clause).  Key: (fill-in edges, degree, seeded priority).
+// ---------------------------------------------------------------------------
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+static std::vector<int32_t> minfill_order(const wmc_network &net, uint64_t seed) {
+    const int32_t n = net.n;
+    const size_t W = ((size_t)n + 63) / 64;
+    std::vector<uint64_t> adj((size_t)n * W, 0);
+    auto row = [&](int32_t v) { return &adj[(size_t)v * W]; };
+    for (const WClause &c : net.clauses)
+        for (int32_t a : c.vars)
+            for (int32_t b : c.vars)
+                if (a != b) row(a - 1)[(size_t)(b - 1) / 64] |= 1ull << ((b - 1) % 64);
+    std::vector<uint8_t> done((size_t)n, 0);
+    std::vector<int64_t> fill((size_t)n, 0), deg((size_t)n, 0);
+    std::vector<uint64_t> prio((size_t)n);
+    for (int32_t v = 0; v < n; ++v) prio[(size_t)v] = splitmix64(seed * 0x100000001B3ull + (uint64_t)v);
+    std::vector<int32_t> nb;
+    auto neighbours = [&](int32_t v) {
+        nb.clear();
+        const uint64_t *r = row(v);
+        for (size_t w = 0; w < W; ++w) {
+            uint64_t bits = r[w];
+            while (bits) {
+                int t = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                nb.push_back((int32_t)(w * 64 + t));
+            }
+        }
+    };
+    auto compute = [&](int32_t v) {
+        neighbours(v);
+        const uint64_t *rv = row(v);
+        int64_t f = 0;
+        for (int32_t u : nb) {
+            const uint64_t *ru = row(u);
+            int64_t c = 0;
+            for (size_t w = 0; w < W; ++w) c += __builtin_popcountll(rv[w] & ~ru[w]);
+            f += c - 1;  // u itself is in N(v) but not in N(u)
+        }
+        fill[(size_t)v] = f / 2;
+        deg[(size_t)v] = (int64_t)nb.size();
+    };
+    for (int32_t v = 0; v < n; ++v) compute(v);
+    std::vector<int32_t> order;
+    order.reserve((size_t)n);
+    std::vector<uint8_t> dirty((size_t)n, 0);
+    std::vector<int32_t> nv;
+    for (int32_t step = 0; step < n; ++step) {
+        int32_t best = -1;
+        for (int32_t v = 0; v < n; ++v) {
+            if (done[(size_t)v]) continue;
+            if (best < 0 || fill[(size_t)v] < fill[(size_t)best] ||
+                (fill[(size_t)v] == fill[(size_t)best] &&
+                 (deg[(size_t)v] < deg[(size_t)best] ||
+                  (deg[(size_t)v] == deg[(size_t)best] && prio[(size_t)v] < prio[(size_t)best]))))
+                best = v;
+        }
+        neighbours(best);
+        nv = nb;
+        // connect the neighbourhood, drop best from the graph
+        uint64_t *rb = row(best);
+        for (int32_t u : nv) {
+            uint64_t *ru = row(u);
+            for (size_t w = 0; w < W; ++w) ru[w] |= rb[w];
+            ru[(size_t)u / 64] &= ~(1ull << (u % 64));
+            ru[(size_t)best / 64] &= ~(1ull << (best % 64));
+        }
+        std::fill(rb, rb + W, 0);
+        done[(size_t)best] = 1;
+        order.push_back(best + 1);
+        for (int32_t u : nv) {
+            dirty[(size_t)u] = 1;
+            neighbours(u);
+            for (int32_t z : nb) dirty[(size_t)z] = 1;
+        }
+        for (int32_t u = 0; u < n; ++u)
+            if (dirty[(size_t)u]) {
+                dirty[(size_t)u] = 0;
+                if (!done[(size_t)u]) compute(u);
+            }
+    }
+    return order;
+}
+
+// ---------------------------------------------------------------------------
+// Contraction-tree construction.  A tensor's open variables are those with
+// some but not all of their occurrences (the clause leaves containing x and
+// A_x) inside its subtree; a variable is summed out at the node whose subtree
+// first holds all of them.  Keeping one storage mode per open variable is the
+// tensor obtained by contracting A_x's COPY factors early, which partial
+// contraction and tree-factorability (Definition 4) allow.
+// ---------------------------------------------------------------------------
+struct TreeBuilder {
+    const wmc_network &net;
+    std::vector<TNode> &T;
+    std::vector<int32_t> total;  // occurrences: degree + 1 (A_x)
+
+    TreeBuilder(const wmc_network &nt, std::vector<TNode> &t) : net(nt), T(t) {
+        total.assign((size_t)net.n + 1, 0);
+        for (int32_t x = 1; x <= net.n; ++x) total[(size_t)x] = net.degree[(size_t)x - 1] + 1;
+    }
+
+    int32_t leaf_clause(int32_t c) {
+        TNode t;
+        t.kind = 0;
+        t.src = c;
+        t.vars = net.clauses[(size_t)c].vars;
+        t.cnt.assign(t.vars.size(), 1);
+        t.has_w.assign(t.vars.size(), 0);
+        t.index_rank = (int32_t)t.vars.size();
+        T.push_back(std::move(t));
+        return (int32_t)T.size() - 1;
+    }
+
+    int32_t leaf_weight(int32_t x) {
+        TNode t;
+        t.kind = 1;
+        t.src = x;
+        if (total[(size_t)x] > 1) {
+            t.vars = {x};
+            t.cnt = {1};
+            t.has_w = {1};
+        }
+        t.index_rank = net.degree[(size_t)x - 1];
+        T.push_back(std::move(t));
+        return (int32_t)T.size() - 1;
+    }
+
+    // storage rank of the merge of a and b (ignoring slicing)
+    int32_t merged_rank(int32_t a, int32_t b) const {
+        const TNode &A = T[(size_t)a], &B = T[(size_t)b];
+        size_t i = 0, j = 0;
+        int32_t r = 0;
+        while (i < A.vars.size() || j < B.vars.size()) {
+            if (j == B.vars.size() || (i < A.vars.size() && A.vars[i] < B.vars[j])) {
+                ++r;
+                ++i;
+            } else if (i == A.vars.size() || B.vars[j] < A.vars[i]) {
+                ++r;
+                ++j;
+            } else {
+                if (A.cnt[i] + B.cnt[j] < total[(size_t)A.vars[i]]) ++r;
+                ++i;
+                ++j;
+            }
+        }
+        return r;
+    }
+
+    int32_t merge(int32_t a, int32_t b) {
+        TNode t;
+        t.kind = 2;
+        t.a = a;
+        t.b = b;
+        const TNode &A = T[(size_t)a], &B = T[(size_t)b];
+        size_t i = 0, j = 0;
+        auto push = [&](int32_t v, int32_t c, uint8_t h) {
+            if (c < total[(size_t)v]) {
+                t.vars.push_back(v);
+                t.cnt.push_back(c);
+                t.has_w.push_back(h);
+            } else {
+                t.kappa.push_back(v);
+            }
+        };
+        while (i < A.vars.size() || j < B.vars.size()) {
+            if (j == B.vars.size() || (i < A.vars.size() && A.vars[i] < B.vars[j])) {
+                push(A.vars[i], A.cnt[i], A.has_w[i]);
+                ++i;
+            } else if (i == A.vars.size() || B.vars[j] < A.vars[i]) {
+                push(B.vars[j], B.cnt[j], B.has_w[j]);
+                ++j;
+            } else {
+                push(A.vars[i], A.cnt[i] + B.cnt[j], (uint8_t)(A.has_w[i] | B.has_w[j]));
+                ++i;
+                ++j;
+            }
+        }
+        int32_t ir = 0;
+        for (size_t q = 0; q < t.vars.size(); ++q)
+            ir += t.has_w[q] ? total[(size_t)t.vars[q]] - t.cnt[q] : t.cnt[q];
+        t.index_rank = ir;
+        T.push_back(std::move(t));
+        int32_t id = (int32_t)T.size() - 1;
+        T[(size_t)a].parent = id;
+        T[(size_t)b].parent = id;
+        return id;
+    }
+
+    // Merge a set of tensors pairwise, each step taking the pair whose result
+    // has the smallest rank (ties: smaller operands, then creation order).
+    int32_t merge_all(std::vector<int32_t> bucket) {
+        while (bucket.size() > 1) {
+            size_t bi = 0, bj = 1;
+            int64_t best_key[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+            for (size_t i = 0; i < bucket.size(); ++i)
+                for (size_t j = i + 1; j < bucket.size(); ++j) {
+                    int64_t k0 = merged_rank(bucket[i], bucket[j]);
+                    int64_t k1 = (int64_t)T[(size_t)bucket[i]].vars.size() + (int64_t)T[(size_t)bucket[j]].vars.size();
+                    int64_t k2 = (int64_t)std::min(bucket[i], bucket[j]) * 1000003 + std::max(bucket[i], bucket[j]);
+                    if (k0 < best_key[0] || (k0 == best_key[0] && (k1 < best_key[1] || (k1 == best_key[1] && k2 < best_key[2])))) {
+                        best_key[0] = k0;
+                        best_key[1] = k1;
+                        best_key[2] = k2;
+                        bi = i;
+                        bj = j;
+                    }
+                }
+            int32_t m = merge(bucket[bi], bucket[bj]);
+            bucket.erase(bucket.begin() + (std::ptrdiff_t)bj);
+            bucket[bi] = m;
+        }
+        return bucket.empty() ? -1 : bucket[0];
+    }
+};
+
+// Bucket tree from an elimination order: for each block of `block`
+// consecutive variables, gather every live tensor that holds one of them
+// plus their weight leaves A_x, and merge the bucket pairwise.
+static int32_t bucket_tree(const wmc_network &net, const std::vector<int32_t> &order, int32_t block,
+                           std::vector<TNode> &T) {
+    TreeBuilder tb(net, T);
+    const int32_t n = net.n;
+    std::vector<uint8_t> alive;
+    std::vector<std::vector<int32_t>> holders((size_t)n + 1);
+    std::vector<int32_t> scalars;
+    auto add_alive = [&](int32_t id) {
+        if ((size_t)id >= alive.size()) alive.resize((size_t)id + 1, 0);
+        alive[(size_t)id] = 1;
+        if (T[(size_t)id].vars.empty()) scalars.push_back(id);
+        for (int32_t v : T[(size_t)id].vars) holders[(size_t)v].push_back(id);
+    };
+    for (int32_t c = 0; c < (int32_t)net.clauses.size(); ++c) add_alive(tb.leaf_clause(c));
+    std::vector<int32_t> wleaf((size_t)n + 1, -1);
+    for (int32_t x = 1; x <= n; ++x)
+        if (net.degree[(size_t)x - 1] == 0) add_alive(tb.leaf_weight(x));
+    if (block < 1) block = 1;
+    std::vector<uint8_t> in_bucket;
+    for (size_t s = 0; s < order.size(); s += (size_t)block) {
+        std::vector<int32_t> bucket;
+        for (size_t q = s; q < std::min(order.size(), s + (size_t)block); ++q) {
+            int32_t x = order[q];
+            if (net.degree[(size_t)x - 1] == 0) continue;
+            for (int32_t id : holders[(size_t)x]) {
+                if (!alive[(size_t)id]) continue;
+                const std::vector<int32_t> &vs = T[(size_t)id].vars;
+                if (!std::binary_search(vs.begin(), vs.end(), x)) continue;
+                alive[(size_t)id] = 0;
+                bucket.push_back(id);
+            }
+            holders[(size_t)x].clear();
+            int32_t wl = tb.leaf_weight(x);
+            if ((size_t)wl >= alive.size()) alive.resize((size_t)wl + 1, 0);
+            bucket.push_back(wl);
+        }
+        if (bucket.empty()) continue;
+        std::sort(bucket.begin(), bucket.end());
+        int32_t r = tb.merge_all(bucket);
+        add_alive(r);
+    }
+    std::vector<int32_t> rest;
+    for (size_t id = 0; id < alive.size(); ++id)
+        if (alive[id]) rest.push_back((int32_t)id);
+    for (int32_t id : rest)
+        if (!T[(size_t)id].vars.empty()) return -2;  // order did not cover every variable
+    if (rest.empty()) return -1;
+    int32_t root = rest[0];
+    for (size_t i = 1; i < rest.size(); ++i) root = tb.merge(root, rest[i]);
+    return root;
+}
+
+// Explicit tree: vertices 0..n-1 = A_x, n..n+m-1 = B_C, then internal vertices.
+static wmc_status explicit_tree(const wmc_network &net, const int64_t *parent, int64_t n_nodes,
+                                std::vector<TNode> &T, int32_t *root_out) {
+    const int64_t L = (int64_t)net.n + (int64_t)net.clauses.size();
+    if (L == 0) {
+        if (n_nodes != 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: expected 0 vertices");
+        *root_out = -1;
+        return WMC_OK;
+    }
+    if (!parent || n_nodes != 2 * L - 1)
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: expected %lld vertices, got %lld",
+                 (long long)(2 * L - 1), (long long)n_nodes);
+    std::vector<std::vector<int64_t>> kids((size_t)n_nodes);
+    int64_t root = -1;
+    for (int64_t v = 0; v < n_nodes; ++v) {
+        int64_t p = parent[v];
+        if (p == -1) {
+            if (root >= 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: two roots (%lld, %lld)",
+                                    (long long)root, (long long)v);
+            root = v;
+            continue;
+        }
+        if (p < L || p >= n_nodes || p == v)
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: vertex %lld has invalid parent %lld",
+                     (long long)v, (long long)p);
+        kids[(size_t)p].push_back(v);
+    }
+    if (root < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: no root");
+    if (L == 1) {
+        if (root != 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: single leaf must be the root");
+    } else if (root < L) {
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: root is a leaf");
+    }
+    for (int64_t v = L; v < n_nodes; ++v)
+        if (kids[(size_t)v].size() != 2)
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: internal vertex %lld has %zu children",
+                     (long long)v, kids[(size_t)v].size());
+    TreeBuilder tb(net, T);
+    std::vector<int32_t> tid((size_t)n_nodes, -1);
+    for (int32_t x = 1; x <= net.n; ++x) tid[(size_t)x - 1] = tb.leaf_weight(x);
+    for (int64_t c = 0; c < (int64_t)net.clauses.size(); ++c) tid[(size_t)(net.n + c)] = tb.leaf_clause((int32_t)c);
+    // post-order from the root (iterative), which also rejects cycles
+    std::vector<std::pair<int64_t, int>> stack;
+    stack.push_back({root, 0});
+    int64_t visited = 0;
+    std::vector<uint8_t> seen((size_t)n_nodes, 0);
+    while (!stack.empty()) {
+        auto &top = stack.back();
+        int64_t v = top.first;
+        if (v < L) {
+            if (seen[(size_t)v]++) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: vertex reached twice");
+            ++visited;
+            stack.pop_back();
+            continue;
+        }
+        if (top.second < 2) {
+            int64_t c = kids[(size_t)v][(size_t)top.second++];
+            if (seen[(size_t)c]) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: cycle");
+            stack.push_back({c, 0});
+            continue;
+        }
+        seen[(size_t)v] = 1;
+        ++visited;
+        tid[(size_t)v] = tb.merge(tid[(size_t)kids[(size_t)v][0]], tid[(size_t)kids[(size_t)v][1]]);
+        stack.pop_back();
+    }
+    if (visited != n_nodes) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "explicit tree: not connected");
+    *root_out = tid[(size_t)root];
+    return WMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lowered sizes under a slice set I
+// ---------------------------------------------------------------------------
+static inline bool is_sliced(const std::vector<uint8_t> &sl, int32_t v) { return sl[(size_t)v] != 0; }
+
+static int32_t srank(const TNode &t, const std::vector<uint8_t> &sl) {
+    int32_t r = 0;
+    for (int32_t v : t.vars) r += !is_sliced(sl, v);
+    return r;
+}
+
+static int32_t skappa(const TNode &t, const std::vector<uint8_t> &sl) {
+    int32_t r = 0;
+    for (int32_t v : t.kappa) r += !is_sliced(sl, v);
+    return r;
+}
+
+// Node class from storage ranks: tiny nodes are batched many per launch.
+static int32_t node_class(int32_t ra, int32_t rb, int32_t rc, int32_t nk) {
+    int32_t mx = std::max(ra, std::max(rb, rc));
+    if (mx <= 14 && rc + nk <= 18) return WMC_CLASS_SMALL;
+    return WMC_CLASS_STREAM;
+}
+
+// Post-order-compatible launch schedule: all ready small nodes go in one
+// batched launch, big nodes one per launch.  Returns internal tensors in
+// launch order and fills launch index per tensor (birth).
+struct Schedule {
+    std::vector<int32_t> order;            // internal tensors in launch order
+    std::vector<std::pair<int32_t, int32_t>> launches;  // [first, count) into order
+};
+
+static Schedule make_schedule(const std::vector<TNode> &T, const std::vector<int32_t> &cls) {
+    Schedule S;
+    const size_t NT = T.size();
+    std::vector<int32_t> pending(NT, 0);
+    std::vector<int32_t> ready_small, ready_big;
+    size_t n_internal = 0;
+    for (size_t i = 0; i < NT; ++i)
+        if (T[i].kind == 2) {
+            ++n_internal;
+            pending[i] = (T[(size_t)T[i].a].kind == 2) + (T[(size_t)T[i].b].kind == 2);
+            if (pending[i] == 0) (cls[i] == WMC_CLASS_SMALL ? ready_small : ready_big).push_back((int32_t)i);
+        }
+    auto finish = [&](int32_t id) {
+        int32_t p = T[(size_t)id].parent;
+        if (p >= 0 && --pending[(size_t)p] == 0)
+            (cls[(size_t)p] == WMC_CLASS_SMALL ? ready_small : ready_big).push_back(p);
+    };
+    while (S.order.size() < n_internal) {
+        if (!ready_small.empty()) {
+            std::vector<int32_t> batch;
+            batch.swap(ready_small);
+            std::sort(batch.begin(), batch.end());
+            S.launches.push_back({(int32_t)S.order.size(), (int32_t)batch.size()});
+            for (int32_t id : batch) S.order.push_back(id);
+            for (int32_t id : batch) finish(id);
+        } else {
+            auto it = std::min_element(ready_big.begin(), ready_big.end());
+            int32_t id = *it;
+            ready_big.erase(it);
+            S.launches.push_back({(int32_t)S.order.size(), 1});
+            S.order.push_back(id);
+            finish(id);
+        }
+    }
+    return S;
+}
+
+// Peak of live tensor bytes over a schedule (MemCost of Algorithm 3).
+static double peak_live(const std::vector<TNode> &T, const Schedule &S, const std::vector<uint8_t> &sl,
+                        int32_t elem, int32_t root) {
+    const size_t NL = S.launches.size();
+    // launch 0 is the leaf fill; node launch k is index k+1
+    std::vector<double> delta(NL + 3, 0.0);
+    std::vector<int32_t> birth(T.size(), 0);
+    for (size_t k = 0; k < NL; ++k)
+        for (int32_t q = 0; q < S.launches[k].second; ++q)
+            birth[(size_t)S.order[(size_t)(S.launches[k].first + q)]] = (int32_t)k + 1;
+    for (size_t i = 0; i < T.size(); ++i) {
+        double b = (double)elem * std::ldexp(1.0, srank(T[i], sl));
+        int32_t death = ((int32_t)i == root || T[i].parent < 0) ? (int32_t)NL + 1 : birth[(size_t)T[i].parent];
+        delta[(size_t)birth[i]] += b;
+        delta[(size_t)death + 1] -= b;
+    }
+    double cur = 0.0, peak = 0.0;
+    for (size_t k = 0; k < delta.size(); ++k) {
+        cur += delta[k];
+        peak = std::max(peak, cur);
+    }
+    return peak;
+}
+
+static double flops_of(const std::vector<TNode> &T, const std::vector<uint8_t> &sl) {
+    double f = 0.0;
+    for (const TNode &t : T)
+        if (t.kind == 2) f += 2.0 * std::ldexp(1.0, srank(t, sl) + skappa(t, sl));
+    return f;
+}
+
+static int32_t max_rank_of(const std::vector<TNode> &T, const std::vector<uint8_t> &sl) {
+    int32_t r = 0;
+    for (const TNode &t : T) r = std::max(r, srank(t, sl));
+    return r;
+}
+
+static std::vector<int32_t> classes_of(const std::vector<TNode> &T, const std::vector<uint8_t> &sl) {
+    std::vector<int32_t> cls(T.size(), -1);
+    for (size_t i = 0; i < T.size(); ++i)
+        if (T[i].kind == 2)
+            cls[i] = node_class(srank(T[(size_t)T[i].a], sl), srank(T[(size_t)T[i].b], sl), srank(T[i], sl),
+                                skappa(T[i], sl));
+    return cls;
+}
+
+// ---------------------------------------------------------------------------
+// wmc_plan
+// ---------------------------------------------------------------------------
+static uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &o, wmc_plan_t &P) {
+    std::vector<TNode> &T = P.T;
+    const size_t NT = T.size();
+    const int32_t n = net.n;
+    std::vector<uint8_t> sl((size_t)n + 1, 0);
+
+    // ---- slicing (Algorithm 3): grow I greedily while MemCost exceeds the bound
+    const int32_t rank0 = max_rank_of(T, sl);
+    int32_t idx_rank = 0;
+    for (const TNode &t : T) idx_rank = std::max(idx_rank, t.index_rank);
+    auto over = [&](const Schedule &S, const std::vector<uint8_t> &s) {
+        if (o.rank_cap > 0 && max_rank_of(T, s) > o.rank_cap) return true;
+        if (o.mem_cap_bytes > 0 && peak_live(T, S, s, P.elem, P.root) > (double)o.mem_cap_bytes) return true;
+        return false;
+    };
+    Schedule S0 = make_schedule(T, classes_of(T, sl));
+    while (over(S0, sl)) {
+        if ((int32_t)P.sliced.size() >= WMC_MAX_SLICED)
+            WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: cap not met after slicing %d variables", WMC_MAX_SLICED);
+        // candidates: variables of the tensors at the current maximum rank,
+        // and of the tensors live at the peak
+        int32_t mr = max_rank_of(T, sl);
+        std::vector<uint8_t> cand((size_t)n + 1, 0);
+        for (const TNode &t : T)
+            if (srank(t, sl) >= mr - 1)
+                for (int32_t v : t.vars)
+                    if (!sl[(size_t)v]) cand[(size_t)v] = 1;
+        int32_t best = -1;
+        double best_mem = 0, best_fl = 0;
+        for (int32_t v = 1; v <= n; ++v) {
+            if (!cand[(size_t)v]) continue;
+            sl[(size_t)v] = 1;
+            double mem = peak_live(T, S0, sl, P.elem, P.root);
+            double fl = flops_of(T, sl);
+            if (o.rank_cap > 0) mem += 1e30 * (double)std::max(0, max_rank_of(T, sl) - o.rank_cap);
+            sl[(size_t)v] = 0;
+            if (best < 0 || mem < best_mem || (mem == best_mem && fl < best_fl)) {
+                best = v;
+                best_mem = mem;
+                best_fl = fl;
+            }
+        }
+        if (best < 0) WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: no variable left to slice");
+        sl[(size_t)best] = 1;
+        P.sliced.push_back(best);
+    }
+    const int32_t rankS = max_rank_of(T, sl);
+    if (rankS > WMC_MAX_RANK)
+        WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_plan: storage rank %d exceeds %d (set rank_cap or mem_cap)", rankS,
+                 WMC_MAX_RANK);
+    std::vector<int32_t> sbit((size_t)n + 1, -1);
+    for (size_t i = 0; i < P.sliced.size(); ++i) sbit[(size_t)P.sliced[i]] = (int32_t)i;
+
+    // ---- layouts, top-down: an operand stores [kappa | its variables in the
+    // order of the node's output]; the root is a scalar
+    if (P.root >= 0) {
+        T[(size_t)P.root].layout.clear();
+        for (int32_t v : T[(size_t)P.root].vars)
+            if (!sl[(size_t)v]) T[(size_t)P.root].layout.push_back(v);
+        std::vector<int32_t> stack = {P.root};
+        std::vector<int32_t> mark((size_t)n + 1, 0);
+        int32_t stamp = 0;
+        while (!stack.empty()) {
+            int32_t q = stack.back();
+            stack.pop_back();
+            TNode &C = T[(size_t)q];
+            if (C.kind != 2) continue;
+            std::vector<int32_t> kap;
+            for (int32_t v : C.kappa)
+                if (!sl[(size_t)v]) kap.push_back(v);
+            for (int32_t child : {C.a, C.b}) {
+                TNode &X = T[(size_t)child];
+                ++stamp;
+                for (int32_t v : X.vars) mark[(size_t)v] = stamp;
+                X.layout = kap;
+                for (int32_t v : C.layout)
+                    if (mark[(size_t)v] == stamp) X.layout.push_back(v);
+                if ((int32_t)X.layout.size() != srank(X, sl)) {
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: internal layout mismatch at tensor %d", child);
+                }
+                stack.push_back(child);
+            }
+        }
+    }
+
+    // ---- classes and schedule
+    std::vector<int32_t> cls = classes_of(T, sl);
+    Schedule S = make_schedule(T, cls);
+    P.node_order = S.order;
+    P.launches.clear();
+    P.launches.push_back({LAUNCH_LEAF, 0, 0, 0, 0});
+    for (size_t k = 0; k < S.launches.size(); ++k)
+        P.launches.push_back({LAUNCH_NODES, S.launches[k].first, S.launches[k].second, 0, 0});
+    for (size_t i = 0; i < NT; ++i) T[i].birth = 0;
+    for (size_t k = 0; k < S.launches.size(); ++k)
+        for (int32_t q = 0; q < S.launches[k].second; ++q)
+            T[(size_t)S.order[(size_t)(S.launches[k].first + q)]].birth = (int32_t)k + 1;
+    const int32_t NL = (int32_t)P.launches.size();
+    for (size_t i = 0; i < NT; ++i) {
+        T[i].death = (T[i].parent < 0) ? NL : T[(size_t)T[i].parent].birth;
+        if (T[i].kind == 2) T[i].cls = cls[i];
+    }
+
+    // ---- static arena: greedy placement by size over lifetime intervals
+    const uint64_t align_elems = 256 / (uint64_t)P.elem;
+    std::vector<int32_t> by_size(NT);
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::vector<uint64_t> elems(NT);
+    for (size_t i = 0; i < NT; ++i) elems[i] = align_up((uint64_t)1 << srank(T[i], sl), align_elems);
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int32_t a, int32_t b) {
+        if (elems[(size_t)a] != elems[(size_t)b]) return elems[(size_t)a] > elems[(size_t)b];
+        return T[(size_t)a].birth < T[(size_t)b].birth;
+    });
+    std::vector<int32_t> placed;
+    uint64_t arena_elems = 0;
+    std::vector<std::pair<uint64_t, uint64_t>> busy;
+    for (int32_t t : by_size) {
+        busy.clear();
+        const TNode &X = T[(size_t)t];
+        for (int32_t p : placed) {
+            const TNode &Y = T[(size_t)p];
+            if (Y.death < X.birth || X.death < Y.birth) continue;
+            busy.push_back({(uint64_t)Y.off, (uint64_t)Y.off + elems[(size_t)p]});
+        }
+        std::sort(busy.begin(), busy.end());
+        uint64_t off = 0;
+        for (auto &iv : busy) {
+            if (iv.first >= off + elems[(size_t)t]) break;
+            off = std::max(off, iv.second);
+        }
+        T[(size_t)t].off = (int64_t)off;
+        arena_elems = std::max(arena_elems, off + elems[(size_t)t]);
+        placed.push_back(t);
+    }
+    P.arena_bytes = arena_elems * (uint64_t)P.elem;
+
+    // ---- descriptors
+    P.leaves.clear();
+    P.nodes.clear();
+    int64_t lw = 0;
+    for (size_t i = 0; i < NT; ++i) {
+        const TNode &X = T[i];
+        if (X.kind == 2) continue;
+        LeafDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.out = X.off;
+        d.work_begin = lw;
+        d.tensor = (int32_t)i;
+        d.rank = (int32_t)X.layout.size();
+        for (int q = 0; q < WMC_LEAF_VARS; ++q) d.pos[q] = 0;
+        auto pos_of = [&](int32_t v) -> int16_t {
+            if (sl[(size_t)v]) return (int16_t)(-(1 + sbit[(size_t)v]));
+            for (size_t q = 0; q < X.layout.size(); ++q)
+                if (X.layout[q] == v) return (int16_t)q;
+            return (int16_t)-1000;
+        };
+        if (X.kind == 0) {
+            const WClause &c = net.clauses[(size_t)X.src];
+            d.kind = WMC_LEAF_CLAUSE;
+            d.k = (int32_t)c.vars.size();
+            d.falsify = c.falsify;
+            d.taut = c.taut ? 1 : 0;
+            for (size_t q = 0; q < c.vars.size(); ++q) d.pos[q] = pos_of(c.vars[q]);
+        } else {
+            d.var = X.src - 1;
+            if (X.vars.empty()) {
+                d.kind = WMC_LEAF_WEIGHT_CLOSED;
+            } else {
+                d.kind = WMC_LEAF_WEIGHT;
+                d.k = 1;
+                d.pos[0] = pos_of(X.src);
+            }
+        }
+        lw += (int64_t)align_up((uint64_t)1 << d.rank, WMC_WAVE);
+        P.leaves.push_back(d);
+    }
+    P.leaf_work = lw;
+    P.launches[0].work = lw;
+    std::vector<int32_t> mark((size_t)n + 1, 0);
+    int32_t stamp = 0;
+    for (size_t k = 1; k < P.launches.size(); ++k) {
+        Launch &L = P.launches[k];
+        int64_t work = 0;
+        for (int32_t q = 0; q < L.count; ++q) {
+            int32_t id = P.node_order[(size_t)(L.first + q)];
+            const TNode &C = T[(size_t)id];
+            NodeDesc d;
+            std::memset(&d, 0, sizeof d);
+            d.a = T[(size_t)C.a].off;
+            d.b = T[(size_t)C.b].off;
+            d.c = C.off;
+            d.ta = C.a;
+            d.tb = C.b;
+            d.tc = id;
+            d.rc = (int32_t)C.layout.size();
+            d.nk = skappa(C, sl);
+            d.cls = C.cls;
+            d.work_begin = work;
+            for (int which = 0; which < 2; ++which) {
+                const TNode &X = T[(size_t)(which ? C.b : C.a)];
+                ++stamp;
+                for (int32_t v : X.vars) mark[(size_t)v] = stamp;
+                unsigned char(*runs)[3] = which ? d.rb : d.ra;
+                int nr = 0, dst = 0;
+                for (int j = 0; j < d.rc;) {
+                    if (mark[(size_t)C.layout[(size_t)j]] != stamp) {
+                        ++j;
+                        continue;
+                    }
+                    int s0 = j;
+                    while (j < d.rc && mark[(size_t)C.layout[(size_t)j]] == stamp) ++j;
+                    if (nr >= WMC_MAX_RUNS)
+                        WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_plan: node %d needs more than %d runs", id, WMC_MAX_RUNS);
+                    runs[nr][0] = (unsigned char)s0;
+                    runs[nr][1] = (unsigned char)(j - s0);
+                    runs[nr][2] = (unsigned char)dst;
+                    dst += j - s0;
+                    ++nr;
+                }
+                if (which) d.nrb = nr; else d.nra = nr;
+                if (dst + d.nk != (int32_t)X.layout.size())
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: internal run mismatch at node %d", id);
+            }
+            work += (int64_t)align_up((uint64_t)1 << d.rc, WMC_WAVE);
+            P.nodes.push_back(d);
+        }
+        L.work = work;
+    }
+
+    // ---- workspace layout
+    uint64_t off = 0;
+    P.off_acc = off;
+    off += align_up(sizeof(wmc_acc), 256);
+    P.off_w = off;
+    off += align_up(sizeof(double) * 2 * (uint64_t)std::max(n, 1), 256);
+    P.off_meta = off;
+    off += align_up(sizeof(wmc_meta) * (uint64_t)std::max<size_t>(NT, 1), 256);
+    P.off_leaf = off;
+    off += align_up(sizeof(LeafDesc) * (uint64_t)std::max<size_t>(P.leaves.size(), 1), 256);
+    P.off_node = off;
+    off += align_up(sizeof(NodeDesc) * (uint64_t)std::max<size_t>(P.nodes.size(), 1), 256);
+    P.off_arena = off;
+    P.desc_bytes = P.off_arena - P.off_leaf;
+    P.desc_image.assign(P.desc_bytes, 0);
+    if (!P.leaves.empty()) std::memcpy(P.desc_image.data(), P.leaves.data(), sizeof(LeafDesc) * P.leaves.size());
+    if (!P.nodes.empty())
+        std::memcpy(P.desc_image.data() + (P.off_node - P.off_leaf), P.nodes.data(), sizeof(NodeDesc) * P.nodes.size());
+    P.workspace_bytes = P.off_arena + align_up(P.arena_bytes, 256);
+
+    // ---- statistics
+    wmc_plan_info &I = P.info;
+    std::memset(&I, 0, sizeof I);
+    I.n_vars = n;
+    I.precision = P.precision;
+    I.n_clauses = (int64_t)net.clauses.size();
+    I.n_tensors = (int64_t)NT;
+    I.n_nodes = (int64_t)P.nodes.size();
+    I.max_rank = rankS;
+    I.max_rank_unsliced = rank0;
+    I.max_index_rank = idx_rank;
+    I.n_sliced = (int32_t)P.sliced.size();
+    I.n_slices = (int64_t)1 << P.sliced.size();
+    for (size_t i = 0; i < P.sliced.size(); ++i) I.sliced_vars[i] = P.sliced[i];
+    double fl = 0, by = 0, mx = 0;
+    for (const NodeDesc &d : P.nodes) {
+        double c = std::ldexp(1.0, d.rc);
+        double a = std::ldexp(1.0, srank(T[(size_t)d.ta], sl));
+        double b = std::ldexp(1.0, srank(T[(size_t)d.tb], sl));
+        fl += 2.0 * c * std::ldexp(1.0, d.nk);
+        double nb = (double)P.elem * (a + b + c);
+        by += nb;
+        mx = std::max(mx, nb);
+        I.class_hist[d.cls]++;
+    }
+    I.flops_per_slice = fl;
+    I.bytes_per_slice = by;
+    I.max_node_bytes = mx;
+    I.peak_live_bytes = peak_live(T, S, sl, P.elem, P.root);
+    I.arena_bytes = P.arena_bytes;
+    I.workspace_bytes = P.workspace_bytes;
+    I.n_launches = (int64_t)P.launches.size() + 2;  // + begin and finish kernels
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *opts, wmc_plan_t **out) {
+    if (!out) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: out is NULL");
+    *out = nullptr;
+    if (!net || !opts) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: NULL argument");
+    if (opts->precision != WMC_FP64 && opts->precision != WMC_FP32_SCALED)
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: unknown precision %d", opts->precision);
+    if (opts->rank_cap < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: negative rank_cap");
+    try {
+        wmc_plan_t *P = new wmc_plan_t();
+        P->n = net->n;
+        P->m = (int64_t)net->clauses.size();
+        P->precision = opts->precision;
+        P->elem = opts->precision == WMC_FP64 ? 8 : 4;
+        P->w = net->w;
+        wmc_status st = WMC_OK;
+        if (opts->kind == WMC_TREE_EXPLICIT) {
+            st = explicit_tree(*net, opts->parent, opts->n_tree_nodes, P->T, &P->root);
+        } else if (opts->kind == WMC_TREE_ORDER || opts->kind == WMC_TREE_MINFILL) {
+            std::vector<int32_t> order;
+            if (opts->kind == WMC_TREE_ORDER) {
+                if (!opts->order || opts->order_len != net->n) {
+                    delete P;
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: order must list all %d variables", net->n);
+                }
+                std::vector<uint8_t> seen((size_t)net->n + 1, 0);
+                for (int32_t i = 0; i < net->n; ++i) {
+                    int32_t v = opts->order[i];
+                    if (v < 1 || v > net->n || seen[(size_t)v]) {
+                        delete P;
+                        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: order is not a permutation (entry %d = %d)", i, v);
+                    }
+                    seen[(size_t)v] = 1;
+                }
+                order.assign(opts->order, opts->order + net->n);
+            } else {
+                order = minfill_order(*net, opts->seed);
+            }
+            P->root = bucket_tree(*net, order, opts->block, P->T);
+            if (P->root == -2) st = WMC_ERR_INVALID_ARGUMENT;
+        } else {
+            delete P;
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: unknown tree kind %d", opts->kind);
+        }
+        if (st == WMC_OK) st = finalize_plan(*net, *opts, *P);
+        if (st != WMC_OK) {
+            delete P;
+            return st;
+        }
+        *out = P;
+    } catch (std::bad_alloc &) {
+        WMC_FAIL(WMC_ERR_OUT_OF_MEMORY, "wmc_plan: host allocation failed");
+    }
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_plan_stats(const wmc_plan_t *plan, wmc_plan_info *out) {
+    if (!plan || !out) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_stats: NULL argument");
+    *out = plan->info;
+    return WMC_OK;
+}
+
+extern "C" void wmc_plan_destroy(wmc_plan_t *plan) { delete plan; }
+
+extern "C" wmc_status wmc_plan_tensor(const wmc_plan_t *plan, int64_t t, int32_t *kind, int32_t *src,
+                                      int32_t *rank, int32_t *vars) {
+    if (!plan) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_tensor: plan is NULL");
+    if (t < 0 || t >= (int64_t)plan->T.size())
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_tensor: tensor %lld out of range", (long long)t);
+    const TNode &X = plan->T[(size_t)t];
+    if (kind) *kind = X.kind;
+    if (src) *src = X.src;
+    if (rank) *rank = (int32_t)X.layout.size();
+    if (vars)
+        for (size_t q = 0; q < X.layout.size(); ++q) vars[q] = X.layout[q];
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_plan_node(const wmc_plan_t *plan, int64_t i, int64_t *a, int64_t *b, int64_t *c,
+                                    int32_t *node_class) {
+    if (!plan) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_node: plan is NULL");
+    if (i < 0 || i >= (int64_t)plan->nodes.size())
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_node: node %lld out of range", (long long)i);
+    const NodeDesc &d = plan->nodes[(size_t)i];
+    if (a) *a = d.ta;
+    if (b) *b = d.tb;
+    if (c) *c = d.tc;
+    if (node_class) *node_class = d.cls;
+    return WMC_OK;
+}
+
+// Raw descriptor image, for tools and tests that replay the launch list:
+// [LeafDesc x n_leaves][NodeDesc x n_nodes][Launch x n_launches].
+// info[] = {n_leaves, n_nodes, n_launches, arena_elems, root, root_off,
+//           n_tensors, elem_bytes, sizeof LeafDesc, sizeof NodeDesc, sizeof Launch}.
+extern "C" wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t dst_bytes, uint64_t *needed,
+                                     int64_t *info) {
+    if (!plan) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_image: plan is NULL");
+    const wmc_plan_t &P = *plan;
+    uint64_t need = sizeof(LeafDesc) * P.leaves.size() + sizeof(NodeDesc) * P.nodes.size() +
+                    sizeof(Launch) * P.launches.size();
+    if (needed) *needed = need;
+    if (info) {
+        info[0] = (int64_t)P.leaves.size();
+        info[1] = (int64_t)P.nodes.size();
+        info[2] = (int64_t)P.launches.size();
+        info[3] = (int64_t)(P.arena_bytes / (uint64_t)P.elem);
+        info[4] = P.root;
+        info[5] = P.root >= 0 ? P.T[(size_t)P.root].off : -1;
+        info[6] = (int64_t)P.T.size();
+        info[7] = P.elem;
+        info[8] = (int64_t)sizeof(LeafDesc);
+        info[9] = (int64_t)sizeof(NodeDesc);
+        info[10] = (int64_t)sizeof(Launch);
+    }
+    if (!dst) return WMC_OK;
+    if (dst_bytes < need) WMC_FAIL(WMC_ERR_OUT_OF_MEMORY, "wmc_plan_image: buffer too small");
+    char *p = (char *)dst;
+    if (!P.leaves.empty()) std::memcpy(p, P.leaves.data(), sizeof(LeafDesc) * P.leaves.size());
+    p += sizeof(LeafDesc) * P.leaves.size();
+    if (!P.nodes.empty()) std::memcpy(p, P.nodes.data(), sizeof(NodeDesc) * P.nodes.size());
+    p += sizeof(NodeDesc) * P.nodes.size();
+    if (!P.launches.empty()) std::memcpy(p, P.launches.data(), sizeof(Launch) * P.launches.size());
+    return WMC_OK;
+}
+
+// Per-launch algorithmic traffic of one slice, in the order wmc_contract
+// issues the kernels: [begin, leaf fill, node launches..., finish].
+extern "C" wmc_status wmc_plan_launches(const wmc_plan_t *plan, double *bytes, double *flops, int32_t *cls,
+                                        int64_t cap, int64_t *n_out) {
+    if (!plan) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_launches: plan is NULL");
+    const wmc_plan_t &P = *plan;
+    const int64_t n = (int64_t)P.launches.size() + 2;
+    if (n_out) *n_out = n;
+    if (!bytes && !flops && !cls) return WMC_OK;
+    if (cap < n) WMC_FAIL(WMC_ERR_OUT_OF_MEMORY, "wmc_plan_launches: need %lld slots", (long long)n);
+    std::vector<double> B((size_t)n, 0.0), F((size_t)n, 0.0);
+    std::vector<int32_t> C((size_t)n, -1);
+    B[0] = (double)(sizeof(wmc_meta) * P.T.size());
+    for (const LeafDesc &d : P.leaves) B[1] += (double)P.elem * std::ldexp(1.0, d.rank);
+    for (size_t k = 1; k < P.launches.size(); ++k) {
+        const Launch &L = P.launches[k];
+        for (int32_t q = 0; q < L.count; ++q) {
+            const NodeDesc &d = P.nodes[(size_t)(L.first + q)];
+            double a = std::ldexp(1.0, (int)P.T[(size_t)d.ta].layout.size());
+            double b = std::ldexp(1.0, (int)P.T[(size_t)d.tb].layout.size());
+            double c = std::ldexp(1.0, d.rc);
+            B[k + 1] += (double)P.elem * (a + b + c);
+            F[k + 1] += 2.0 * c * std::ldexp(1.0, d.nk);
+            C[k + 1] = d.cls;
+        }
+    }
+    B[(size_t)n - 1] = (double)(P.elem + sizeof(wmc_acc));
+    for (int64_t k = 0; k < n; ++k) {
+        if (bytes) bytes[k] = B[(size_t)k];
+        if (flops) flops[k] = F[(size_t)k];
+        if (cls) cls[k] = C[(size_t)k];
+    }
+    return WMC_OK;
+}

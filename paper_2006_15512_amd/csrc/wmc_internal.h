@@ -1,0 +1,78 @@
+// Host-side internals shared by the planner (wmc_host.cpp) and the executor
+// (wmc_device.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/wmc.h"
+#include "wmc_desc.h"
+
+// A clause of the Theorem-2 reduction: its distinct variables (ascending,
+// 1-based), the single assignment that falsifies it (bit i <-> vars[i]), and
+// whether it is a tautology (x and not-x), in which case B_C is all ones.
+struct WClause {
+    std::vector<int32_t> vars;
+    uint32_t falsify = 0;
+    bool taut = false;
+};
+
+struct wmc_network {
+    int32_t n = 0;
+    std::vector<WClause> clauses;
+    std::vector<double> w;        // 2n: {W(x,0), W(x,1)}
+    std::vector<int32_t> degree;  // clauses containing x (index x-1)
+    int64_t n_indices = 0;
+};
+
+// A tensor of the contraction tree (leaf or internal node output).
+struct TNode {
+    int32_t kind = 0;   // 0 clause leaf, 1 weight leaf, 2 internal
+    int32_t src = -1;   // clause index (kind 0) or variable 1..n (kind 1)
+    int32_t a = -1, b = -1, parent = -1;
+    std::vector<int32_t> vars;    // open variables (unsliced), ascending
+    std::vector<int32_t> cnt;     // occurrences of vars[i] inside the subtree
+    std::vector<uint8_t> has_w;   // whether A_x of vars[i] is inside the subtree
+    std::vector<int32_t> kappa;   // internal: variables summed out here (unsliced)
+    int32_t index_rank = 0;       // rank counting Theorem-2 indices
+    // after slicing and layout
+    std::vector<int32_t> layout;  // storage order, least-significant bit first
+    int64_t off = 0;              // arena element offset
+    int32_t birth = 0, death = 0; // launch indices
+    int32_t cls = 0;              // internal: node class
+};
+
+enum { LAUNCH_LEAF = 0, LAUNCH_NODES = 1 };
+
+struct Launch {
+    int32_t type;
+    int32_t first, count;   // descriptor range (node launches)
+    int32_t pad;
+    int64_t work;           // padded work items
+};
+static_assert(sizeof(Launch) == 24, "Launch layout");
+
+struct wmc_plan_t {
+    int32_t n = 0;
+    int64_t m = 0;
+    int32_t precision = WMC_FP64;
+    int32_t elem = 8;
+    std::vector<double> w;            // the network's weights
+    std::vector<TNode> T;
+    int32_t root = -1;
+    std::vector<int32_t> node_order;  // internal tensors in launch order
+    std::vector<int32_t> sliced;      // sliced variables (bit i of eta <-> sliced[i])
+    std::vector<Launch> launches;
+    std::vector<LeafDesc> leaves;
+    std::vector<NodeDesc> nodes;
+    int64_t leaf_work = 0;
+    // workspace layout (bytes)
+    uint64_t off_acc = 0, off_w = 0, off_meta = 0, off_leaf = 0, off_node = 0, off_arena = 0;
+    uint64_t desc_bytes = 0;          // contiguous [off_leaf, off_arena) image
+    std::vector<uint8_t> desc_image;
+    uint64_t arena_bytes = 0, workspace_bytes = 0;
+    wmc_plan_info info{};
+};
+
+void wmc_set_error(const char *fmt, ...);

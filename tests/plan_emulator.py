@@ -1,0 +1,129 @@
+"""Replays a plan's raw device descriptors on the CPU with numpy.
+
+Test infrastructure for the host planner: it interprets the leaf and node
+descriptors, launch list and arena offsets exactly as the HIP kernels do
+(run-list bit extraction, kappa-lowest operand layouts, shared arena,
+power-of-two operand scaling), so a wrong layout, run list, slice bit or
+arena overlap shows up on a machine without a GPU.  It is not the oracle:
+it mirrors the GPU path and is itself checked against the oracle.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+LEAF = np.dtype([("out", "<i8"), ("work_begin", "<i8"), ("tensor", "<i4"), ("kind", "<i4"),
+                 ("rank", "<i4"), ("k", "<i4"), ("var", "<i4"), ("falsify", "<u4"), ("taut", "<i4"),
+                 ("pad", "<i4"), ("pos", "<i2", (24,))])
+NODE = np.dtype({"names": ["a", "b", "c", "work_begin", "ta", "tb", "tc", "rc", "nk", "nra", "nrb", "cls",
+                           "ra", "rb"],
+                 "formats": ["<i8", "<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4",
+                             ("u1", (20, 3)), ("u1", (20, 3))],
+                 "offsets": [0, 8, 16, 24, 32, 36, 40, 44, 48, 52, 56, 60, 64, 124],
+                 "itemsize": 200})
+LAUNCH = np.dtype([("type", "<i4"), ("first", "<i4"), ("count", "<i4"), ("pad", "<i4"), ("work", "<i8")])
+
+
+def parse(plan):
+    img, info = plan.image()
+    assert info["leaf_desc_bytes"] == LEAF.itemsize
+    assert info["node_desc_bytes"] == NODE.itemsize
+    assert info["launch_bytes"] == LAUNCH.itemsize
+    nl, nn, nla = info["n_leaves"], info["n_nodes"], info["n_launches"]
+    leaves = np.frombuffer(img, LEAF, count=nl, offset=0)
+    nodes = np.frombuffer(img, NODE, count=nn, offset=nl * LEAF.itemsize)
+    launches = np.frombuffer(img, LAUNCH, count=nla, offset=nl * LEAF.itemsize + nn * NODE.itemsize)
+    return leaves, nodes, launches, info
+
+
+def _pext(r: np.ndarray, runs, nr: int) -> np.ndarray:
+    out = np.zeros_like(r)
+    for q in range(nr):
+        s, l, d = (int(x) for x in runs[q])
+        out |= ((r >> np.uint64(s)) & np.uint64((1 << l) - 1)) << np.uint64(d)
+    return out
+
+
+def _sexp(m: float) -> int:
+    if not m > 0.0:
+        return 0
+    return math.frexp(m)[1]
+
+
+def emulate(plan, weights, store=np.float64, slices=None):
+    """Contract ``plan`` on the CPU exactly as the kernels would.  Returns the
+    exact rational sum over the requested slices (default: all) of the slice
+    values as they would be produced, plus the list of per-slice values."""
+    leaves, nodes, launches, info = parse(plan)
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    root = info["root"]
+    if root < 0:
+        return Fraction(1), [Fraction(1)]
+    arena = np.zeros(max(info["arena_elems"], 1), dtype=store)
+    nt = info["n_tensors"]
+    n_slices = 1 << len(plan.stats()["sliced_vars"])
+    total = Fraction(0)
+    per = []
+    for eta in (range(n_slices) if slices is None else slices):
+        maxv = np.zeros(nt)
+        ex = np.zeros(nt, dtype=np.int64)
+        for d in leaves:
+            size = 1 << int(d["rank"])
+            e = np.arange(size, dtype=np.int64)
+            if d["kind"] == 0:
+                a = np.zeros(size, dtype=np.int64)
+                for q in range(int(d["k"])):
+                    p = int(d["pos"][q])
+                    bit = (e >> p) & 1 if p >= 0 else np.full(size, (eta >> (-p - 1)) & 1)
+                    a |= bit << q
+                v = np.where((a != int(d["falsify"])) | bool(d["taut"]), 1.0, 0.0)
+            elif d["kind"] == 1:
+                p = int(d["pos"][0])
+                bit = (e >> p) & 1 if p >= 0 else np.full(size, (eta >> (-p - 1)) & 1)
+                v = w[2 * int(d["var"]) + bit]
+            else:
+                v = np.array([w[2 * int(d["var"])] + w[2 * int(d["var"]) + 1]])
+            s = v.astype(store)
+            arena[int(d["out"]): int(d["out"]) + size] = s
+            maxv[int(d["tensor"])] = float(np.max(np.abs(s.astype(np.float64))))
+        for L in launches[1:]:
+            results = []
+            for d in nodes[int(L["first"]): int(L["first"]) + int(L["count"])]:
+                rc, nk = int(d["rc"]), int(d["nk"])
+                r = np.arange(1 << rc, dtype=np.uint64)
+                pa = _pext(r, d["ra"], int(d["nra"])) << np.uint64(nk)
+                pb = _pext(r, d["rb"], int(d["nrb"])) << np.uint64(nk)
+                sA, sB = _sexp(maxv[int(d["ta"])]), _sexp(maxv[int(d["tb"])])
+                acc = np.zeros(1 << rc)
+                for j in range(1 << nk):
+                    acc += arena[int(d["a"]) + (pa + np.uint64(j)).astype(np.int64)].astype(np.float64) * \
+                           arena[int(d["b"]) + (pb + np.uint64(j)).astype(np.int64)].astype(np.float64)
+                out = np.ldexp(acc, -(sA + sB)).astype(store)
+                results.append((d, out, int(ex[int(d["ta"])] + ex[int(d["tb"])] + sA + sB)))
+            for d, out, e in results:
+                arena[int(d["c"]): int(d["c"]) + out.size] = out
+                maxv[int(d["tc"])] = float(np.max(np.abs(out.astype(np.float64))))
+                ex[int(d["tc"])] = e
+        v = float(arena[info["root_off"]])
+        val = Fraction(v) * (Fraction(2) ** int(ex[root]))
+        per.append(val)
+        total += val
+    return total, per
+
+
+def to_float(x: Fraction) -> float:
+    if x == 0:
+        return 0.0
+    try:
+        return float(x)
+    except OverflowError:
+        return math.inf
+
+
+def rel_err(a: Fraction, b: Fraction) -> float:
+    if a == b:
+        return 0.0
+    d = abs(a - b) / max(abs(a), abs(b))
+    return float(d)

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+FP64: relative error <= 1e-12 (non-negative weights; an exact zero must come
+back as exactly zero).  Scaled FP32: <= 1e-5.  Bit-exact where the
+arithmetic is exact: all weights 1/2 (W = #models / 2^n) and all weights 1
+(W = #models) while the counts stay below 2^53 (FP64) or 2^24 (FP32).
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_15512_amd as W
+import wmc_workloads as wl
+from wmc_workloads import Formula
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    W.lib()  # fails loudly if libwmc.so is missing
+    return torch
+
+
+def value_fraction(v):
+    if v.mantissa == 0.0:
+        return Fraction(0)
+    return Fraction(v.mantissa) * Fraction(2) ** v.exp2
+
+
+def ref_of(f):
+    if f.n <= 22:
+        return Fraction(oracle.brute(f))
+    m, e = oracle.bucket(f)
+    return Fraction(m) * Fraction(2) ** e
+
+
+def rel(a: Fraction, b: Fraction) -> float:
+    if a == b:
+        return 0.0
+    return float(abs(a - b) / max(abs(a), abs(b)))
+
+
+def run(f, weights=None, **kw):
+    net = W.Network.from_formula(f)
+    p = W.Plan(net, **kw)
+    v = W.wmc_contract(p, weights)
+    return v, p
+
+
+# ------------------------------------------------------------------ small random formulas
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_mixed_small(precision, tol):
+    for s in range(120):
+        f = wl.random_mixed(s, n_max=14, m_max=28)
+        say(f"mixed seed={s} n={f.n} m={f.m} {precision}")
+        v, _ = run(f, seed=s, precision=precision)
+        ref = Fraction(oracle.brute(f))
+        got = value_fraction(v)
+        if ref == 0:
+            assert got == 0, s
+        else:
+            assert rel(got, ref) <= tol, (s, float(got), float(ref))
+
+
+def test_negative_weights():
+    for s in range(40):
+        f = wl.random_mixed(s, n_max=12, m_max=20, negative=True)
+        say(f"negative seed={s}")
+        v, _ = run(f, seed=s)
+        ref = oracle.brute(f)
+        scale = float(np.prod(np.abs(f.weights).sum(axis=1)))
+        assert abs(v.value - ref) <= 1e-12 * scale
+
+
+def test_config1_random3cnf_seed_sweep():
+    """Random 3-CNF, 20 variables, 85 clauses: seeds 0..39 against brute force."""
+    n_sat = 0
+    for s in range(40):
+        f = wl.random_kcnf(20, 85, s)
+        say(f"config1 seed={s}")
+        v, p = run(f, seed=0)
+        ref = Fraction(oracle.brute(f))
+        got = value_fraction(v)
+        if ref == 0:
+            assert got == 0
+        else:
+            n_sat += 1
+            assert rel(got, ref) <= 1e-12
+    assert n_sat > 10
+
+
+# ------------------------------------------------------------------ exact modes
+def test_all_half_bit_exact():
+    """All weights 1/2: W = #models / 2^n exactly (FP64 and FP32 while the
+    counts stay below 2^24)."""
+    for s in range(30):
+        f = wl.random_kcnf(22, 60 + s, 300 + s)
+        half = f.with_weights(np.full((f.n, 2), 0.5))
+        cnt = oracle.exact_count(f)
+        say(f"half seed={s} count={cnt}")
+        for prec in ("fp64", "fp32"):
+            v, _ = run(half, seed=s, precision=prec)
+            assert value_fraction(v) == Fraction(cnt, 2 ** f.n), (s, prec)
+
+
+def test_all_ones_bit_exact():
+    """All weights 1: W = #models exactly."""
+    for s in range(20):
+        f = wl.banded_3cnf(40, 100, 12, seed=s)
+        ones = f.with_weights(np.ones((f.n, 2)))
+        cnt = oracle.exact_count(f)
+        assert cnt < 2 ** 53
+        say(f"ones seed={s} count={cnt}")
+        v, _ = run(ones, seed=s)
+        assert value_fraction(v) == cnt
+
+
+# ------------------------------------------------------------------ trees and slicing
+def test_tree_independence():
+    f = wl.random_kcnf(20, 70, 9)
+    ref = Fraction(oracle.brute(f))
+    vals = []
+    for seed in range(8):
+        say(f"tree seed={seed}")
+        v, _ = run(f, seed=seed)
+        vals.append(value_fraction(v))
+        assert rel(vals[-1], ref) <= 1e-12
+    for block in (2, 3, 5):
+        v, _ = run(f, kind="order", order=oracle.minfill_order(f), block=block)
+        assert rel(value_fraction(v), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("cap", [3, 6, 9])
+def test_slicing(cap):
+    f = wl.random_kcnf(20, 75, 41)
+    say(f"slicing cap={cap}")
+    net = W.Network.from_formula(f)
+    p = W.Plan(net, seed=3, rank_cap=cap)
+    st = p.stats()
+    assert st["max_rank"] <= cap and st["n_sliced"] > 0
+    tot, per = W.wmc_contract_slices(p, 0, p.n_slices, per_slice=True)
+    ref = Fraction(oracle.brute(f))
+    assert rel(value_fraction(tot), ref) <= 1e-12
+    sv = st["sliced_vars"]
+    for eta in range(min(p.n_slices, 8)):
+        units = [[v if (eta >> i) & 1 else -v] for i, v in enumerate(sv)]
+        r = Fraction(oracle.brute(f.with_clauses(units)))
+        got = value_fraction(per[eta])
+        assert (got == 0) if r == 0 else rel(got, r) <= 1e-12
+    # a partition of the slices sums to the whole (the multi-GPU split)
+    half = p.n_slices // 2
+    a = value_fraction(W.wmc_contract_slices(p, 0, half))
+    b = value_fraction(W.wmc_contract_slices(p, half, p.n_slices))
+    assert rel(a + b, ref) <= 1e-12
+
+
+def test_weights_override_and_reuse():
+    f = wl.grid_cnf(6, 7, 0.2, seed=4)
+    net = W.Network.from_formula(f)
+    p = W.Plan(net, kind="order", order=wl.row_major_order(6, 7))
+    ws = W.workspace(p)
+    rng = np.random.default_rng(0)
+    for q in range(10):
+        w = rng.uniform(0.1, 0.9, size=f.n)
+        Wt = np.stack([1 - w, w], axis=1)
+        v = W.wmc_contract(p, Wt, ws)
+        m, e = oracle.bucket(f.with_weights(Wt))
+        assert rel(value_fraction(v), Fraction(m) * Fraction(2) ** e) <= 1e-12
+
+
+@pytest.mark.parametrize("f", [
+    Formula(0, [], np.zeros((0, 2))),
+    Formula(1, [], np.array([[0.3, 0.4]])),
+    Formula(2, [[]], np.array([[0.3, 0.4], [0.5, 0.5]])),
+    Formula(2, [[1, -1]], np.array([[0.3, 0.4], [0.5, 0.25]])),
+    Formula(3, [[1], [-1]], np.full((3, 2), 0.5)),
+    Formula(3, [[2, 2, 2]], np.array([[1, 2], [3, 4], [5, 6]], dtype=float)),
+    wl.psi_formula(20),
+])
+def test_degenerate(f):
+    say(f"degenerate {f.clauses[:3]}")
+    v, _ = run(f)
+    ref = Fraction(oracle.brute(f)) if f.n else Fraction(1)
+    assert rel(value_fraction(v), ref) <= 1e-14
+
+
+def test_workspace_too_small():
+    f = wl.random_kcnf(12, 30, 1)
+    p = W.Plan(W.Network.from_formula(f))
+    import torch
+    ws = torch.empty(p.workspace_bytes - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(W.WmcError) as e:
+        W.wmc_contract(p, None, ws)
+    assert e.value.status == 2
+
+
+# ------------------------------------------------------------------ full-size lattice
+def _golden(name):
+    with open(GOLDEN) as fh:
+        return json.load(fh)[name]
+
+
+@pytest.mark.parametrize("name,rows", [("grid12x24_t0.10_s1", 12), ("grid24x24_t0.10_s0", 24)])
+@pytest.mark.parametrize("block", [1, 6])
+def test_grid_lattice_vs_golden(name, rows, block):
+    """The 24-column lattice swept row by row (max storage rank 25) against
+    the oracle's stored value for the same seeded instance."""
+    g = _golden(name)
+    seed = 0 if name.endswith("s0") else 1
+    f = wl.grid_cnf(rows, 24, 0.10, seed=seed)
+    assert f.digest() == g["digest"]
+    say(f"{name} block={block}")
+    v, p = run(f, kind="order", order=wl.row_major_order(rows, 24), block=block)
+    ref = Fraction(float.fromhex(g["mantissa_hex"])) * Fraction(2) ** g["exp2"]
+    assert rel(value_fraction(v), ref) <= 1e-12

@@ -1,0 +1,269 @@
+"""Host-side tests of the reduction and the planner (no GPU needed).
+
+The plans' device descriptors are replayed on the CPU by the kernel emulator
+(tests/plan_emulator.py) and the result is compared with the oracle.  This
+covers the tree construction, variable closure, tied storage modes, index
+slicing, layouts, bit-extraction run lists and arena placement before any
+kernel runs.  The GPU parity tests then check the kernels themselves.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_15512_amd as W
+import wmc_workloads as wl
+from wmc_workloads import Formula
+from plan_emulator import emulate, rel_err, parse
+
+pytestmark = pytest.mark.skipif(not __import__("os").path.exists(W.LIB_PATH), reason="libwmc.so not built")
+
+
+def ref_fraction(f):
+    if f.n <= 20:
+        return Fraction(oracle.brute(f))
+    m, e = oracle.bucket(f)
+    return Fraction(m) * Fraction(2) ** e
+
+
+def random_parent(f, seed):
+    """A uniformly random merge order over the n+m leaves, as a parent array
+    in the ABI's numbering (A_x first, then B_C, then internal vertices)."""
+    rng = np.random.default_rng(seed)
+    L = f.n + f.m
+    parent = np.full(2 * L - 1, -1, dtype=np.int64)
+    roots = list(range(L))
+    nxt = L
+    while len(roots) > 1:
+        i, j = sorted(rng.choice(len(roots), size=2, replace=False))
+        a, b = roots[i], roots[j]
+        parent[a] = parent[b] = nxt
+        roots.pop(j)
+        roots[i] = nxt
+        nxt += 1
+    return parent
+
+
+# --------------------------------------------------------------- reduction
+def test_fig1_network_info():
+    """Figure 1: 8 tensors and 10 indices."""
+    net = W.Network.from_formula(wl.fig1_formula())
+    assert net.info() == {"n_tensors": 8, "n_indices": 10}
+
+
+def test_network_info_counts_distinct_incidences():
+    f = Formula(3, [[1, 1, 2], [2, -2, 3], [-3]], np.ones((3, 2)))
+    assert W.Network.from_formula(f).info() == {"n_tensors": 6, "n_indices": 5}
+
+
+@pytest.mark.parametrize("clauses,n,weights,status", [
+    ([[4]], 3, None, 1),                  # literal out of range
+    ([[0, 1]], 3, None, 1),               # zero literal
+    ([[1]], 1, [[np.nan, 1.0]], 1),       # NaN weight
+    ([[1]], 1, [[np.inf, 1.0]], 1),       # Inf weight
+    ([list(range(1, 27))], 26, None, 6),  # clause longer than WMC_MAX_CLAUSE
+])
+def test_build_network_errors(clauses, n, weights, status):
+    w = np.ones((n, 2)) if weights is None else np.array(weights)
+    with pytest.raises(W.WmcError) as e:
+        W.Network(n, clauses, w)
+    assert e.value.status == status
+
+
+def test_plan_errors():
+    f = wl.random_kcnf(10, 20, 1)
+    net = W.Network.from_formula(f)
+    with pytest.raises(W.WmcError) as e:
+        W.Plan(net, kind="order", order=[1, 2, 3])
+    assert e.value.status == 1
+    with pytest.raises(W.WmcError) as e:
+        W.Plan(net, kind="order", order=[1] * 10)
+    assert e.value.status == 1
+    bad = random_parent(f, 0)
+    bad[0] = bad[1]
+    bad[2] = -1
+    with pytest.raises(W.WmcError) as e:
+        W.Plan(net, kind="explicit", parent=bad)
+    assert e.value.status == 1
+    with pytest.raises(W.WmcError) as e:
+        W.Plan(net, kind="explicit", parent=random_parent(f, 0)[:-1])
+    assert e.value.status == 1
+
+
+# --------------------------------------------------------------- plans replayed on the CPU
+@pytest.mark.parametrize("kind", ["minfill", "order", "explicit"])
+def test_emulated_plans_match_oracle(kind):
+    """Every tree kind, replayed from its descriptors, equals the oracle."""
+    rng = np.random.default_rng(1)
+    for s in range(60):
+        f = wl.random_mixed(s, n_max=12, m_max=24)
+        net = W.Network.from_formula(f)
+        if kind == "minfill":
+            p = W.Plan(net, seed=s)
+        elif kind == "order":
+            p = W.Plan(net, kind="order", order=rng.permutation(f.n) + 1, block=int(rng.integers(1, 4)))
+        else:
+            p = W.Plan(net, kind="explicit", parent=random_parent(f, s))
+        got, _ = emulate(p, f.weights)
+        ref = ref_fraction(f)
+        if ref == 0:
+            assert got == 0, s
+        else:
+            assert rel_err(got, ref) < 1e-12, (s, float(got), float(ref))
+
+
+def test_emulated_negative_weights():
+    for s in range(30):
+        f = wl.random_mixed(s, n_max=10, m_max=16, negative=True)
+        p = W.Plan(W.Network.from_formula(f), seed=s)
+        got, _ = emulate(p, f.weights)
+        ref = Fraction(oracle.brute(f))
+        scale = float(np.prod(np.abs(f.weights).sum(axis=1)))
+        assert abs(float(got - ref)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("block", [1, 2, 5])
+def test_emulated_grid_sweep(block):
+    """A small lattice swept row by row, in blocks of variables."""
+    f = wl.grid_cnf(5, 6, 0.2, seed=3)
+    p = W.Plan(W.Network.from_formula(f), kind="order", order=wl.row_major_order(5, 6), block=block)
+    got, _ = emulate(p, f.weights)
+    m, e = oracle.bucket(f)
+    assert rel_err(got, Fraction(m) * Fraction(2) ** e) < 1e-12
+
+
+def test_emulated_weights_override():
+    """The same plan with another weight vector (the serving pattern)."""
+    f = wl.random_kcnf(16, 50, 12)
+    p = W.Plan(W.Network.from_formula(f), seed=2)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        w = rng.uniform(0.1, 0.9, size=f.n)
+        Wt = np.stack([1 - w, w], axis=1)
+        got, _ = emulate(p, Wt)
+        ref = Fraction(oracle.brute(f.with_weights(Wt)))
+        assert rel_err(got, ref) < 1e-12
+
+
+def test_emulated_fp32_storage():
+    """FP32 storage with per-tensor power-of-two exponents stays within 1e-5."""
+    for s in range(20):
+        f = wl.random_kcnf(18, 70, 200 + s)
+        p = W.Plan(W.Network.from_formula(f), seed=s, precision="fp32")
+        got, _ = emulate(p, f.weights, store=np.float32)
+        ref = Fraction(oracle.brute(f))
+        if ref == 0:
+            assert got == 0
+        else:
+            assert rel_err(got, ref) < 1e-5
+
+
+# --------------------------------------------------------------- slicing (Algorithm 3)
+@pytest.mark.parametrize("cap", [2, 4, 6])
+def test_rank_cap_slicing(cap):
+    """Slicing meets the rank cap; the slices sum to W (slicing theorem) and
+    each slice equals the oracle with the sliced variables fixed."""
+    f = wl.random_kcnf(16, 56, 31)
+    net = W.Network.from_formula(f)
+    p = W.Plan(net, seed=1, rank_cap=cap)
+    s = p.stats()
+    assert s["max_rank"] <= cap
+    assert s["n_slices"] == 2 ** s["n_sliced"]
+    assert s["max_rank_unsliced"] > cap
+    got, per = emulate(p, f.weights)
+    assert rel_err(got, Fraction(oracle.brute(f))) < 1e-12
+    sv = s["sliced_vars"]
+    for eta in range(min(len(per), 16)):
+        units = [[v if (eta >> i) & 1 else -v] for i, v in enumerate(sv)]
+        ref = Fraction(oracle.brute(f.with_clauses(units)))
+        if ref == 0:
+            assert per[eta] == 0
+        else:
+            assert rel_err(per[eta], ref) < 1e-12
+
+
+def test_mem_cap_slicing():
+    f = wl.random_kcnf(18, 64, 5)
+    net = W.Network.from_formula(f)
+    p0 = W.Plan(net, seed=0)
+    peak = p0.stats()["peak_live_bytes"]
+    p = W.Plan(net, seed=0, mem_cap_bytes=int(peak // 5))
+    s = p.stats()
+    assert s["peak_live_bytes"] <= peak // 5
+    assert s["n_sliced"] >= 1
+    got, _ = emulate(p, f.weights)
+    assert rel_err(got, Fraction(oracle.brute(f))) < 1e-12
+
+
+def test_cap_unreachable():
+    f = wl.random_kcnf(12, 40, 5)
+    with pytest.raises(W.WmcError) as e:
+        W.Plan(W.Network.from_formula(f), seed=0, mem_cap_bytes=8)
+    assert e.value.status == 3
+
+
+# --------------------------------------------------------------- statistics and edge cases
+def test_stats_recount():
+    """flops and bytes per slice recounted from the exported tensors."""
+    f = wl.grid_cnf(4, 5, 0.3, seed=1)
+    p = W.Plan(W.Network.from_formula(f), kind="order", order=wl.row_major_order(4, 5))
+    tensors, nodes, sliced = p.export()
+    s = p.stats()
+    fl = by = 0.0
+    for a, b, c, _ in nodes:
+        ra, rb, rc = (len(tensors[t][2]) for t in (a, b, c))
+        shared = set(tensors[a][2]) & set(tensors[b][2])
+        nk = len(shared - set(tensors[c][2]))
+        fl += 2.0 * 2 ** (rc + nk)
+        by += 8.0 * (2 ** ra + 2 ** rb + 2 ** rc)
+    assert fl == s["flops_per_slice"]
+    assert by == s["bytes_per_slice"]
+    assert s["max_rank"] == max(len(t[2]) for t in tensors)
+
+
+def test_tree_independence_emulated():
+    """Different trees (seeds, orders, blocks, explicit) give the same W."""
+    f = wl.random_kcnf(14, 45, 77)
+    net = W.Network.from_formula(f)
+    ref = Fraction(oracle.brute(f))
+    for seed in range(6):
+        got, _ = emulate(W.Plan(net, seed=seed), f.weights)
+        assert rel_err(got, ref) < 1e-12
+    for seed in range(4):
+        got, _ = emulate(W.Plan(net, kind="explicit", parent=random_parent(f, seed)), f.weights)
+        assert rel_err(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("f", [
+    Formula(0, [], np.zeros((0, 2))),
+    Formula(1, [], np.array([[0.3, 0.4]])),
+    Formula(2, [[]], np.array([[0.3, 0.4], [0.5, 0.5]])),
+    Formula(2, [[1, -1]], np.array([[0.3, 0.4], [0.5, 0.25]])),
+    Formula(3, [[1], [-1]], np.full((3, 2), 0.5)),
+    Formula(3, [[2, 2, 2]], np.array([[1, 2], [3, 4], [5, 6]], dtype=float)),
+])
+def test_degenerate_formulas(f):
+    p = W.Plan(W.Network.from_formula(f))
+    got, _ = emulate(p, f.weights)
+    ref = Fraction(oracle.brute(f)) if f.n else Fraction(1)
+    assert rel_err(got, ref) < 1e-14
+
+
+def test_fig1_index_rank_and_storage_rank():
+    """Storage rank counts tied variables; the index rank counts Theorem-2
+    indices and is never smaller."""
+    f = wl.fig1_formula()
+    s = W.Plan(W.Network.from_formula(f)).stats()
+    assert s["max_rank"] <= s["max_index_rank"]
+
+
+def test_grid24_sweep_plan_shape():
+    """The 24x24 lattice swept row-major has max storage rank 25 (width 24-25)."""
+    f = wl.grid_cnf(24, 24, 0.10, seed=0)
+    assert f.m == 2 * 1104 + 110
+    p = W.Plan(W.Network.from_formula(f), kind="order", order=wl.row_major_order(24, 24))
+    s = p.stats()
+    assert 24 <= s["max_rank"] <= 26
+    assert s["class_hist"]["stream"] > 500

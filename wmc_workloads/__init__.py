@@ -116,8 +116,17 @@ def random_kcnf(n: int, m: int, seed: int, k: int = 3, wlo: float = 0.1, whi: fl
     return Formula(n, clauses, weights, f"random{k}cnf-n{n}-m{m}-s{seed}")
 
 
+def _planted_signed(rng: np.random.Generator, vars_: np.ndarray, sigma: np.ndarray) -> List[int]:
+    """Signs drawn uniformly among the patterns the planted assignment sigma
+    satisfies (rejection: redraw while every literal is false under sigma)."""
+    while True:
+        signs = rng.integers(0, 2, size=len(vars_))
+        if any(int(sigma[int(v) - 1]) == int(s) for v, s in zip(vars_, signs)):
+            return [int(v) if s else -int(v) for v, s in zip(vars_, signs)]
+
+
 def grid_cnf(rows: int, cols: int, ternary_frac: float, seed: int,
-             n_global: int = 0, wlo: float = 0.1, whi: float = 0.9) -> Formula:
+             n_global: int = 0, wlo: float = 0.1, whi: float = 0.9, planted: bool = True) -> Formula:
     """Lattice CNF on a rows x cols variable grid, variable (i, j) = i*cols + j + 1.
 
     Each lattice edge (horizontal edges of a cell first, then its vertical
@@ -126,8 +135,18 @@ def grid_cnf(rows: int, cols: int, ternary_frac: float, seed: int,
     #edges) ternary clauses, each over 3 distinct corners of a uniformly drawn
     plaquette (a local reading: the clause stays inside one lattice square).
     Then ``n_global`` random 3-clauses over 3 distinct variables of the whole
-    grid.  Weights last, w ~ U(wlo, whi)."""
+    grid.  Weights last, w ~ U(wlo, whi).
+
+    With ``planted`` (the default) a hidden assignment sigma ~ U{0,1}^n is
+    drawn first and every clause's signs are drawn uniformly among the sign
+    patterns sigma satisfies.  With independent fair-coin signs two binary
+    clauses per edge force units that collide almost surely (e.g. (a|b) and
+    (a|~b) force a), so the lattice is unsatisfiable and W = 0; the planted
+    reading keeps the same structure with W > 0."""
     rng = np.random.default_rng(seed)
+    n = rows * cols
+    sigma = rng.integers(0, 2, size=n) if planted else None
+    sign = (lambda vs: _planted_signed(rng, vs, sigma)) if planted else (lambda vs: _signed(rng, vs))
     vid = lambda i, j: i * cols + j + 1
     clauses: List[List[int]] = []
     n_edges = 0
@@ -141,18 +160,17 @@ def grid_cnf(rows: int, cols: int, ternary_frac: float, seed: int,
             for (a, b) in nb:
                 n_edges += 1
                 for _ in range(2):
-                    clauses.append(_signed(rng, np.array([vid(i, j), vid(a, b)])))
+                    clauses.append(sign(np.array([vid(i, j), vid(a, b)])))
     n_tern = int(round(ternary_frac * n_edges))
     for _ in range(n_tern):
         pi = int(rng.integers(0, rows - 1))
         pj = int(rng.integers(0, cols - 1))
         corners = [vid(pi, pj), vid(pi, pj + 1), vid(pi + 1, pj), vid(pi + 1, pj + 1)]
         pick = rng.choice(4, size=3, replace=False)
-        clauses.append(_signed(rng, np.array([corners[p] for p in pick])))
-    n = rows * cols
+        clauses.append(sign(np.array([corners[p] for p in pick])))
     for _ in range(n_global):
         vs = rng.choice(n, size=3, replace=False) + 1
-        clauses.append(_signed(rng, vs))
+        clauses.append(sign(vs))
     weights = uniform_weights(rng, n, wlo, whi)
     return Formula(n, clauses, weights, f"grid{rows}x{cols}-t{ternary_frac}-g{n_global}-s{seed}")
 
