@@ -151,16 +151,17 @@ void wmc_plan_destroy(wmc_plan_t *plan);
  *     room for WMC_MAX_RANK entries).
  *   wmc_plan_node: node i (launch order) contracts tensors a and b into c.
  *   wmc_plan_image: the raw device descriptors as they are uploaded
- *     ([leaf descriptors][node descriptors][launch list]); with dst == NULL it
- *     only reports *needed and info[0..10] = {n_leaves, n_nodes, n_launches,
- *     arena_elems, root, root_offset, n_tensors, elem_bytes, leaf_desc_bytes,
- *     node_desc_bytes, launch_bytes}. */
+ *     ([leaf descriptors][node descriptors][launch list][matrix-node
+ *     descriptors]); with dst == NULL it only reports *needed and
+ *     info[0..12] = {n_leaves, n_nodes, n_launches, arena_elems, root,
+ *     root_offset, n_tensors, elem_bytes, leaf_desc_bytes, node_desc_bytes,
+ *     launch_bytes, n_gemms, gemm_desc_bytes}. */
 wmc_status wmc_plan_tensor(const wmc_plan_t *plan, int64_t t, int32_t *kind, int32_t *src,
                            int32_t *rank, int32_t *vars);
 wmc_status wmc_plan_node(const wmc_plan_t *plan, int64_t i, int64_t *a, int64_t *b, int64_t *c,
                          int32_t *node_class);
 wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t dst_bytes, uint64_t *needed,
-                          int64_t *info /* 11 entries */);
+                          int64_t *info /* 13 entries */);
 
 /* ------------------------------------------------------------------ */
 /* Execution stage (Algorithm 2 over the slices of Algorithm 3)         */

@@ -237,12 +237,12 @@ class Plan:
     def image(self):
         """Raw descriptor image: (bytes, info dict) as uploaded to the device."""
         need = ctypes.c_uint64()
-        info = (ctypes.c_int64 * 11)()
+        info = (ctypes.c_int64 * 13)()
         _check(lib().wmc_plan_image(self._h, None, 0, ctypes.byref(need), info))
         buf = (ctypes.c_uint8 * max(int(need.value), 1))()
         _check(lib().wmc_plan_image(self._h, buf, int(need.value), ctypes.byref(need), info))
         keys = ["n_leaves", "n_nodes", "n_launches", "arena_elems", "root", "root_off", "n_tensors",
-                "elem", "leaf_desc_bytes", "node_desc_bytes", "launch_bytes"]
+                "elem", "leaf_desc_bytes", "node_desc_bytes", "launch_bytes", "n_gemms", "gemm_desc_bytes"]
         return bytes(buf)[: int(need.value)], dict(zip(keys, list(info)))
 
     def __del__(self):

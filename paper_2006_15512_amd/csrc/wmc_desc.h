@@ -65,5 +65,26 @@ struct NodeDesc {
     int pad[3];
 };
 
+// A contraction run as a batched matrix product on MFMA:
+//   C[beta, mu, nu] = sum_kappa A[beta, mu, kappa] * B[beta, kappa, nu]
+// with rows (beta, mu) of the larger operand A and columns (beta, nu) of B.
+// Logical indices list their variables in C's storage order; each deposit
+// run list maps a logical index onto storage bits (src bit, length, dst bit):
+//   row of A = dep(mu, 0) | dep(beta, 1)   -> A + (row << nk) + kappa
+//   col of B = dep(nu, 2) | dep(beta, 3)   -> B + (col << nk) + kappa
+//   address in C = dep(mu, 4) | dep(nu, 5) | dep(beta, 6)
+#define WMC_GEMM_RUNS 12
+enum { GR_MU_A = 0, GR_BETA_A, GR_NU_B, GR_BETA_B, GR_MU_C, GR_NU_C, GR_BETA_C, GR_N };
+
+struct GemmDesc {
+    long long a, b, c;
+    int ta, tb, tc;
+    int nk, nm, nn, nb;
+    int nrun[GR_N];
+    unsigned char run[GR_N][WMC_GEMM_RUNS][3];
+    int pad;
+};
+
 static_assert(sizeof(LeafDesc) == 96, "LeafDesc layout");
+static_assert(sizeof(GemmDesc) == 336, "GemmDesc layout");
 static_assert(sizeof(NodeDesc) == 200, "NodeDesc layout");

@@ -150,6 +150,159 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-shaped contractions on MFMA (16x16x4, FP64 or FP32).
+//
+// A workgroup of 4 waves owns 128 rows (beta fixed by blockIdx.y, mu from
+// blockIdx.x) and every column.  Each wave computes 32 rows x N columns as
+// 2 x NT tiles of 16x16.  For the 16x16x4 instruction lane l supplies row
+// (or column) l%16 and reduction slot l/16; here lane group g = l/16 walks a
+// contiguous range of S summed indices [g*S, g*S+S) over S instructions, so
+// a lane's A operand is S consecutive elements of one row, loaded straight
+// from HBM into registers.  A and B use the same permutation of the summed
+// index, so the product sums every (row, k, col) term exactly once.  B (the
+// small operand, columns contiguous in kappa) is staged in LDS per chunk of
+// KC summed indices.
+// ---------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Output register v of lane l holds column l%16 and row out_row(l/16, v):
+// rows g + 4v for the FP64 instruction, 4g + v for the FP32 one (measured).
+template <> struct Mfma<double> {
+    typedef dbl4 acc_t;
+    static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int g, int v) { return g + 4 * v; }
+};
+template <> struct Mfma<float> {
+    typedef flt4 acc_t;
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int g, int v) { return 4 * g + v; }
+};
+
+#define GEMM_ROWS 128
+#define GEMM_LDS_BYTES (48 * 1024)
+
+__host__ __device__ inline int gemm_kc(int nk, int nn, int elem) {
+    int K = 1 << nk, N = 1 << nn;
+    int kc = K < 64 ? K : 64;
+    while (kc > 4 && (long long)N * (kc + 4) * elem > GEMM_LDS_BYTES) kc >>= 1;
+    return kc;
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T *__restrict__ arena, wmc_meta *meta) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    extern __shared__ char smem_raw[];
+    T *Bs = (T *)smem_raw;
+    const GemmDesc &d = *G;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, l16 = lane & 15;
+    const unsigned long long M = 1ull << d.nm;
+    const int K = 1 << d.nk, N = 1 << d.nn;
+    const int KC = gemm_kc(d.nk, d.nn, (int)sizeof(T));
+    const int S = KC >= 4 ? KC / 4 : 1;
+    const int LDK = KC + (sizeof(T) == 8 ? 2 : 4);
+    const unsigned long long beta = blockIdx.y;
+    const int sA = scale_exp(meta[d.ta].maxbits);
+    const int sB = scale_exp(meta[d.tb].maxbits);
+    const unsigned long long rowBeta = pext_runs(beta, d.run[GR_BETA_A], d.nrun[GR_BETA_A]);
+    const unsigned long long colBeta = pext_runs(beta, d.run[GR_BETA_B], d.nrun[GR_BETA_B]);
+    const unsigned long long m0 = (unsigned long long)blockIdx.x * GEMM_ROWS + (unsigned long long)wave * 32;
+
+    long long arow[2];
+    bool rv[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        unsigned long long m = m0 + rt * 16 + l16;
+        rv[rt] = m < M;
+        arow[rt] = d.a + (long long)((pext_runs(rv[rt] ? m : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << d.nk);
+    }
+    acc_t acc[2][NT];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
+
+    for (int kc = 0; kc < K; kc += KC) {
+        for (int idx = threadIdx.x; idx < N * KC; idx += 256) {
+            int col = idx / KC, k = idx - col * KC;
+            unsigned long long cb = pext_runs((unsigned long long)col, d.run[GR_NU_B], d.nrun[GR_NU_B]) | colBeta;
+            Bs[col * LDK + k] = arena[d.b + (long long)(cb << d.nk) + kc + k];
+        }
+        __syncthreads();
+        T a[2][16];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                int k = g * S + s;
+                a[rt][s] = (s < S && rv[rt] && k < KC) ? arena[arow[rt] + kc + k] : (T)0;
+            }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+            const int col = ct * 16 + l16;
+            T b[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                int k = g * S + s;
+                b[s] = (s < S && col < N && k < KC) ? Bs[col * LDK + k] : (T)0;
+            }
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                if (s < S) {
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) acc[rt][ct] = Mfma<T>::step(a[rt][s], b[s], acc[rt][ct]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    const double scale = ldexp(1.0, -(sA + sB));
+    const unsigned long long cBeta = pext_runs(beta, d.run[GR_BETA_C], d.nrun[GR_BETA_C]);
+    double vmax = 0.0;
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+        const int col = ct * 16 + l16;
+        if (col >= N) continue;
+        const unsigned long long cc = pext_runs((unsigned long long)col, d.run[GR_NU_C], d.nrun[GR_NU_C]) | cBeta;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                unsigned long long m = m0 + rt * 16 + Mfma<T>::out_row(g, v);
+                if (m >= M) continue;
+                T sv = (T)((double)acc[rt][ct][v] * scale);
+                arena[d.c + (long long)(pext_runs(m, d.run[GR_MU_C], d.nrun[GR_MU_C]) | cc)] = sv;
+                vmax = fmax(vmax, fabs((double)sv));
+            }
+    }
+    publish_max(meta, d.tc, vmax);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
+}
+
+template <typename T>
+static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_meta *meta, hipStream_t st) {
+    const int N = 1 << hd.nn;
+    const int KC = gemm_kc(hd.nk, hd.nn, (int)sizeof(T));
+    const int LDK = KC + (sizeof(T) == 8 ? 2 : 4);
+    const size_t smem = (size_t)N * LDK * sizeof(T);
+    const unsigned long long M = 1ull << hd.nm;
+    dim3 grid((unsigned)((M + GEMM_ROWS - 1) / GEMM_ROWS), 1u << hd.nb);
+    const int NT = (N + 15) / 16;
+    if (NT <= 1) hipLaunchKernelGGL((k_gemm<T, 1>), grid, dim3(256), smem, st, dd, arena, meta);
+    else if (NT <= 2) hipLaunchKernelGGL((k_gemm<T, 2>), grid, dim3(256), smem, st, dd, arena, meta);
+    else if (NT <= 4) hipLaunchKernelGGL((k_gemm<T, 4>), grid, dim3(256), smem, st, dd, arena, meta);
+    else hipLaunchKernelGGL((k_gemm<T, 8>), grid, dim3(256), smem, st, dd, arena, meta);
+}
+
 // Root of one slice: fold its value into the running sum (s + c) * 2^e.
 template <typename T>
 __global__ void k_finish(const T *__restrict__ arena, long long root_off, const wmc_meta *meta, int root,
@@ -256,6 +409,7 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
     const double *w = (const double *)(ws + P.off_w);
     const LeafDesc *L = (const LeafDesc *)(ws + P.off_leaf);
     const NodeDesc *D = (const NodeDesc *)(ws + P.off_node);
+    const GemmDesc *Gd = (const GemmDesc *)(ws + P.off_gemm);
     T *arena = (T *)(ws + P.off_arena);
     const int nt = (int)P.T.size();
     for (long long eta = b; eta < e; ++eta) {
@@ -273,8 +427,11 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
         if (tm) tm->mark();
         for (size_t k = 1; k < P.launches.size(); ++k) {
             const Launch &Ln = P.launches[k];
-            hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first, Ln.count,
-                               (long long)Ln.work, arena, meta);
+            if (Ln.type == LAUNCH_GEMM)
+                launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st);
+            else
+                hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first,
+                                   Ln.count, (long long)Ln.work, arena, meta);
             if (tm) tm->mark();
         }
         hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(1), 0, st, arena, (long long)P.T[(size_t)P.root].off, meta,

@@ -484,11 +484,77 @@ static int32_t skappa(const TNode &t, const std::vector<uint8_t> &sl) {
     return r;
 }
 
-// Node class from storage ranks: tiny nodes are batched many per launch.
+// Node class from storage ranks: tiny nodes are batched many per launch;
+// nodes with a real matrix shape (summed and column dimensions of at least
+// 4, product at least 64, columns at most 128) run on MFMA; the rest
+// (Hadamard, outer products, a single summed variable) stream.
 static int32_t node_class(int32_t ra, int32_t rb, int32_t rc, int32_t nk) {
     int32_t mx = std::max(ra, std::max(rb, rc));
     if (mx <= 14 && rc + nk <= 18) return WMC_CLASS_SMALL;
+    int32_t nb = ra + rb - rc - 2 * nk;
+    int32_t nn = std::min(ra, rb) - nk - nb;  // columns: variables of the smaller operand only
+    int32_t nm = std::max(ra, rb) - nk - nb;
+    if (nk >= 2 && nn >= 2 && nk + nn >= 6 && nn <= 7 && nm + nb >= 4) return WMC_CLASS_GEMM;
     return WMC_CLASS_STREAM;
+}
+
+// Compress (src, dst) bit pairs, src = 0, 1, 2, ... into runs where both advance together.
+static bool make_runs(const std::vector<int32_t> &dst, unsigned char (*runs)[3], int *nrun, int cap) {
+    int nr = 0;
+    for (size_t t = 0; t < dst.size();) {
+        size_t u = t + 1;
+        while (u < dst.size() && dst[u] == dst[u - 1] + 1) ++u;
+        if (nr >= cap) return false;
+        runs[nr][0] = (unsigned char)t;
+        runs[nr][1] = (unsigned char)(u - t);
+        runs[nr][2] = (unsigned char)dst[t];
+        ++nr;
+        t = u;
+    }
+    *nrun = nr;
+    return true;
+}
+
+// Matrix form of node id for the MFMA kernel; false if a run list overflows.
+static bool make_gemm(const std::vector<TNode> &T, int32_t id, const std::vector<uint8_t> &sl, GemmDesc &g) {
+    const TNode &C = T[(size_t)id];
+    int32_t xa = C.a, xb = C.b;
+    if (T[(size_t)xb].layout.size() > T[(size_t)xa].layout.size()) std::swap(xa, xb);
+    const TNode &A = T[(size_t)xa], &B = T[(size_t)xb];
+    std::memset(&g, 0, sizeof g);
+    g.a = A.off;
+    g.b = B.off;
+    g.c = C.off;
+    g.ta = xa;
+    g.tb = xb;
+    g.tc = id;
+    g.nk = skappa(C, sl);
+    auto contains = [](const std::vector<int32_t> &L, int32_t v) { return std::find(L.begin(), L.end(), v) != L.end(); };
+    // positions in C, and row ranks inside A and B (their C-variables follow C's order)
+    std::vector<int32_t> mu_a, beta_a, nu_b, beta_b, mu_c, nu_c, beta_c;
+    int32_t ra = 0, rb = 0;
+    for (size_t j = 0; j < C.layout.size(); ++j) {
+        int32_t v = C.layout[j];
+        bool ia = contains(A.layout, v), ib = contains(B.layout, v);
+        if (ia && ib) {
+            beta_a.push_back(ra++);
+            beta_b.push_back(rb++);
+            beta_c.push_back((int32_t)j);
+        } else if (ia) {
+            mu_a.push_back(ra++);
+            mu_c.push_back((int32_t)j);
+        } else {
+            nu_b.push_back(rb++);
+            nu_c.push_back((int32_t)j);
+        }
+    }
+    g.nm = (int)mu_c.size();
+    g.nn = (int)nu_c.size();
+    g.nb = (int)beta_c.size();
+    const std::vector<int32_t> *lists[GR_N] = {&mu_a, &beta_a, &nu_b, &beta_b, &mu_c, &nu_c, &beta_c};
+    for (int q = 0; q < GR_N; ++q)
+        if (!make_runs(*lists[q], g.run[q], &g.nrun[q], WMC_GEMM_RUNS)) return false;
+    return (int32_t)A.layout.size() == g.nk + g.nb + g.nm && (int32_t)B.layout.size() == g.nk + g.nb + g.nn;
 }
 
 // Post-order-compatible launch schedule: all ready small nodes go in one
@@ -765,6 +831,21 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     }
     P.leaf_work = lw;
     P.launches[0].work = lw;
+    P.gemms.clear();
+    for (size_t k = 1; k < P.launches.size(); ++k) {
+        Launch &L = P.launches[k];
+        if (L.count != 1) continue;
+        int32_t id = P.node_order[(size_t)L.first];
+        if (T[(size_t)id].cls != WMC_CLASS_GEMM) continue;
+        GemmDesc g;
+        if (make_gemm(T, id, sl, g)) {
+            L.type = LAUNCH_GEMM;
+            L.pad = (int32_t)P.gemms.size();
+            P.gemms.push_back(g);
+        } else {
+            T[(size_t)id].cls = WMC_CLASS_STREAM;
+        }
+    }
     std::vector<int32_t> mark((size_t)n + 1, 0);
     int32_t stamp = 0;
     for (size_t k = 1; k < P.launches.size(); ++k) {
@@ -828,12 +909,16 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     off += align_up(sizeof(LeafDesc) * (uint64_t)std::max<size_t>(P.leaves.size(), 1), 256);
     P.off_node = off;
     off += align_up(sizeof(NodeDesc) * (uint64_t)std::max<size_t>(P.nodes.size(), 1), 256);
+    P.off_gemm = off;
+    off += align_up(sizeof(GemmDesc) * (uint64_t)std::max<size_t>(P.gemms.size(), 1), 256);
     P.off_arena = off;
     P.desc_bytes = P.off_arena - P.off_leaf;
     P.desc_image.assign(P.desc_bytes, 0);
     if (!P.leaves.empty()) std::memcpy(P.desc_image.data(), P.leaves.data(), sizeof(LeafDesc) * P.leaves.size());
     if (!P.nodes.empty())
         std::memcpy(P.desc_image.data() + (P.off_node - P.off_leaf), P.nodes.data(), sizeof(NodeDesc) * P.nodes.size());
+    if (!P.gemms.empty())
+        std::memcpy(P.desc_image.data() + (P.off_gemm - P.off_leaf), P.gemms.data(), sizeof(GemmDesc) * P.gemms.size());
     P.workspace_bytes = P.off_arena + align_up(P.arena_bytes, 256);
 
     // ---- statistics
@@ -962,15 +1047,16 @@ extern "C" wmc_status wmc_plan_node(const wmc_plan_t *plan, int64_t i, int64_t *
 }
 
 // Raw descriptor image, for tools and tests that replay the launch list:
-// [LeafDesc x n_leaves][NodeDesc x n_nodes][Launch x n_launches].
+// [LeafDesc x n_leaves][NodeDesc x n_nodes][Launch x n_launches][GemmDesc x n_gemms].
 // info[] = {n_leaves, n_nodes, n_launches, arena_elems, root, root_off,
-//           n_tensors, elem_bytes, sizeof LeafDesc, sizeof NodeDesc, sizeof Launch}.
+//           n_tensors, elem_bytes, sizeof LeafDesc, sizeof NodeDesc, sizeof Launch,
+//           n_gemms, sizeof GemmDesc}.
 extern "C" wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t dst_bytes, uint64_t *needed,
                                      int64_t *info) {
     if (!plan) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan_image: plan is NULL");
     const wmc_plan_t &P = *plan;
     uint64_t need = sizeof(LeafDesc) * P.leaves.size() + sizeof(NodeDesc) * P.nodes.size() +
-                    sizeof(Launch) * P.launches.size();
+                    sizeof(Launch) * P.launches.size() + sizeof(GemmDesc) * P.gemms.size();
     if (needed) *needed = need;
     if (info) {
         info[0] = (int64_t)P.leaves.size();
@@ -984,6 +1070,8 @@ extern "C" wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t
         info[8] = (int64_t)sizeof(LeafDesc);
         info[9] = (int64_t)sizeof(NodeDesc);
         info[10] = (int64_t)sizeof(Launch);
+        info[11] = (int64_t)P.gemms.size();
+        info[12] = (int64_t)sizeof(GemmDesc);
     }
     if (!dst) return WMC_OK;
     if (dst_bytes < need) WMC_FAIL(WMC_ERR_OUT_OF_MEMORY, "wmc_plan_image: buffer too small");
@@ -993,6 +1081,8 @@ extern "C" wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t
     if (!P.nodes.empty()) std::memcpy(p, P.nodes.data(), sizeof(NodeDesc) * P.nodes.size());
     p += sizeof(NodeDesc) * P.nodes.size();
     if (!P.launches.empty()) std::memcpy(p, P.launches.data(), sizeof(Launch) * P.launches.size());
+    p += sizeof(Launch) * P.launches.size();
+    if (!P.gemms.empty()) std::memcpy(p, P.gemms.data(), sizeof(GemmDesc) * P.gemms.size());
     return WMC_OK;
 }
 

@@ -43,11 +43,11 @@ struct TNode {
     int32_t cls = 0;              // internal: node class
 };
 
-enum { LAUNCH_LEAF = 0, LAUNCH_NODES = 1 };
+enum { LAUNCH_LEAF = 0, LAUNCH_NODES = 1, LAUNCH_GEMM = 2 };
 
 struct Launch {
     int32_t type;
-    int32_t first, count;   // descriptor range (node launches)
+    int32_t first, count;   // descriptor range (node launches); GEMM: first = GemmDesc index
     int32_t pad;
     int64_t work;           // padded work items
 };
@@ -66,9 +66,10 @@ struct wmc_plan_t {
     std::vector<Launch> launches;
     std::vector<LeafDesc> leaves;
     std::vector<NodeDesc> nodes;
+    std::vector<GemmDesc> gemms;
     int64_t leaf_work = 0;
     // workspace layout (bytes)
-    uint64_t off_acc = 0, off_w = 0, off_meta = 0, off_leaf = 0, off_node = 0, off_arena = 0;
+    uint64_t off_acc = 0, off_w = 0, off_meta = 0, off_leaf = 0, off_node = 0, off_gemm = 0, off_arena = 0;
     uint64_t desc_bytes = 0;          // contiguous [off_leaf, off_arena) image
     std::vector<uint8_t> desc_image;
     uint64_t arena_bytes = 0, workspace_bytes = 0;

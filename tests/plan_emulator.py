@@ -24,6 +24,12 @@ NODE = np.dtype({"names": ["a", "b", "c", "work_begin", "ta", "tb", "tc", "rc", 
                  "offsets": [0, 8, 16, 24, 32, 36, 40, 44, 48, 52, 56, 60, 64, 124],
                  "itemsize": 200})
 LAUNCH = np.dtype([("type", "<i4"), ("first", "<i4"), ("count", "<i4"), ("pad", "<i4"), ("work", "<i8")])
+GEMM = np.dtype({"names": ["a", "b", "c", "ta", "tb", "tc", "nk", "nm", "nn", "nb", "nrun", "run"],
+                 "formats": ["<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", ("<i4", (7,)),
+                             ("u1", (7, 12, 3))],
+                 "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 48, 52, 80],
+                 "itemsize": 336})
+GR_MU_A, GR_BETA_A, GR_NU_B, GR_BETA_B, GR_MU_C, GR_NU_C, GR_BETA_C = range(7)
 
 
 def parse(plan):
@@ -31,11 +37,14 @@ def parse(plan):
     assert info["leaf_desc_bytes"] == LEAF.itemsize
     assert info["node_desc_bytes"] == NODE.itemsize
     assert info["launch_bytes"] == LAUNCH.itemsize
-    nl, nn, nla = info["n_leaves"], info["n_nodes"], info["n_launches"]
+    assert info["gemm_desc_bytes"] == GEMM.itemsize
+    nl, nn, nla, ng = info["n_leaves"], info["n_nodes"], info["n_launches"], info["n_gemms"]
     leaves = np.frombuffer(img, LEAF, count=nl, offset=0)
     nodes = np.frombuffer(img, NODE, count=nn, offset=nl * LEAF.itemsize)
-    launches = np.frombuffer(img, LAUNCH, count=nla, offset=nl * LEAF.itemsize + nn * NODE.itemsize)
-    return leaves, nodes, launches, info
+    off = nl * LEAF.itemsize + nn * NODE.itemsize
+    launches = np.frombuffer(img, LAUNCH, count=nla, offset=off)
+    gemms = np.frombuffer(img, GEMM, count=ng, offset=off + nla * LAUNCH.itemsize)
+    return leaves, nodes, launches, gemms, info
 
 
 def _pext(r: np.ndarray, runs, nr: int) -> np.ndarray:
@@ -56,7 +65,7 @@ def emulate(plan, weights, store=np.float64, slices=None):
     """Contract ``plan`` on the CPU exactly as the kernels would.  Returns the
     exact rational sum over the requested slices (default: all) of the slice
     values as they would be produced, plus the list of per-slice values."""
-    leaves, nodes, launches, info = parse(plan)
+    leaves, nodes, launches, gemms, info = parse(plan)
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
     root = info["root"]
     if root < 0:
@@ -90,6 +99,32 @@ def emulate(plan, weights, store=np.float64, slices=None):
             maxv[int(d["tensor"])] = float(np.max(np.abs(s.astype(np.float64))))
         for L in launches[1:]:
             results = []
+            if int(L["type"]) == 2:
+                g = gemms[int(L["pad"])]
+                nk, nm, nn, nb = (int(g[k]) for k in ("nk", "nm", "nn", "nb"))
+                runs = lambda q: (g["run"][q], int(g["nrun"][q]))
+                mu = np.arange(1 << nm, dtype=np.uint64)
+                nu = np.arange(1 << nn, dtype=np.uint64)
+                sA, sB = _sexp(maxv[int(g["ta"])]), _sexp(maxv[int(g["tb"])])
+                outs = []
+                for beta in range(1 << nb):
+                    bt = np.array([beta], dtype=np.uint64)
+                    rows = (_pext(mu, *runs(GR_MU_A)) | _pext(bt, *runs(GR_BETA_A))) << np.uint64(nk)
+                    cols = (_pext(nu, *runs(GR_NU_B)) | _pext(bt, *runs(GR_BETA_B))) << np.uint64(nk)
+                    kk = np.arange(1 << nk, dtype=np.uint64)
+                    Am = arena[int(g["a"]) + (rows[:, None] + kk[None, :]).astype(np.int64)].astype(np.float64)
+                    Bm = arena[int(g["b"]) + (cols[:, None] + kk[None, :]).astype(np.int64)].astype(np.float64)
+                    Cm = np.ldexp(Am @ Bm.T, -(sA + sB)).astype(store)
+                    addr = (_pext(mu, *runs(GR_MU_C))[:, None] | _pext(nu, *runs(GR_NU_C))[None, :] |
+                            _pext(bt, *runs(GR_BETA_C)))
+                    outs.append((addr.astype(np.int64).ravel(), Cm.ravel()))
+                mx = 0.0
+                for addr, val in outs:
+                    arena[int(g["c"]) + addr] = val
+                    mx = max(mx, float(np.max(np.abs(val.astype(np.float64)))))
+                maxv[int(g["tc"])] = mx
+                ex[int(g["tc"])] = ex[int(g["ta"])] + ex[int(g["tb"])] + sA + sB
+                continue
             for d in nodes[int(L["first"]): int(L["first"]) + int(L["count"])]:
                 rc, nk = int(d["rc"]), int(d["nk"])
                 r = np.arange(1 << rc, dtype=np.uint64)

@@ -227,3 +227,16 @@ def test_grid_lattice_vs_golden(name, rows, block):
     v, p = run(f, kind="order", order=wl.row_major_order(rows, 24), block=block)
     ref = Fraction(float.fromhex(g["mantissa_hex"])) * Fraction(2) ** g["exp2"]
     assert rel(value_fraction(v), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("rows,cols", [(8, 16), (6, 18), (5, 20)])
+@pytest.mark.parametrize("block", [1, 3, 4, 6, 7])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_grid_blocks_vs_oracle(rows, cols, block, precision, tol):
+    """Blocked sweeps put matrix-shaped nodes on MFMA (FP64 or FP32)."""
+    f = wl.grid_cnf(rows, cols, 0.1, seed=2)
+    order = wl.row_major_order(rows, cols)
+    say(f"grid {rows}x{cols} block={block} {precision}")
+    v, p = run(f, kind="order", order=order, block=block, precision=precision)
+    m, e = oracle.bucket(f, order=order)
+    assert rel(value_fraction(v), Fraction(m) * Fraction(2) ** e) <= tol

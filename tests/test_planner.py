@@ -267,3 +267,21 @@ def test_grid24_sweep_plan_shape():
     s = p.stats()
     assert 24 <= s["max_rank"] <= 26
     assert s["class_hist"]["stream"] > 500
+
+
+@pytest.mark.parametrize("rows,cols,block", [(8, 16, 4), (8, 16, 6), (6, 18, 5), (5, 20, 7)])
+def test_emulated_matrix_nodes(rows, cols, block):
+    """Blocked sweeps create matrix-shaped nodes (the MFMA class); their
+    descriptors replayed on the CPU equal the oracle, in FP64 and FP32."""
+    f = wl.grid_cnf(rows, cols, 0.1, seed=2)
+    net = W.Network.from_formula(f)
+    order = wl.row_major_order(rows, cols)
+    m, e = oracle.bucket(f, order=order)
+    ref = Fraction(m) * Fraction(2) ** e
+    p = W.Plan(net, kind="order", order=order, block=block)
+    assert p.stats()["class_hist"]["gemm"] > 0
+    got, _ = emulate(p, f.weights)
+    assert rel_err(got, ref) < 1e-12
+    p32 = W.Plan(net, kind="order", order=order, block=block, precision="fp32")
+    got32, _ = emulate(p32, f.weights, store=np.float32)
+    assert rel_err(got32, ref) < 1e-5
