@@ -153,16 +153,18 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict_
 // ---------------------------------------------------------------------------
 // Matrix-shaped contractions on MFMA (16x16x4, FP64 or FP32).
 //
-// A workgroup of 4 waves owns 128 rows (beta fixed by blockIdx.y, mu from
-// blockIdx.x) and every column.  Each wave computes 32 rows x N columns as
-// 2 x NT tiles of 16x16.  For the 16x16x4 instruction lane l supplies row
-// (or column) l%16 and reduction slot l/16; here lane group g = l/16 walks a
-// contiguous range of S summed indices [g*S, g*S+S) over S instructions, so
-// a lane's A operand is S consecutive elements of one row, loaded straight
-// from HBM into registers.  A and B use the same permutation of the summed
-// index, so the product sums every (row, k, col) term exactly once.  B (the
-// small operand, columns contiguous in kappa) is staged in LDS per chunk of
-// KC summed indices.
+//   C[beta, mu, nu] = sum_k A[beta, mu, k] * B[beta, k, nu]
+//
+// The row operand A is stored [4 lowest mu bits | kappa | rest], so the 16
+// rows of a row tile are contiguous for each summed index k.  For the
+// 16x16x4 instruction lane l supplies row (or column) l%16 and reduction
+// slot l/16; at step s lane group g = l/16 takes summed index k = 4s + g, so
+// one load instruction of a wave reads A[tile][k = 4s..4s+3][16 rows]: 512
+// contiguous bytes (FP64).  A and B use the same k for a given (s, g), so
+// every (row, k, column) term is summed exactly once.  B, the small operand
+// (columns contiguous in kappa), is staged per chunk of KC summed indices in
+// LDS as [k][column].  A workgroup of 4 waves owns 8 row tiles (2 per wave)
+// of one beta and all N <= 128 columns.
 // ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -185,13 +187,16 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int out_row(int g, int v) { return 4 * g + v; }
 };
 
-#define GEMM_ROWS 128
+#define GEMM_TILES_PER_WAVE 2
+#define GEMM_TILES (4 * GEMM_TILES_PER_WAVE)
 #define GEMM_LDS_BYTES (48 * 1024)
 
+__host__ __device__ inline int gemm_ldn(int nn, int elem) { return (1 << nn) + (elem == 8 ? 2 : 4); }
+
 __host__ __device__ inline int gemm_kc(int nk, int nn, int elem) {
-    int K = 1 << nk, N = 1 << nn;
+    int K = 1 << nk;
     int kc = K < 64 ? K : 64;
-    while (kc > 4 && (long long)N * (kc + 4) * elem > GEMM_LDS_BYTES) kc >>= 1;
+    while (kc > 4 && (long long)kc * gemm_ldn(nn, elem) * elem > GEMM_LDS_BYTES) kc >>= 1;
     return kc;
 }
 
@@ -203,29 +208,31 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T 
     const GemmDesc &d = *G;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, l16 = lane & 15;
-    const unsigned long long M = 1ull << d.nm;
-    const int K = 1 << d.nk, N = 1 << d.nn;
-    const int KC = gemm_kc(d.nk, d.nn, (int)sizeof(T));
-    const int S = KC >= 4 ? KC / 4 : 1;
-    const int LDK = KC + (sizeof(T) == 8 ? 2 : 4);
+    const int nk = d.nk;
+    const int K = 1 << nk, N = 1 << d.nn;
+    const int KC = gemm_kc(nk, d.nn, (int)sizeof(T));
+    const int S = KC / 4;
+    const int LDN = gemm_ldn(d.nn, (int)sizeof(T));
+    const unsigned long long tiles = 1ull << (d.nm - 4);
     const unsigned long long beta = blockIdx.y;
     const int sA = scale_exp(meta[d.ta].maxbits);
     const int sB = scale_exp(meta[d.tb].maxbits);
     const unsigned long long rowBeta = pext_runs(beta, d.run[GR_BETA_A], d.nrun[GR_BETA_A]);
     const unsigned long long colBeta = pext_runs(beta, d.run[GR_BETA_B], d.nrun[GR_BETA_B]);
-    const unsigned long long m0 = (unsigned long long)blockIdx.x * GEMM_ROWS + (unsigned long long)wave * 32;
+    const unsigned long long t0 = ((unsigned long long)blockIdx.x * 4 + wave) * GEMM_TILES_PER_WAVE;
 
-    long long arow[2];
-    bool rv[2];
+    long long abase[GEMM_TILES_PER_WAVE];
+    bool tv[GEMM_TILES_PER_WAVE];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        unsigned long long m = m0 + rt * 16 + l16;
-        rv[rt] = m < M;
-        arow[rt] = d.a + (long long)((pext_runs(rv[rt] ? m : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << d.nk);
+    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+        unsigned long long t = t0 + rt;
+        tv[rt] = t < tiles;
+        abase[rt] = d.a + l16 +
+                    (long long)((pext_runs(tv[rt] ? t : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << (4 + nk));
     }
-    acc_t acc[2][NT];
+    acc_t acc[GEMM_TILES_PER_WAVE][NT];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
 
@@ -233,31 +240,25 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T 
         for (int idx = threadIdx.x; idx < N * KC; idx += 256) {
             int col = idx / KC, k = idx - col * KC;
             unsigned long long cb = pext_runs((unsigned long long)col, d.run[GR_NU_B], d.nrun[GR_NU_B]) | colBeta;
-            Bs[col * LDK + k] = arena[d.b + (long long)(cb << d.nk) + kc + k];
+            Bs[k * LDN + col] = arena[d.b + (long long)(cb << nk) + kc + k];
         }
+        T a[GEMM_TILES_PER_WAVE][16];
+#pragma unroll
+        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                a[rt][s] = (s < S && tv[rt]) ? arena[abase[rt] + 16 * (long long)(kc + 4 * s + g)] : (T)0;
         __syncthreads();
-        T a[2][16];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int s = 0; s < 16; ++s) {
+            if (s < S) {
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                int k = g * S + s;
-                a[rt][s] = (s < S && rv[rt] && k < KC) ? arena[arow[rt] + kc + k] : (T)0;
-            }
+                for (int ct = 0; ct < NT; ++ct) {
+                    const int col = ct * 16 + l16;
+                    T b = (col < N) ? Bs[(4 * s + g) * LDN + col] : (T)0;
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-            const int col = ct * 16 + l16;
-            T b[16];
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                int k = g * S + s;
-                b[s] = (s < S && col < N && k < KC) ? Bs[col * LDK + k] : (T)0;
-            }
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                if (s < S) {
-#pragma unroll
-                    for (int rt = 0; rt < 2; ++rt) acc[rt][ct] = Mfma<T>::step(a[rt][s], b[s], acc[rt][ct]);
+                    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
+                        acc[rt][ct] = Mfma<T>::step(a[rt][s], b, acc[rt][ct]);
                 }
             }
         }
@@ -266,37 +267,201 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T 
 
     const double scale = ldexp(1.0, -(sA + sB));
     const unsigned long long cBeta = pext_runs(beta, d.run[GR_BETA_C], d.nrun[GR_BETA_C]);
+    unsigned long long rowC[GEMM_TILES_PER_WAVE][4];
+#pragma unroll
+    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            unsigned long long m = ((t0 + rt) << 4) + Mfma<T>::out_row(g, v);
+            rowC[rt][v] = pext_runs(m, d.run[GR_MU_C], d.nrun[GR_MU_C]) | cBeta;
+        }
     double vmax = 0.0;
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
         const int col = ct * 16 + l16;
         if (col >= N) continue;
-        const unsigned long long cc = pext_runs((unsigned long long)col, d.run[GR_NU_C], d.nrun[GR_NU_C]) | cBeta;
+        const unsigned long long cc = pext_runs((unsigned long long)col, d.run[GR_NU_C], d.nrun[GR_NU_C]);
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+            if (!tv[rt]) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                unsigned long long m = m0 + rt * 16 + Mfma<T>::out_row(g, v);
-                if (m >= M) continue;
                 T sv = (T)((double)acc[rt][ct][v] * scale);
-                arena[d.c + (long long)(pext_runs(m, d.run[GR_MU_C], d.nrun[GR_MU_C]) | cc)] = sv;
+                arena[d.c + (long long)(rowC[rt][v] | cc)] = sv;
                 vmax = fmax(vmax, fabs((double)sv));
             }
+        }
     }
     publish_max(meta, d.tc, vmax);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
 }
 
+// Persistent form for the common case where all of B[beta] (K <= 64 summed
+// indices x N columns) fits in LDS: each workgroup stages B once, then walks
+// row-tile groups blockIdx.x, blockIdx.x + gridDim.x, ..., loading the next
+// group's A fragments into registers while the MFMAs of the current group run.
+template <typename T, int NT, int S>
+__global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, T *__restrict__ arena,
+                                                wmc_meta *meta) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    extern __shared__ char smem_raw[];
+    __shared__ GemmDesc sd;
+    T *Bs = (T *)smem_raw;
+    // the descriptor lives in LDS so that run-list reads never wait on the
+    // vector-memory counter that tracks the A prefetches
+    for (int i = threadIdx.x; i < (int)(sizeof(GemmDesc) / sizeof(int)); i += 256)
+        ((int *)&sd)[i] = ((const int *)G)[i];
+    __syncthreads();
+    const GemmDesc &d = sd;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, l16 = lane & 15;
+    constexpr int K = 4 * S;
+    const int nk = d.nk;
+    const int N = 1 << d.nn;
+    constexpr int LDN = NT * 16 + (sizeof(T) == 8 ? 2 : 4);
+    const unsigned long long tiles = 1ull << (d.nm - 4);
+    const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;
+    const unsigned long long beta = blockIdx.y;
+    const long long a0 = d.a, c0 = d.c;
+    const int sA = scale_exp(meta[d.ta].maxbits);
+    const int sB = scale_exp(meta[d.tb].maxbits);
+    const unsigned long long rowBeta = pext_runs(beta, d.run[GR_BETA_A], d.nrun[GR_BETA_A]);
+    const unsigned long long colBeta = pext_runs(beta, d.run[GR_BETA_B], d.nrun[GR_BETA_B]);
+    const unsigned long long cBeta = pext_runs(beta, d.run[GR_BETA_C], d.nrun[GR_BETA_C]);
+    const double scale = ldexp(1.0, -(sA + sB));
+
+    // B[beta] as [k][column], columns N..16*NT-1 zero
+    for (int idx = threadIdx.x; idx < NT * 16 * K; idx += 256) {
+        int col = idx / K, k = idx - col * K;
+        T v = (T)0;
+        if (col < N) {
+            unsigned long long cb = pext_runs((unsigned long long)col, d.run[GR_NU_B], d.nrun[GR_NU_B]) | colBeta;
+            v = arena[d.b + (long long)(cb << nk) + k];
+        }
+        Bs[k * LDN + col] = v;
+    }
+    unsigned long long cols[NT];
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+        const int col = ct * 16 + l16;
+        cols[ct] = pext_runs((unsigned long long)(col < N ? col : 0), d.run[GR_NU_C], d.nrun[GR_NU_C]) | cBeta;
+    }
+    unsigned long long rlo[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        rlo[v] = pext_runs((unsigned long long)Mfma<T>::out_row(g, v), d.run[GR_MU_C], d.nrun[GR_MU_C]);
+
+    // A fragments: loads are unconditional (a row tile past the end reads
+    // tile 0 and is discarded) so the compiler can count them precisely
+    T an[GEMM_TILES_PER_WAVE][S];
+    bool okn[GEMM_TILES_PER_WAVE];
+    auto load = [&](unsigned long long grp) {
+#pragma unroll
+        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+            unsigned long long t = (grp * 4 + wave) * GEMM_TILES_PER_WAVE + rt;
+            okn[rt] = grp < groups && t < tiles;
+            long long base =
+                a0 + l16 + (long long)((pext_runs(okn[rt] ? t : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << (4 + nk));
+#pragma unroll
+            for (int s = 0; s < S; ++s) an[rt][s] = arena[base + 16 * (4 * s + g)];
+        }
+    };
+    load(blockIdx.x);
+    __syncthreads();
+    double vmax = 0.0;
+    for (unsigned long long grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        T a[GEMM_TILES_PER_WAVE][S];
+        bool ok[GEMM_TILES_PER_WAVE];
+#pragma unroll
+        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+            ok[rt] = okn[rt];
+#pragma unroll
+            for (int s = 0; s < S; ++s) a[rt][s] = an[rt][s];
+        }
+        unsigned long long thi[GEMM_TILES_PER_WAVE];
+#pragma unroll
+        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+            unsigned long long t = (grp * 4 + wave) * GEMM_TILES_PER_WAVE + rt;
+            thi[rt] = pext_runs(ok[rt] ? (t << 4) : 0, d.run[GR_MU_C], d.nrun[GR_MU_C]);
+        }
+        load(grp + gridDim.x);
+        acc_t acc[GEMM_TILES_PER_WAVE][NT];
+#pragma unroll
+        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                T b = Bs[(4 * s + g) * LDN + ct * 16 + l16];
+#pragma unroll
+                for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
+                    acc[rt][ct] = Mfma<T>::step(a[rt][s], b, acc[rt][ct]);
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+            if (!ok[rt]) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const unsigned long long rc = thi[rt] | rlo[v];
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    if (NT == 1 && l16 >= N) continue;
+                    T sv = (T)((double)acc[rt][ct][v] * scale);
+                    arena[c0 + (long long)(rc | cols[ct])] = sv;
+                    vmax = fmax(vmax, fabs((double)sv));
+                }
+            }
+        }
+    }
+    publish_max(meta, d.tc, vmax);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
+}
+
+// LDS a workgroup may use for B, from the device's per-block limit (kept to
+// at most 96 KiB so that two workgroups share a CU).
+static int lds_budget() {
+    static int budget[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return GEMM_LDS_BYTES;
+    if (!budget[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
+        budget[dev] = v >= 96 * 1024 ? 96 * 1024 : GEMM_LDS_BYTES;
+    }
+    return budget[dev];
+}
+
 template <typename T>
 static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_meta *meta, hipStream_t st) {
-    const int N = 1 << hd.nn;
-    const int KC = gemm_kc(hd.nk, hd.nn, (int)sizeof(T));
-    const int LDK = KC + (sizeof(T) == 8 ? 2 : 4);
-    const size_t smem = (size_t)N * LDK * sizeof(T);
-    const unsigned long long M = 1ull << hd.nm;
-    dim3 grid((unsigned)((M + GEMM_ROWS - 1) / GEMM_ROWS), 1u << hd.nb);
+    const int N = 1 << hd.nn, K = 1 << hd.nk;
     const int NT = (N + 15) / 16;
+    const unsigned long long tiles = 1ull << (hd.nm - 4);
+    const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;
+    const size_t full = (size_t)K * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
+    const size_t padded = (size_t)K * (NT * 16 + (sizeof(T) == 8 ? 2 : 4)) * sizeof(T);
+    if (K >= 4 && K <= 64 && padded <= (size_t)lds_budget()) {
+        const unsigned long long per_beta = (512ull + (1ull << hd.nb) - 1) >> hd.nb;
+        dim3 grid((unsigned)(groups < per_beta ? groups : (per_beta ? per_beta : 1)), 1u << hd.nb);
+        const int NTp = NT <= 1 ? 1 : NT <= 2 ? 2 : NT <= 4 ? 4 : 8;
+#define WMC_GP(NTV, SV)                                                                                   \
+    if (NTp == NTV && K / 4 == SV) {                                                                       \
+        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV>), grid, dim3(256), padded, st, dd, arena, meta);       \
+        return;                                                                                        \
+    }
+#define WMC_GP_S(NTV) WMC_GP(NTV, 1) WMC_GP(NTV, 2) WMC_GP(NTV, 4) WMC_GP(NTV, 8) WMC_GP(NTV, 16)
+        WMC_GP_S(1) WMC_GP_S(2) WMC_GP_S(4) WMC_GP_S(8)
+#undef WMC_GP_S
+#undef WMC_GP
+    }
+    (void)full;
+    const int KC = gemm_kc(hd.nk, hd.nn, (int)sizeof(T));
+    const size_t smem = (size_t)KC * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
+    dim3 grid((unsigned)groups, 1u << hd.nb);
     if (NT <= 1) hipLaunchKernelGGL((k_gemm<T, 1>), grid, dim3(256), smem, st, dd, arena, meta);
     else if (NT <= 2) hipLaunchKernelGGL((k_gemm<T, 2>), grid, dim3(256), smem, st, dd, arena, meta);
     else if (NT <= 4) hipLaunchKernelGGL((k_gemm<T, 4>), grid, dim3(256), smem, st, dd, arena, meta);

@@ -515,11 +515,14 @@ static bool make_runs(const std::vector<int32_t> &dst, unsigned char (*runs)[3],
     return true;
 }
 
-// Matrix form of node id for the MFMA kernel; false if a run list overflows.
-static bool make_gemm(const std::vector<TNode> &T, int32_t id, const std::vector<uint8_t> &sl, GemmDesc &g) {
+// Matrix form of node id for the MFMA kernel, read off the layouts: the row
+// operand A is stored [4 lowest mu variables | kappa | rest in C order] and
+// the column operand B [kappa | rest in C order].  False if the shapes do not
+// match that form or a run list overflows.
+static bool make_gemm(const std::vector<TNode> &T, int32_t id, int32_t xa, const std::vector<uint8_t> &sl,
+                      GemmDesc &g) {
     const TNode &C = T[(size_t)id];
-    int32_t xa = C.a, xb = C.b;
-    if (T[(size_t)xb].layout.size() > T[(size_t)xa].layout.size()) std::swap(xa, xb);
+    const int32_t xb = (xa == C.a) ? C.b : C.a;
     const TNode &A = T[(size_t)xa], &B = T[(size_t)xb];
     std::memset(&g, 0, sizeof g);
     g.a = A.off;
@@ -529,32 +532,48 @@ static bool make_gemm(const std::vector<TNode> &T, int32_t id, const std::vector
     g.tb = xb;
     g.tc = id;
     g.nk = skappa(C, sl);
-    auto contains = [](const std::vector<int32_t> &L, int32_t v) { return std::find(L.begin(), L.end(), v) != L.end(); };
-    // positions in C, and row ranks inside A and B (their C-variables follow C's order)
+    const int32_t nk = g.nk;
+    auto pos_in = [](const std::vector<int32_t> &L, int32_t v, size_t from) -> int32_t {
+        for (size_t q = from; q < L.size(); ++q)
+            if (L[q] == v) return (int32_t)(q - from);
+        return -1;
+    };
+    if ((int32_t)A.layout.size() < 4 + nk || (int32_t)B.layout.size() < nk) return false;
+    for (int32_t q = 0; q < nk; ++q)
+        if (A.layout[(size_t)(4 + q)] != B.layout[(size_t)q]) return false;
     std::vector<int32_t> mu_a, beta_a, nu_b, beta_b, mu_c, nu_c, beta_c;
-    int32_t ra = 0, rb = 0;
+    int32_t nmu = 0;
     for (size_t j = 0; j < C.layout.size(); ++j) {
         int32_t v = C.layout[j];
-        bool ia = contains(A.layout, v), ib = contains(B.layout, v);
-        if (ia && ib) {
-            beta_a.push_back(ra++);
-            beta_b.push_back(rb++);
+        int32_t pa = pos_in(A.layout, v, 0), pb = pos_in(B.layout, v, 0);
+        if (pa >= 0 && pb >= 0) {
+            if (pa < 4 + nk || pb < nk) return false;
+            beta_a.push_back(pa - 4 - nk);
+            beta_b.push_back(pb - nk);
             beta_c.push_back((int32_t)j);
-        } else if (ia) {
-            mu_a.push_back(ra++);
+        } else if (pa >= 0) {
+            if (nmu < 4) {
+                if (pa != nmu) return false;  // the 4 lowest mu variables sit at A's bits 0..3
+            } else {
+                if (pa < 4 + nk) return false;
+                mu_a.push_back(pa - 4 - nk);
+            }
+            ++nmu;
             mu_c.push_back((int32_t)j);
         } else {
-            nu_b.push_back(rb++);
+            if (pb < nk) return false;
+            nu_b.push_back(pb - nk);
             nu_c.push_back((int32_t)j);
         }
     }
     g.nm = (int)mu_c.size();
     g.nn = (int)nu_c.size();
     g.nb = (int)beta_c.size();
+    if (g.nm < 4) return false;
     const std::vector<int32_t> *lists[GR_N] = {&mu_a, &beta_a, &nu_b, &beta_b, &mu_c, &nu_c, &beta_c};
     for (int q = 0; q < GR_N; ++q)
         if (!make_runs(*lists[q], g.run[q], &g.nrun[q], WMC_GEMM_RUNS)) return false;
-    return (int32_t)A.layout.size() == g.nk + g.nb + g.nm && (int32_t)B.layout.size() == g.nk + g.nb + g.nn;
+    return (int32_t)A.layout.size() == nk + g.nb + g.nm && (int32_t)B.layout.size() == nk + g.nb + g.nn;
 }
 
 // Post-order-compatible launch schedule: all ready small nodes go in one
@@ -706,8 +725,12 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     std::vector<int32_t> sbit((size_t)n + 1, -1);
     for (size_t i = 0; i < P.sliced.size(); ++i) sbit[(size_t)P.sliced[i]] = (int32_t)i;
 
-    // ---- layouts, top-down: an operand stores [kappa | its variables in the
-    // order of the node's output]; the root is a scalar
+    // ---- layouts, top-down.  An operand normally stores [kappa | its
+    // variables in the order of the node's output]; the row operand of a
+    // matrix-class node stores [its 4 lowest mu variables | kappa | rest], so
+    // that 16 rows of one summed index are contiguous.  The root is a scalar.
+    std::vector<int32_t> cls = classes_of(T, sl);
+    std::vector<int32_t> gemm_a(NT, -1);
     if (P.root >= 0) {
         T[(size_t)P.root].layout.clear();
         for (int32_t v : T[(size_t)P.root].vars)
@@ -723,23 +746,57 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
             std::vector<int32_t> kap;
             for (int32_t v : C.kappa)
                 if (!sl[(size_t)v]) kap.push_back(v);
-            for (int32_t child : {C.a, C.b}) {
+            auto plain = [&](int32_t child) {
                 TNode &X = T[(size_t)child];
                 ++stamp;
                 for (int32_t v : X.vars) mark[(size_t)v] = stamp;
                 X.layout = kap;
                 for (int32_t v : C.layout)
                     if (mark[(size_t)v] == stamp) X.layout.push_back(v);
-                if ((int32_t)X.layout.size() != srank(X, sl)) {
-                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: internal layout mismatch at tensor %d", child);
+            };
+            bool done = false;
+            if (cls[(size_t)q] == WMC_CLASS_GEMM) {
+                int32_t xa = C.a, xb = C.b;
+                if (srank(T[(size_t)xb], sl) > srank(T[(size_t)xa], sl)) std::swap(xa, xb);
+                plain(xb);
+                TNode &A = T[(size_t)xa];
+                ++stamp;
+                for (int32_t v : A.vars) mark[(size_t)v] = stamp;
+                const int32_t sB = stamp;
+                (void)sB;
+                std::vector<int32_t> lo, rest;
+                std::vector<uint8_t> inB((size_t)n + 1, 0);
+                for (int32_t v : T[(size_t)xb].vars) inB[(size_t)v] = 1;
+                for (int32_t v : C.layout) {
+                    if (mark[(size_t)v] != stamp) continue;
+                    if (!inB[(size_t)v] && lo.size() < 4) lo.push_back(v);
+                    else rest.push_back(v);
                 }
+                if (lo.size() == 4) {
+                    A.layout = lo;
+                    A.layout.insert(A.layout.end(), kap.begin(), kap.end());
+                    A.layout.insert(A.layout.end(), rest.begin(), rest.end());
+                    GemmDesc probe;
+                    if (make_gemm(T, q, xa, sl, probe)) {
+                        gemm_a[(size_t)q] = xa;
+                        done = true;
+                    }
+                }
+                if (!done) cls[(size_t)q] = WMC_CLASS_STREAM;
+            }
+            if (!done) {
+                plain(C.a);
+                plain(C.b);
+            }
+            for (int32_t child : {C.a, C.b}) {
+                if ((int32_t)T[(size_t)child].layout.size() != srank(T[(size_t)child], sl))
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: internal layout mismatch at tensor %d", child);
                 stack.push_back(child);
             }
         }
     }
 
-    // ---- classes and schedule
-    std::vector<int32_t> cls = classes_of(T, sl);
+    // ---- schedule
     Schedule S = make_schedule(T, cls);
     P.node_order = S.order;
     P.launches.clear();
@@ -838,13 +895,11 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
         int32_t id = P.node_order[(size_t)L.first];
         if (T[(size_t)id].cls != WMC_CLASS_GEMM) continue;
         GemmDesc g;
-        if (make_gemm(T, id, sl, g)) {
-            L.type = LAUNCH_GEMM;
-            L.pad = (int32_t)P.gemms.size();
-            P.gemms.push_back(g);
-        } else {
-            T[(size_t)id].cls = WMC_CLASS_STREAM;
-        }
+        if (!make_gemm(T, id, gemm_a[(size_t)id], sl, g))
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: internal matrix descriptor mismatch at node %d", id);
+        L.type = LAUNCH_GEMM;
+        L.pad = (int32_t)P.gemms.size();
+        P.gemms.push_back(g);
     }
     std::vector<int32_t> mark((size_t)n + 1, 0);
     int32_t stamp = 0;

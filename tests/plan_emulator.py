@@ -109,10 +109,12 @@ def emulate(plan, weights, store=np.float64, slices=None):
                 outs = []
                 for beta in range(1 << nb):
                     bt = np.array([beta], dtype=np.uint64)
-                    rows = (_pext(mu, *runs(GR_MU_A)) | _pext(bt, *runs(GR_BETA_A))) << np.uint64(nk)
+                    # A is stored [4 lowest mu bits | kappa | rest]
+                    rows = (mu & np.uint64(15)) | \
+                        ((_pext(mu >> np.uint64(4), *runs(GR_MU_A)) | _pext(bt, *runs(GR_BETA_A))) << np.uint64(4 + nk))
                     cols = (_pext(nu, *runs(GR_NU_B)) | _pext(bt, *runs(GR_BETA_B))) << np.uint64(nk)
                     kk = np.arange(1 << nk, dtype=np.uint64)
-                    Am = arena[int(g["a"]) + (rows[:, None] + kk[None, :]).astype(np.int64)].astype(np.float64)
+                    Am = arena[int(g["a"]) + (rows[:, None] + (kk[None, :] << np.uint64(4))).astype(np.int64)].astype(np.float64)
                     Bm = arena[int(g["b"]) + (cols[:, None] + kk[None, :]).astype(np.int64)].astype(np.float64)
                     Cm = np.ldexp(Am @ Bm.T, -(sA + sB)).astype(store)
                     addr = (_pext(mu, *runs(GR_MU_C))[:, None] | _pext(nu, *runs(GR_NU_C))[None, :] |
