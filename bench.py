@@ -40,6 +40,11 @@ def workload(name: str):
     if name == "grid12":
         f = wl.grid_cnf(12, 24, 0.10, seed=1)
         return f, dict(kind="order", order=wl.row_major_order(12, 24)), "grid CNF 12x24, seed 1, row-major sweep"
+    if name == "banded300":
+        f = wl.banded_3cnf(300, 1050, 37, seed=0)
+        return f, dict(kind="minfill", seed=0, rank_cap=27), \
+            "banded random 3-CNF, 300 vars, 1050 clauses (ratio 3.5), window 37, w~U(0.05,0.95), seed 0; " \
+            "seeded min-fill tree (max rank 30) sliced to rank 27"
     if name == "config1":
         f = wl.random_kcnf(20, 85, seed=2)
         return f, dict(kind="minfill", seed=0), "random 3-CNF 20 vars 85 clauses, seed 2, min-fill tree"
@@ -107,6 +112,9 @@ def main():
     ap.add_argument("--block", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="a few solves, no timing output (for rocprofv3)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="with --profile-only: also run a plain device-to-device copy of MIB MiB "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the slice loop would be split across "
@@ -121,7 +129,8 @@ def main():
     f, pkw, desc = workload(args.workload)
     net = W.Network.from_formula(f)
     t0 = time.perf_counter()
-    plan = W.Plan(net, precision=args.precision, block=args.block, **pkw)
+    block = args.block if pkw.get("kind") == "order" else 1
+    plan = W.Plan(net, precision=args.precision, block=block, **pkw)
     plan_s = time.perf_counter() - t0
     st = plan.stats()
     ws = W.workspace(plan)
@@ -131,6 +140,13 @@ def main():
         for _ in range(max(args.steps, 1)):
             v = W.wmc_contract(plan, None, ws, stream)
         torch.cuda.synchronize()
+        if args.copy_calibration:
+            n = args.copy_calibration * (1 << 20) // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            print(f"copy calibration: {n * 8} bytes read and written", flush=True)
         print(f"profile-only: {args.steps} solves, W = {v.mantissa} * 2^{v.exp2}", flush=True)
         return
 
@@ -167,7 +183,7 @@ def main():
     ach_tf = d["flops"] / (d["ms"] * 1e-3) / 1e12
     peak_tf = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
     bound = "hbm" if ach_gbs / HBM_PEAK_GBS >= ach_tf / peak_tf else "mfma"
-    traffic = traffic_for(args.workload, args.precision, args.block)
+    traffic = traffic_for(args.workload, args.precision, block)
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -196,7 +212,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32 storage, f64 accumulate",
         "data": "synthetic",
-        "config": {"workload": desc, "precision": args.precision, "block": args.block,
+        "config": {"workload": desc, "precision": args.precision, "block": block,
                    "max_rank": st["max_rank"], "n_nodes": st["n_nodes"], "n_slices": n_slices,
                    "class_hist": st["class_hist"], "plan_seconds": round(plan_s, 3)},
         "contraction_tflops": round(total_flops / (ms_step * 1e-3) / 1e12, 3),
@@ -205,7 +221,8 @@ def main():
         "roofline": roof,
     }
     gpath = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
-    gname = {"grid24": "grid24x24_t0.10_s0", "grid12": "grid12x24_t0.10_s1"}.get(args.workload)
+    gname = {"grid24": "grid24x24_t0.10_s0", "grid12": "grid12x24_t0.10_s1",
+             "banded300": "banded300_m1050_W37_s0"}.get(args.workload)
     if gname and os.path.exists(gpath):
         with open(gpath) as fh:
             g = json.load(fh).get(gname)

@@ -468,6 +468,183 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
     else hipLaunchKernelGGL((k_gemm<T, 8>), grid, dim3(256), smem, st, dd, arena, meta);
 }
 
+// ---------------------------------------------------------------------------
+// Streaming contraction for one big node with a small summed dimension
+// (K = 2^nk <= 8): Hadamard scaling, a single summed variable, outer
+// products.  HBM-bound.  The operands' storage orders follow C's, so the
+// address of A for output r is r with the bits A lacks (C's "holes" for A)
+// removed, times K; B's is the few bits of r that B owns, gathered, times K.
+// Both bit lists arrive by value in the kernel arguments (scalar registers).
+// Every thread produces 4 consecutive outputs (one 32-byte FP64 / 16-byte
+// FP32 store); when C's two lowest bits belong to A the 4 rows of A are one
+// contiguous run of 4K elements, loaded with 16-byte vector loads.  B is
+// staged in LDS (scaled by its power of two) when it has at most 2^12
+// entries.
+// ---------------------------------------------------------------------------
+#define STREAM_B_LDS 4096
+#define STREAM_MAX_HOLES 8
+#define STREAM_MAX_BBITS 14
+
+struct StreamArgs {
+    long long a, b, c;
+    int ta, tb, tc;
+    int rc;
+    int nhole;                      // C bit positions not in A, ascending
+    int hole[STREAM_MAX_HOLES];
+    int nbbit;                      // C bit positions owned by B, ascending
+    int bbit[STREAM_MAX_BBITS];
+    int rb;                         // storage rank of B
+    int b_lds;
+    int low_contig;                 // C bits 0 and 1 both belong to A
+};
+
+template <typename T> struct Vec4;
+template <> struct Vec4<double> {
+    static __device__ __forceinline__ void store(double *p, double a, double b, double c, double d) {
+        double2 *q = (double2 *)p;
+        q[0] = make_double2(a, b);
+        q[1] = make_double2(c, d);
+    }
+};
+template <> struct Vec4<float> {
+    static __device__ __forceinline__ void store(float *p, double a, double b, double c, double d) {
+        *(float4 *)p = make_float4((float)a, (float)b, (float)c, (float)d);
+    }
+};
+
+__device__ __forceinline__ unsigned long long drop_holes(unsigned long long r, const StreamArgs &s) {
+#pragma unroll
+    for (int i = STREAM_MAX_HOLES - 1; i >= 0; --i) {
+        if (i < s.nhole) {
+            const int h = s.hole[i];
+            r = ((r >> (h + 1)) << h) | (r & ((1ull << h) - 1ull));
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ unsigned long long gather_bits(unsigned long long r, const StreamArgs &s) {
+    unsigned long long out = 0;
+#pragma unroll
+    for (int i = 0; i < STREAM_MAX_BBITS; ++i)
+        if (i < s.nbbit) out |= ((r >> s.bbit[i]) & 1ull) << i;
+    return out;
+}
+
+template <typename T, int NK>
+__global__ void __launch_bounds__(256) k_stream(const StreamArgs args, T *__restrict__ arena, wmc_meta *meta) {
+    __shared__ double Bs[STREAM_B_LDS];
+    constexpr int K = 1 << NK;
+    const int sA = scale_exp(meta[args.ta].maxbits);
+    const int sB = scale_exp(meta[args.tb].maxbits);
+    const double scaleB = ldexp(1.0, -sB), scaleA = ldexp(1.0, -sA);
+    const T *__restrict__ A = arena + args.a;
+    const T *__restrict__ B = arena + args.b;
+    T *__restrict__ C = arena + args.c;
+    if (args.b_lds) {
+        for (int i = threadIdx.x; i < (1 << args.rb); i += 256) Bs[i] = (double)B[i] * scaleB;
+        __syncthreads();
+    }
+    const unsigned long long quads = (1ull << args.rc) >> 2;
+    double vmax = 0.0;
+    for (unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; q < quads;
+         q += (unsigned long long)gridDim.x * blockDim.x) {
+        double av[4][K];
+        if (args.low_contig) {
+            const unsigned long long pa = drop_holes(q << 2, args) << NK;
+            const T *p = A + pa;
+            if (sizeof(T) == 8) {
+#pragma unroll
+                for (int i = 0; i < 2 * K; ++i) {
+                    double2 v = ((const double2 *)p)[i];
+                    av[(2 * i) / K][(2 * i) % K] = v.x;
+                    av[(2 * i + 1) / K][(2 * i + 1) % K] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    float4 v = ((const float4 *)p)[i];
+                    av[(4 * i) / K][(4 * i) % K] = v.x;
+                    av[(4 * i + 1) / K][(4 * i + 1) % K] = v.y;
+                    av[(4 * i + 2) / K][(4 * i + 2) % K] = v.z;
+                    av[(4 * i + 3) / K][(4 * i + 3) % K] = v.w;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const unsigned long long pa = drop_holes((q << 2) | (unsigned long long)e, args) << NK;
+#pragma unroll
+                for (int j = 0; j < K; ++j) av[e][j] = (double)A[pa + j];
+            }
+        }
+        double o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const unsigned long long pb = gather_bits((q << 2) | (unsigned long long)e, args) << NK;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const double bv = args.b_lds ? Bs[pb + j] : (double)B[pb + j] * scaleB;
+                acc = fma(av[e][j], bv, acc);
+            }
+            o[e] = acc * scaleA;
+        }
+        Vec4<T>::store(C + (q << 2), o[0], o[1], o[2], o[3]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs((double)(T)o[e]));
+    }
+    publish_max(meta, args.tc, vmax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
+}
+
+// Streaming arguments for a single-node launch, if the node fits the kernel.
+static bool stream_args(const NodeDesc &d, StreamArgs *a) {
+    if (d.rc < 2 || d.nk > 3) return false;
+    std::memset(a, 0, sizeof *a);
+    a->a = d.a;
+    a->b = d.b;
+    a->c = d.c;
+    a->ta = d.ta;
+    a->tb = d.tb;
+    a->tc = d.tc;
+    a->rc = d.rc;
+    std::vector<int> inA((size_t)d.rc, 0);
+    for (int q = 0; q < d.nra; ++q)
+        for (int j = 0; j < d.ra[q][1]; ++j) inA[(size_t)(d.ra[q][0] + j)] = 1;
+    for (int p = 0; p < d.rc; ++p)
+        if (!inA[(size_t)p]) {
+            if (a->nhole >= STREAM_MAX_HOLES) return false;
+            a->hole[a->nhole++] = p;
+        }
+    for (int q = 0; q < d.nrb; ++q)
+        for (int j = 0; j < d.rb[q][1]; ++j) {
+            if (a->nbbit >= STREAM_MAX_BBITS) return false;
+            a->bbit[a->nbbit++] = d.rb[q][0] + j;
+        }
+    // gather order must match the runs' destination order (ascending in C)
+    for (int i = 1; i < a->nbbit; ++i)
+        if (a->bbit[i] < a->bbit[i - 1]) return false;
+    a->rb = d.nk + a->nbbit;
+    a->b_lds = a->rb <= 12;
+    a->low_contig = inA[0] && inA[1];
+    return true;
+}
+
+template <typename T>
+static void launch_stream(const StreamArgs &sa, T *arena, wmc_meta *meta, hipStream_t st, int nk) {
+    const unsigned long long quads = (1ull << sa.rc) >> 2;
+    unsigned long long blocks = (quads + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    switch (nk) {
+    case 0: hipLaunchKernelGGL((k_stream<T, 0>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
+    case 1: hipLaunchKernelGGL((k_stream<T, 1>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
+    case 2: hipLaunchKernelGGL((k_stream<T, 2>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
+    default: hipLaunchKernelGGL((k_stream<T, 3>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
+    }
+}
+
 // Root of one slice: fold its value into the running sum (s + c) * 2^e.
 template <typename T>
 __global__ void k_finish(const T *__restrict__ arena, long long root_off, const wmc_meta *meta, int root,
@@ -592,8 +769,12 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
         if (tm) tm->mark();
         for (size_t k = 1; k < P.launches.size(); ++k) {
             const Launch &Ln = P.launches[k];
+            StreamArgs sa;
             if (Ln.type == LAUNCH_GEMM)
                 launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st);
+            else if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM &&
+                     stream_args(P.nodes[(size_t)Ln.first], &sa))
+                launch_stream<T>(sa, arena, meta, st, P.nodes[(size_t)Ln.first].nk);
             else
                 hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first,
                                    Ln.count, (long long)Ln.work, arena, meta);

@@ -32,6 +32,8 @@ def cases():
         "grid12x24_t0.10_s1": (lambda: wl.grid_cnf(12, 24, 0.10, seed=1),
                                lambda f: wl.row_major_order(12, 24),
                                "grid_cnf(12, 24, 0.10, seed=1), planted signs; row-major order"),
+        "banded300_m1050_W37_s0": (lambda: wl.banded_3cnf(300, 1050, 37, seed=0), None,
+                                   "banded_3cnf(300, 1050, window 37, seed=0); oracle min-fill order"),
     }
 
 
@@ -46,7 +48,7 @@ def main(names):
         f = make()
         order = order_of(f) if order_of else None
         t0 = time.time()
-        m, e, width = oracle.bucket(f, order=order, max_log2=30, return_width=True)
+        m, e, width = oracle.bucket(f, order=order, max_log2=31, return_width=True)
         dt = time.time() - t0
         data[name] = {"description": desc, "digest": f.digest(), "n": f.n, "m": f.m,
                       "mantissa_hex": float(m).hex(), "mantissa": m, "exp2": int(e), "width": int(width),

@@ -240,3 +240,34 @@ def test_grid_blocks_vs_oracle(rows, cols, block, precision, tol):
     v, p = run(f, kind="order", order=order, block=block, precision=precision)
     m, e = oracle.bucket(f, order=order)
     assert rel(value_fraction(v), Fraction(m) * Fraction(2) ** e) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_banded300_sliced_vs_golden(precision, tol):
+    """Banded random 3-CNF, 300 variables, ratio 3.5: seeded min-fill tree of
+    max storage rank 30 sliced to rank 27 (index slicing), against the
+    oracle's stored value."""
+    g = _golden("banded300_m1050_W37_s0")
+    f = wl.banded_3cnf(300, 1050, 37, seed=0)
+    assert f.digest() == g["digest"]
+    say(f"banded300 {precision}")
+    v, p = run(f, kind="minfill", seed=0, rank_cap=27, precision=precision)
+    st = p.stats()
+    assert st["max_rank"] <= 27 and st["max_rank_unsliced"] == 30 and st["n_slices"] >= 8
+    ref = Fraction(float.fromhex(g["mantissa_hex"])) * Fraction(2) ** g["exp2"]
+    assert rel(value_fraction(v), ref) <= tol
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_banded_medium_stream_shapes(seed):
+    """Banded 3-CNF of 120 variables (max rank ~20): min-fill trees with
+    several seeds and blocks exercise the streaming and matrix kernels on
+    irregular layouts; FP64 against the oracle."""
+    f = wl.banded_3cnf(120, 400, 24, seed=seed)
+    m, e = oracle.bucket(f)
+    ref = Fraction(m) * Fraction(2) ** e
+    for kw in (dict(seed=seed), dict(kind="order", order=oracle.minfill_order(f), block=3, rank_cap=24),
+               dict(kind="order", order=oracle.minfill_order(f), block=5, rank_cap=24)):
+        say(f"banded120 seed={seed} {kw.get('block', 1)}")
+        v, _ = run(f, **kw)
+        assert rel(value_fraction(v), ref) <= 1e-12
