@@ -34,7 +34,7 @@ def workload(name: str):
     """(formula, plan kwargs, description) for a named workload."""
     if name == "grid24":
         f = wl.grid_cnf(24, 24, 0.10, seed=0)
-        return f, dict(kind="order", order=wl.row_major_order(24, 24)), \
+        return f, dict(kind="order", order=wl.row_major_order(24, 24), block=5), \
             "grid CNF 24x24 lattice (576 vars, 2 planted-sign binary clauses per edge + 110 local ternary), " \
             "w~U(0.1,0.9), seed 0, row-major sweep tree"
     if name == "grid12":
@@ -42,7 +42,7 @@ def workload(name: str):
         return f, dict(kind="order", order=wl.row_major_order(12, 24)), "grid CNF 12x24, seed 1, row-major sweep"
     if name == "banded300":
         f = wl.banded_3cnf(300, 1050, 37, seed=0)
-        return f, dict(kind="minfill", seed=0, rank_cap=27), \
+        return f, dict(kind="minfill", seed=0, rank_cap=27, block=3), \
             "banded random 3-CNF, 300 vars, 1050 clauses (ratio 3.5), window 37, w~U(0.05,0.95), seed 0; " \
             "seeded min-fill tree (max rank 30) sliced to rank 27"
     if name == "config1":
@@ -102,6 +102,49 @@ def cpu_baseline(name: str):
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample}
 
 
+def bench_batch(args, W, torch):
+    """512 small banded 3-CNF instances (n 30-150, ratio 3.0-4.2, window 20)
+    contracted as one batch (merged launches, HIP graph replay)."""
+    n_inst = 512
+    fs = [wl.batch_instance(i) for i in range(n_inst)]
+    t0 = time.perf_counter()
+    plans = [W.Plan(W.Network.from_formula(f), seed=i, precision=args.precision) for i, f in enumerate(fs)]
+    b = W.Batch(plans)
+    plan_s = time.perf_counter() - t0
+    ws = b.workspace()
+    stream = torch.cuda.current_stream()
+    flags = W.BATCH_GRAPH
+    vals = b.contract(ws=ws, stream=stream, flags=flags)
+    flags |= W.BATCH_RESIDENT
+    for _ in range(args.warmup):
+        vals = b.contract(ws=ws, stream=stream, flags=flags)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        vals = b.contract(ws=ws, stream=stream, flags=flags)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    total_bytes = sum(p.stats()["bytes_per_slice"] for p in plans)
+    total_flops = sum(p.stats()["flops_per_slice"] for p in plans)
+    ms_step = dt / args.steps * 1e3
+    out = {
+        "metric": "WMC solves/s (512-instance batch)",
+        "value": round(n_inst * args.steps / dt, 1),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 storage",
+        "data": "synthetic",
+        "config": {"workload": "batch of 512 banded random 3-CNF (n~U{30..150}, ratio~U(3.0,4.2), window 20, "
+                               "seed i), seeded min-fill trees, merged launches + HIP graph",
+                   "precision": args.precision, "launches": b.n_launches, "plan_seconds": round(plan_s, 2)},
+        "algorithmic_gbs": round(total_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "contraction_tflops": round(total_flops / (ms_step * 1e-3) / 1e12, 3),
+        "zero_fraction": sum(1 for v in vals if v.mantissa == 0.0) / n_inst,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +152,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid24")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--block", type=int, default=5)
+    ap.add_argument("--block", type=int, default=0, help="variables per elimination step (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="a few solves, no timing output (for rocprofv3)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -126,10 +169,13 @@ def main():
     import paper_2006_15512_amd as W
 
     torch.cuda.set_device(0)
+    if args.workload == "batch512":
+        return bench_batch(args, W, torch)
     f, pkw, desc = workload(args.workload)
     net = W.Network.from_formula(f)
     t0 = time.perf_counter()
-    block = args.block if pkw.get("kind") == "order" else 1
+    block = args.block if args.block > 0 else pkw.pop("block", 1)
+    pkw.pop("block", None)
     plan = W.Plan(net, precision=args.precision, block=block, **pkw)
     plan_s = time.perf_counter() - t0
     st = plan.stats()

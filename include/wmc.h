@@ -200,6 +200,38 @@ wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double *weights, v
                                 uint64_t workspace_bytes, void *stream, float *ms, int64_t cap,
                                 wmc_value *out);
 
+/* ------------------------------------------------------------------ */
+/* Batches: many planned networks contracted in shared launches         */
+/* ------------------------------------------------------------------ */
+/* The plans' launch lists are merged by index (launch k of one plan depends
+ * only on its own launches < k), their descriptors concatenated into one
+ * arena, meta table and weight vector, and every root finished by one kernel.
+ * Plans must share a precision and be unsliced (WMC_ERR_UNSUPPORTED
+ * otherwise).  The batch copies what it needs; the plans may be destroyed
+ * afterwards.  A batch is used by one thread at a time (calls are
+ * serialised internally). */
+typedef struct wmc_batch wmc_batch;
+
+#define WMC_BATCH_RESIDENT 1u /* descriptors already in this workspace from an earlier call */
+#define WMC_BATCH_GRAPH 2u    /* capture the launch sequence once per workspace as a HIP graph
+                                 and replay it (captured on a private stream) */
+
+wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n, wmc_batch **out);
+wmc_status wmc_batch_info(const wmc_batch *b, uint64_t *workspace_bytes, int64_t *n_launches,
+                          int64_t *n_instances);
+/* weights: the instances' weight vectors concatenated (2 * sum of n_vars
+ * doubles, host) or NULL for the networks' own; out: n_instances values. */
+wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, void *workspace,
+                              uint64_t workspace_bytes, void *stream, uint32_t flags,
+                              wmc_value *out);
+void wmc_batch_destroy(wmc_batch *b);
+/* Raw descriptor image of a batch (tools and tests): [leaf descriptors][node
+ * descriptors][launch list][matrix-node descriptors][root tensor int32 x n]
+ * [root offset int64 x n]; info[0..8] = {n_leaves, n_nodes, n_launches,
+ * arena_elems, n_instances, meta_total, elem_bytes, n_gemms, n_vars_total}. */
+wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, uint64_t *needed,
+                           int64_t *info /* 9 entries */);
+
 /* Thread-local description of the last non-OK status on this thread. */
 const char *wmc_last_error(void);
 

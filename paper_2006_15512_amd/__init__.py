@@ -89,13 +89,17 @@ def lib():
             "wmc_contract": [P, P, P, u64, P, ctypes.POINTER(wmc_value)],
             "wmc_contract_slices": [P, P, P, u64, P, i64, i64, ctypes.POINTER(wmc_value), P],
             "wmc_plan_launches": [P, P, P, P, i64, P],
+            "wmc_batch_create": [P, i64, P],
+            "wmc_batch_info": [P, P, P, P],
+            "wmc_batch_contract": [P, P, P, u64, P, ctypes.c_uint32, P],
+            "wmc_batch_image": [P, P, u64, P, P],
             "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
-        for name in ("wmc_network_destroy", "wmc_plan_destroy"):
+        for name in ("wmc_network_destroy", "wmc_plan_destroy", "wmc_batch_destroy"):
             getattr(L, name).argtypes = [P]
             getattr(L, name).restype = None
         L.wmc_last_error.restype = ctypes.c_char_p
@@ -342,3 +346,58 @@ def wmc_contract_profile(plan: Plan, weights=None, ws=None, stream=None):
 
 def version() -> str:
     return lib().wmc_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+BATCH_RESIDENT = 1
+BATCH_GRAPH = 2
+
+
+class Batch:
+    """wmc_batch_create over a list of unsliced plans of one precision."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+        h = ctypes.c_void_p()
+        _check(lib().wmc_batch_create(arr, len(plans), ctypes.byref(h)))
+        self._h = h
+        self.plans = list(plans)
+        wsb, nl, ni = ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().wmc_batch_info(self._h, ctypes.byref(wsb), ctypes.byref(nl), ctypes.byref(ni)))
+        self.workspace_bytes = int(wsb.value)
+        self.n_launches = int(nl.value)
+        self.n = int(ni.value)
+
+    def workspace(self, device: str = "cuda:0"):
+        import torch
+        return torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
+
+    def image(self):
+        """Raw descriptor image: (bytes, info dict)."""
+        need = ctypes.c_uint64()
+        info = (ctypes.c_int64 * 9)()
+        _check(lib().wmc_batch_image(self._h, None, 0, ctypes.byref(need), info))
+        buf = (ctypes.c_uint8 * max(int(need.value), 1))()
+        _check(lib().wmc_batch_image(self._h, buf, int(need.value), ctypes.byref(need), info))
+        keys = ["n_leaves", "n_nodes", "n_launches", "arena_elems", "n_instances", "meta_total", "elem",
+                "n_gemms", "n_vars_total"]
+        return bytes(buf)[: int(need.value)], dict(zip(keys, list(info)))
+
+    def contract(self, weights=None, ws=None, stream=None, flags: int = 0) -> List[Value]:
+        if ws is None:
+            ws = self.workspace()
+        w = None
+        if weights is not None:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        out = (wmc_value * self.n)()
+        _check(lib().wmc_batch_contract(self._h, _p(w), ctypes.c_void_p(ws.data_ptr()),
+                                        ws.numel() * ws.element_size(), _stream_ptr(stream), int(flags), out))
+        return [Value.of(out[i]) for i in range(self.n)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.wmc_batch_destroy(h)
+            self._h = None

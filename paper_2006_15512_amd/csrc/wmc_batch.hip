@@ -1,0 +1,367 @@
+// Batched execution of many planned networks (many small formulas, or one
+// structure with many weight vectors) in shared launches.
+//
+// Launch k of one plan depends only on that plan's launches < k, so launch k
+// of every instance can run in the same kernel.  The batch concatenates the
+// instances' leaf and node descriptors (offsets patched into one arena, one
+// meta table and one weight vector), merges their launch lists by index,
+// runs every generic or streaming node of a merged step in one k_nodes
+// launch and every matrix node in its own MFMA launch, and finishes all
+// roots with one kernel.  The whole sequence can be captured once as a HIP
+// graph and replayed.
+#include <mutex>
+
+#include "wmc_kernels.h"
+
+struct BatchRes {
+    double m;
+    long long e;
+};
+
+template <typename T>
+__global__ void k_finish_batch(const T *__restrict__ arena, const long long *__restrict__ root_off,
+                               const int *__restrict__ root, const wmc_meta *meta, int n, BatchRes *out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (root[i] < 0) {  // no variables and no clauses: the empty product
+        out[i].m = 0.5;
+        out[i].e = 1;
+        return;
+    }
+    double v = (double)arena[root_off[i]];
+    long long e = meta[root[i]].exp;
+    if (v != 0.0) {
+        int k;
+        v = frexp(v, &k);
+        e += k;
+    } else {
+        e = 0;
+    }
+    out[i].m = v;
+    out[i].e = e;
+}
+
+struct wmc_batch {
+    int32_t precision = WMC_FP64;
+    int32_t elem = 8;
+    int64_t n = 0;
+    int64_t n_vars_total = 0;
+    std::vector<int64_t> var_off;
+    std::vector<int32_t> nvars;
+    std::vector<double> w;
+    std::vector<LeafDesc> leaves;
+    int64_t leaf_work = 0;
+    std::vector<NodeDesc> nodes;
+    std::vector<GemmDesc> gemms;
+    std::vector<Launch> launches;  // [0] = leaves; then LAUNCH_NODES / LAUNCH_GEMM
+    std::vector<int32_t> roots;
+    std::vector<long long> root_off;
+    int64_t meta_total = 0;
+    uint64_t off_res = 0, off_w = 0, off_meta = 0, off_leaf = 0, off_node = 0, off_gemm = 0, off_roots = 0,
+             off_rootoff = 0, off_arena = 0;
+    uint64_t arena_bytes = 0, workspace_bytes = 0, desc_bytes = 0;
+    std::vector<uint8_t> image;  // [off_leaf, off_arena) of the workspace
+    std::mutex mu;
+    void *graph_ws = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    ~wmc_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
+static uint64_t bal(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n, wmc_batch **out) {
+    if (!out) {
+        wmc_set_error("wmc_batch_create: out is NULL");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    *out = nullptr;
+    if (n <= 0 || !plans) {
+        wmc_set_error("wmc_batch_create: need at least one plan");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!plans[i]) {
+            wmc_set_error("wmc_batch_create: plan %lld is NULL", (long long)i);
+            return WMC_ERR_INVALID_ARGUMENT;
+        }
+        if (plans[i]->precision != plans[0]->precision) {
+            wmc_set_error("wmc_batch_create: plans mix precisions");
+            return WMC_ERR_INVALID_ARGUMENT;
+        }
+        if (!plans[i]->sliced.empty()) {
+            wmc_set_error("wmc_batch_create: plan %lld is sliced (%zu variables); batches take unsliced plans",
+                          (long long)i, plans[i]->sliced.size());
+            return WMC_ERR_UNSUPPORTED;
+        }
+    }
+    try {
+        wmc_batch *B = new wmc_batch();
+        B->precision = plans[0]->precision;
+        B->elem = plans[0]->elem;
+        B->n = n;
+        std::vector<int64_t> abase((size_t)n), mbase((size_t)n);
+        int64_t arena_elems = 0, meta = 0, vars = 0;
+        size_t kmax = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const wmc_plan_t &P = *plans[i];
+            abase[(size_t)i] = arena_elems;
+            mbase[(size_t)i] = meta;
+            B->var_off.push_back(vars);
+            B->nvars.push_back(P.n);
+            B->w.insert(B->w.end(), P.w.begin(), P.w.end());
+            arena_elems += (int64_t)bal(P.arena_bytes / (uint64_t)P.elem, 64);
+            meta += (int64_t)P.T.size();
+            vars += P.n;
+            kmax = std::max(kmax, P.launches.size());
+        }
+        B->n_vars_total = vars;
+        B->meta_total = std::max<int64_t>(meta, 1);
+        // leaves
+        B->launches.push_back({LAUNCH_LEAF, 0, 0, 0, 0});
+        for (int64_t i = 0; i < n; ++i) {
+            const wmc_plan_t &P = *plans[i];
+            for (LeafDesc d : P.leaves) {
+                d.out += abase[(size_t)i];
+                d.tensor += (int)mbase[(size_t)i];
+                if (d.kind != WMC_LEAF_CLAUSE) d.var += (int)B->var_off[(size_t)i];
+                d.work_begin = B->leaf_work;
+                B->leaf_work += (int64_t)bal((uint64_t)1 << d.rank, WMC_WAVE);
+                B->leaves.push_back(d);
+            }
+        }
+        B->launches[0].work = B->leaf_work;
+        // node launches, merged by index
+        for (size_t k = 1; k < kmax; ++k) {
+            Launch merged{LAUNCH_NODES, (int32_t)B->nodes.size(), 0, 0, 0};
+            std::vector<Launch> gemm_launches;
+            for (int64_t i = 0; i < n; ++i) {
+                const wmc_plan_t &P = *plans[i];
+                if (k >= P.launches.size()) continue;
+                const Launch &L = P.launches[k];
+                if (L.type == LAUNCH_GEMM) {
+                    GemmDesc g = P.gemms[(size_t)L.pad];
+                    g.a += abase[(size_t)i];
+                    g.b += abase[(size_t)i];
+                    g.c += abase[(size_t)i];
+                    g.ta += (int)mbase[(size_t)i];
+                    g.tb += (int)mbase[(size_t)i];
+                    g.tc += (int)mbase[(size_t)i];
+                    gemm_launches.push_back({LAUNCH_GEMM, 0, 1, (int32_t)B->gemms.size(), 0});
+                    B->gemms.push_back(g);
+                    continue;
+                }
+                for (int32_t q = 0; q < L.count; ++q) {
+                    NodeDesc d = P.nodes[(size_t)(L.first + q)];
+                    d.a += abase[(size_t)i];
+                    d.b += abase[(size_t)i];
+                    d.c += abase[(size_t)i];
+                    d.ta += (int)mbase[(size_t)i];
+                    d.tb += (int)mbase[(size_t)i];
+                    d.tc += (int)mbase[(size_t)i];
+                    d.work_begin = merged.work;
+                    merged.work += (int64_t)bal((uint64_t)1 << d.rc, WMC_WAVE);
+                    B->nodes.push_back(d);
+                    ++merged.count;
+                }
+            }
+            if (merged.count) B->launches.push_back(merged);
+            for (const Launch &g : gemm_launches) B->launches.push_back(g);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            const wmc_plan_t &P = *plans[i];
+            B->roots.push_back(P.root < 0 ? -1 : P.root + (int)mbase[(size_t)i]);
+            B->root_off.push_back(P.root < 0 ? 0 : (long long)(P.T[(size_t)P.root].off + abase[(size_t)i]));
+        }
+        // workspace layout
+        uint64_t off = 0;
+        B->off_res = off;
+        off += bal(sizeof(BatchRes) * (uint64_t)n, 256);
+        B->off_w = off;
+        off += bal(sizeof(double) * 2 * (uint64_t)std::max<int64_t>(vars, 1), 256);
+        B->off_meta = off;
+        off += bal(sizeof(wmc_meta) * (uint64_t)B->meta_total, 256);
+        B->off_leaf = off;
+        off += bal(sizeof(LeafDesc) * std::max<size_t>(B->leaves.size(), 1), 256);
+        B->off_node = off;
+        off += bal(sizeof(NodeDesc) * std::max<size_t>(B->nodes.size(), 1), 256);
+        B->off_gemm = off;
+        off += bal(sizeof(GemmDesc) * std::max<size_t>(B->gemms.size(), 1), 256);
+        B->off_roots = off;
+        off += bal(sizeof(int) * (uint64_t)n, 256);
+        B->off_rootoff = off;
+        off += bal(sizeof(long long) * (uint64_t)n, 256);
+        B->off_arena = off;
+        B->arena_bytes = (uint64_t)arena_elems * (uint64_t)B->elem;
+        B->workspace_bytes = off + bal(B->arena_bytes, 256);
+        B->desc_bytes = B->off_arena - B->off_leaf;
+        B->image.assign(B->desc_bytes, 0);
+        uint8_t *img = B->image.data();
+        auto put = [&](uint64_t o, const void *src, size_t bytes) {
+            if (bytes) std::memcpy(img + (o - B->off_leaf), src, bytes);
+        };
+        put(B->off_leaf, B->leaves.data(), sizeof(LeafDesc) * B->leaves.size());
+        put(B->off_node, B->nodes.data(), sizeof(NodeDesc) * B->nodes.size());
+        put(B->off_gemm, B->gemms.data(), sizeof(GemmDesc) * B->gemms.size());
+        put(B->off_roots, B->roots.data(), sizeof(int) * B->roots.size());
+        put(B->off_rootoff, B->root_off.data(), sizeof(long long) * B->root_off.size());
+        *out = B;
+    } catch (std::bad_alloc &) {
+        wmc_set_error("wmc_batch_create: host allocation failed");
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_batch_info(const wmc_batch *b, uint64_t *workspace_bytes, int64_t *n_launches,
+                                     int64_t *n_instances) {
+    if (!b) {
+        wmc_set_error("wmc_batch_info: batch is NULL");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (workspace_bytes) *workspace_bytes = b->workspace_bytes;
+    if (n_launches) *n_launches = (int64_t)b->launches.size() + 2;
+    if (n_instances) *n_instances = b->n;
+    return WMC_OK;
+}
+
+extern "C" void wmc_batch_destroy(wmc_batch *b) { delete b; }
+
+template <typename T>
+static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
+    wmc_meta *meta = (wmc_meta *)(ws + B.off_meta);
+    const double *w = (const double *)(ws + B.off_w);
+    const LeafDesc *L = (const LeafDesc *)(ws + B.off_leaf);
+    const NodeDesc *D = (const NodeDesc *)(ws + B.off_node);
+    const GemmDesc *G = (const GemmDesc *)(ws + B.off_gemm);
+    T *arena = (T *)(ws + B.off_arena);
+    const int nt = (int)B.meta_total;
+    hipLaunchKernelGGL(k_begin, dim3((nt + WMC_BLOCK - 1) / WMC_BLOCK), dim3(WMC_BLOCK), 0, st, meta, nt,
+                       (wmc_acc *)nullptr, 0);
+    if (!B.leaves.empty())
+        hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(B.leaf_work)), dim3(WMC_BLOCK), 0, st, L, (int)B.leaves.size(),
+                           (long long)B.leaf_work, w, arena, meta, 0ull);
+    for (size_t k = 1; k < B.launches.size(); ++k) {
+        const Launch &Ln = B.launches[k];
+        if (Ln.type == LAUNCH_GEMM)
+            launch_gemm<T>(B.gemms[(size_t)Ln.pad], G + Ln.pad, arena, meta, st);
+        else
+            hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first, Ln.count,
+                               (long long)Ln.work, arena, meta);
+    }
+    hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n + 255) / 256)), dim3(256), 0, st, arena,
+                       (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n,
+                       (BatchRes *)(ws + B.off_res));
+}
+
+extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, void *workspace,
+                                         uint64_t workspace_bytes, void *stream, uint32_t flags, wmc_value *out) {
+    if (!b || !out) {
+        wmc_set_error("wmc_batch_contract: NULL batch or out");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    wmc_batch &B = *b;
+    if (!workspace || ((uintptr_t)workspace & 255u)) {
+        wmc_set_error("wmc_batch_contract: workspace is NULL or not 256-byte aligned");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (workspace_bytes < B.workspace_bytes) {
+        wmc_set_error("wmc_batch_contract: workspace has %llu bytes, batch needs %llu",
+                      (unsigned long long)workspace_bytes, (unsigned long long)B.workspace_bytes);
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    const double *w = weights ? weights : B.w.data();
+    if (weights)
+        for (int64_t i = 0; i < 2 * B.n_vars_total; ++i)
+            if (!std::isfinite(weights[i])) {
+                wmc_set_error("wmc_batch_contract: weight %lld is not finite", (long long)i);
+                return WMC_ERR_INVALID_ARGUMENT;
+            }
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    std::lock_guard<std::mutex> lock(B.mu);
+    if (B.n_vars_total > 0)
+        HIP_TRY(hipMemcpyAsync(ws + B.off_w, w, sizeof(double) * 2 * (size_t)B.n_vars_total, hipMemcpyHostToDevice, st));
+    if (!(flags & WMC_BATCH_RESIDENT))
+        HIP_TRY(hipMemcpyAsync(ws + B.off_leaf, B.image.data(), B.desc_bytes, hipMemcpyHostToDevice, st));
+    if (flags & WMC_BATCH_GRAPH) {
+        if (B.exec && B.graph_ws != workspace) {
+            HIP_TRY(hipGraphExecDestroy(B.exec));
+            B.exec = nullptr;
+        }
+        if (!B.exec) {
+            if (!B.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
+            if (B.precision == WMC_FP64) batch_launches<double>(B, ws, B.cap_stream);
+            else batch_launches<float>(B, ws, B.cap_stream);
+            HIP_TRY(hipStreamEndCapture(B.cap_stream, &graph));
+            hipError_t e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                B.exec = nullptr;
+                wmc_set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+                return WMC_ERR_DEVICE;
+            }
+            B.graph_ws = workspace;
+        }
+        HIP_TRY(hipGraphLaunch(B.exec, st));
+    } else {
+        if (B.precision == WMC_FP64) batch_launches<double>(B, ws, st);
+        else batch_launches<float>(B, ws, st);
+    }
+    HIP_TRY(hipGetLastError());
+    std::vector<BatchRes> h((size_t)B.n);
+    HIP_TRY(hipMemcpyAsync(h.data(), ws + B.off_res, sizeof(BatchRes) * (size_t)B.n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < B.n; ++i) out[i] = make_value(h[(size_t)i].m, h[(size_t)i].e);
+    return WMC_OK;
+}
+
+// Raw descriptor image of a batch, for tools and tests:
+// [LeafDesc][NodeDesc][Launch][GemmDesc][root tensor int32][root offset int64];
+// info[] = {n_leaves, n_nodes, n_launches, arena_elems, n_instances,
+//           meta_total, elem_bytes, n_gemms, n_vars_total}.
+extern "C" wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, uint64_t *needed,
+                                      int64_t *info) {
+    if (!b) {
+        wmc_set_error("wmc_batch_image: batch is NULL");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    const wmc_batch &B = *b;
+    const uint64_t need = sizeof(LeafDesc) * B.leaves.size() + sizeof(NodeDesc) * B.nodes.size() +
+                          sizeof(Launch) * B.launches.size() + sizeof(GemmDesc) * B.gemms.size() +
+                          sizeof(int) * B.roots.size() + sizeof(long long) * B.root_off.size();
+    if (needed) *needed = need;
+    if (info) {
+        info[0] = (int64_t)B.leaves.size();
+        info[1] = (int64_t)B.nodes.size();
+        info[2] = (int64_t)B.launches.size();
+        info[3] = (int64_t)(B.arena_bytes / (uint64_t)B.elem);
+        info[4] = B.n;
+        info[5] = B.meta_total;
+        info[6] = B.elem;
+        info[7] = (int64_t)B.gemms.size();
+        info[8] = B.n_vars_total;
+    }
+    if (!dst) return WMC_OK;
+    if (dst_bytes < need) {
+        wmc_set_error("wmc_batch_image: buffer too small");
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    char *p = (char *)dst;
+    auto put = [&](const void *src, size_t bytes) {
+        if (bytes) std::memcpy(p, src, bytes);
+        p += bytes;
+    };
+    put(B.leaves.data(), sizeof(LeafDesc) * B.leaves.size());
+    put(B.nodes.data(), sizeof(NodeDesc) * B.nodes.size());
+    put(B.launches.data(), sizeof(Launch) * B.launches.size());
+    put(B.gemms.data(), sizeof(GemmDesc) * B.gemms.size());
+    put(B.roots.data(), sizeof(int) * B.roots.size());
+    put(B.root_off.data(), sizeof(long long) * B.root_off.size());
+    return WMC_OK;
+}

@@ -51,7 +51,9 @@ struct LeafDesc {
 // Every operand's storage layout is [kappa bits | its C-variables in C's
 // storage order], so for an output address r:
 //   addr_A(r, j) = (pext(r, maskA) << nk) | j,   j over the 2^nk kappa values,
-// where pext is given as runs (src bit in r, length, dst bit).
+// where pext is given as runs packed in one word each:
+//   src bit in r | length << 8 | dst bit << 16.
+#define WMC_RUN(src, len, dst) ((unsigned)(src) | ((unsigned)(len) << 8) | ((unsigned)(dst) << 16))
 struct NodeDesc {
     long long a, b, c;        // element offsets in the arena
     long long work_begin;     // first work item of this node in its launch
@@ -60,9 +62,8 @@ struct NodeDesc {
     int nk;                   // |kappa| (after slicing)
     int nra, nrb;             // number of runs in ra / rb
     int cls;                  // node class
-    unsigned char ra[WMC_MAX_RUNS][3];
-    unsigned char rb[WMC_MAX_RUNS][3];
-    int pad[3];
+    unsigned ra[WMC_MAX_RUNS];
+    unsigned rb[WMC_MAX_RUNS];
 };
 
 // A contraction run as a batched matrix product on MFMA:
@@ -87,4 +88,4 @@ struct GemmDesc {
 
 static_assert(sizeof(LeafDesc) == 96, "LeafDesc layout");
 static_assert(sizeof(GemmDesc) == 336, "GemmDesc layout");
-static_assert(sizeof(NodeDesc) == 200, "NodeDesc layout");
+static_assert(sizeof(NodeDesc) == 224, "NodeDesc layout");

@@ -1,732 +1,7 @@
-// Execution stage on gfx950: the pairwise contractions of Algorithm 2 over
-// the slices of Algorithm 3, all on the device.
-//
-// Numerics.  Every tensor t carries an exponent: its true entries are
-// stored * 2^exp.  A node reads the largest magnitude of each operand (kept
-// by the producer with an integer atomicMax on the IEEE bits), scales the
-// operand by the power of two that brings that maximum into [0.5, 1) while
-// it contracts (exact for normal numbers), and adds both shifts to the
-// output's exponent.  Sums are formed in double for both storage
-// precisions; the FP32 path rounds once when it stores.  Slices are summed
-// in double as (s + c) * 2^e with Neumaier compensation, in slice order.
-#include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstring>
-#include <vector>
-
-#include "wmc_internal.h"
-
-#define WMC_BLOCK 256
-
-// ---------------------------------------------------------------------------
-// device helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int scale_exp(unsigned long long maxbits) {
-    double m = __longlong_as_double((long long)maxbits);
-    if (!(m > 0.0)) return 0;
-    int e;
-    frexp(m, &e);
-    return e;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WMC_WAVE));
-    return v;
-}
-
-__device__ __forceinline__ void publish_max(wmc_meta *meta, int t, double v) {
-    v = wave_max(v);
-    if ((threadIdx.x & (WMC_WAVE - 1)) == 0 && v > 0.0)
-        atomicMax(&meta[t].maxbits, (unsigned long long)__double_as_longlong(v));
-}
-
-// bit extraction of r along runs (src bit, length, dst bit)
-__device__ __forceinline__ unsigned long long pext_runs(unsigned long long r, const unsigned char (*runs)[3], int nr) {
-    unsigned long long out = 0;
-    for (int q = 0; q < nr; ++q) {
-        unsigned s = runs[q][0], l = runs[q][1], d = runs[q][2];
-        out |= ((r >> s) & ((1ull << l) - 1ull)) << d;
-    }
-    return out;
-}
-
-template <typename T>
-__device__ __forceinline__ double ld(const T *p) { return (double)*p; }
-
-// ---------------------------------------------------------------------------
-// kernels
-// ---------------------------------------------------------------------------
-__global__ void k_begin(wmc_meta *meta, int nt, wmc_acc *acc, int reset) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nt) {
-        meta[i].maxbits = 0ull;
-        meta[i].exp = 0;
-    }
-    if (i == 0 && reset) {
-        acc->s = 0.0;
-        acc->c = 0.0;
-        acc->e = 0;
-        acc->n_added = 0;
-        acc->last_m = 0.0;
-        acc->last_e = 0;
-    }
-}
-
-// Leaf fill (Theorem 2): clause tables B_C restricted to the slice, weight
-// vectors [W(x,0), W(x,1)], or W(x,0)+W(x,1) for a variable in no clause.
-template <typename T>
-__global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict__ L, int nl, long long work,
-                                                      const double *__restrict__ w, T *__restrict__ arena,
-                                                      wmc_meta *meta, unsigned long long eta) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
-        int lo = 0, hi = nl - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (L[mid].work_begin <= g) lo = mid; else hi = mid - 1;
-        }
-        const LeafDesc &d = L[lo];
-        const long long e = g - d.work_begin;
-        const bool valid = e < (1ll << d.rank);
-        double v = 0.0;
-        if (valid) {
-            if (d.kind == WMC_LEAF_CLAUSE) {
-                unsigned a = 0;
-                for (int q = 0; q < d.k; ++q) {
-                    int p = d.pos[q];
-                    unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((eta >> (-p - 1)) & 1ull);
-                    a |= bit << q;
-                }
-                v = (d.taut || a != d.falsify) ? 1.0 : 0.0;
-            } else if (d.kind == WMC_LEAF_WEIGHT) {
-                int p = d.pos[0];
-                unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((eta >> (-p - 1)) & 1ull);
-                v = w[2 * d.var + bit];
-            } else {
-                v = w[2 * d.var] + w[2 * d.var + 1];
-            }
-            T s = (T)v;
-            arena[d.out + e] = s;
-            v = fabs((double)s);
-        }
-        publish_max(meta, d.tensor, v);
-    }
-}
-
-// Pairwise contraction, any shape: one output entry per thread,
-// C[r] = 2^-(sA+sB) * sum_j A[(pext_A(r) << nk) | j] * B[(pext_B(r) << nk) | j].
-// A launch covers a run of nodes; each node's outputs are padded to a wave
-// multiple so that a wave never straddles two nodes.
-template <typename T>
-__global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict__ D, int nd, long long work,
-                                                     T *__restrict__ arena, wmc_meta *meta) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
-        int lo = 0, hi = nd - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (D[mid].work_begin <= g) lo = mid; else hi = mid - 1;
-        }
-        const NodeDesc &d = D[lo];
-        const unsigned long long r = (unsigned long long)(g - d.work_begin);
-        const bool valid = r < (1ull << d.rc);
-        const int sA = scale_exp(meta[d.ta].maxbits);
-        const int sB = scale_exp(meta[d.tb].maxbits);
-        double v = 0.0;
-        if (valid) {
-            const T *A = arena + d.a + (pext_runs(r, d.ra, d.nra) << d.nk);
-            const T *B = arena + d.b + (pext_runs(r, d.rb, d.nrb) << d.nk);
-            const int K = 1 << d.nk;
-            double acc = 0.0;
-            for (int j = 0; j < K; ++j) acc = fma(ld(A + j), ld(B + j), acc);
-            T s = (T)ldexp(acc, -(sA + sB));
-            arena[d.c + (long long)r] = s;
-            v = fabs((double)s);
-        }
-        publish_max(meta, d.tc, v);
-        if (r == 0) meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Matrix-shaped contractions on MFMA (16x16x4, FP64 or FP32).
-//
-//   C[beta, mu, nu] = sum_k A[beta, mu, k] * B[beta, k, nu]
-//
-// The row operand A is stored [4 lowest mu bits | kappa | rest], so the 16
-// rows of a row tile are contiguous for each summed index k.  For the
-// 16x16x4 instruction lane l supplies row (or column) l%16 and reduction
-// slot l/16; at step s lane group g = l/16 takes summed index k = 4s + g, so
-// one load instruction of a wave reads A[tile][k = 4s..4s+3][16 rows]: 512
-// contiguous bytes (FP64).  A and B use the same k for a given (s, g), so
-// every (row, k, column) term is summed exactly once.  B, the small operand
-// (columns contiguous in kappa), is staged per chunk of KC summed indices in
-// LDS as [k][column].  A workgroup of 4 waves owns 8 row tiles (2 per wave)
-// of one beta and all N <= 128 columns.
-// ---------------------------------------------------------------------------
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-typedef float flt4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-// Output register v of lane l holds column l%16 and row out_row(l/16, v):
-// rows g + 4v for the FP64 instruction, 4g + v for the FP32 one (measured).
-template <> struct Mfma<double> {
-    typedef dbl4 acc_t;
-    static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int out_row(int g, int v) { return g + 4 * v; }
-};
-template <> struct Mfma<float> {
-    typedef flt4 acc_t;
-    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int out_row(int g, int v) { return 4 * g + v; }
-};
-
-#define GEMM_TILES_PER_WAVE 2
-#define GEMM_TILES (4 * GEMM_TILES_PER_WAVE)
-#define GEMM_LDS_BYTES (48 * 1024)
-
-__host__ __device__ inline int gemm_ldn(int nn, int elem) { return (1 << nn) + (elem == 8 ? 2 : 4); }
-
-__host__ __device__ inline int gemm_kc(int nk, int nn, int elem) {
-    int K = 1 << nk;
-    int kc = K < 64 ? K : 64;
-    while (kc > 4 && (long long)kc * gemm_ldn(nn, elem) * elem > GEMM_LDS_BYTES) kc >>= 1;
-    return kc;
-}
-
-template <typename T, int NT>
-__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T *__restrict__ arena, wmc_meta *meta) {
-    typedef typename Mfma<T>::acc_t acc_t;
-    extern __shared__ char smem_raw[];
-    T *Bs = (T *)smem_raw;
-    const GemmDesc &d = *G;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, l16 = lane & 15;
-    const int nk = d.nk;
-    const int K = 1 << nk, N = 1 << d.nn;
-    const int KC = gemm_kc(nk, d.nn, (int)sizeof(T));
-    const int S = KC / 4;
-    const int LDN = gemm_ldn(d.nn, (int)sizeof(T));
-    const unsigned long long tiles = 1ull << (d.nm - 4);
-    const unsigned long long beta = blockIdx.y;
-    const int sA = scale_exp(meta[d.ta].maxbits);
-    const int sB = scale_exp(meta[d.tb].maxbits);
-    const unsigned long long rowBeta = pext_runs(beta, d.run[GR_BETA_A], d.nrun[GR_BETA_A]);
-    const unsigned long long colBeta = pext_runs(beta, d.run[GR_BETA_B], d.nrun[GR_BETA_B]);
-    const unsigned long long t0 = ((unsigned long long)blockIdx.x * 4 + wave) * GEMM_TILES_PER_WAVE;
-
-    long long abase[GEMM_TILES_PER_WAVE];
-    bool tv[GEMM_TILES_PER_WAVE];
-#pragma unroll
-    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-        unsigned long long t = t0 + rt;
-        tv[rt] = t < tiles;
-        abase[rt] = d.a + l16 +
-                    (long long)((pext_runs(tv[rt] ? t : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << (4 + nk));
-    }
-    acc_t acc[GEMM_TILES_PER_WAVE][NT];
-#pragma unroll
-    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
-
-    for (int kc = 0; kc < K; kc += KC) {
-        for (int idx = threadIdx.x; idx < N * KC; idx += 256) {
-            int col = idx / KC, k = idx - col * KC;
-            unsigned long long cb = pext_runs((unsigned long long)col, d.run[GR_NU_B], d.nrun[GR_NU_B]) | colBeta;
-            Bs[k * LDN + col] = arena[d.b + (long long)(cb << nk) + kc + k];
-        }
-        T a[GEMM_TILES_PER_WAVE][16];
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
-#pragma unroll
-            for (int s = 0; s < 16; ++s)
-                a[rt][s] = (s < S && tv[rt]) ? arena[abase[rt] + 16 * (long long)(kc + 4 * s + g)] : (T)0;
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            if (s < S) {
-#pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    const int col = ct * 16 + l16;
-                    T b = (col < N) ? Bs[(4 * s + g) * LDN + col] : (T)0;
-#pragma unroll
-                    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
-                        acc[rt][ct] = Mfma<T>::step(a[rt][s], b, acc[rt][ct]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    const double scale = ldexp(1.0, -(sA + sB));
-    const unsigned long long cBeta = pext_runs(beta, d.run[GR_BETA_C], d.nrun[GR_BETA_C]);
-    unsigned long long rowC[GEMM_TILES_PER_WAVE][4];
-#pragma unroll
-    for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            unsigned long long m = ((t0 + rt) << 4) + Mfma<T>::out_row(g, v);
-            rowC[rt][v] = pext_runs(m, d.run[GR_MU_C], d.nrun[GR_MU_C]) | cBeta;
-        }
-    double vmax = 0.0;
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-        const int col = ct * 16 + l16;
-        if (col >= N) continue;
-        const unsigned long long cc = pext_runs((unsigned long long)col, d.run[GR_NU_C], d.nrun[GR_NU_C]);
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-            if (!tv[rt]) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                T sv = (T)((double)acc[rt][ct][v] * scale);
-                arena[d.c + (long long)(rowC[rt][v] | cc)] = sv;
-                vmax = fmax(vmax, fabs((double)sv));
-            }
-        }
-    }
-    publish_max(meta, d.tc, vmax);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-        meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
-}
-
-// Persistent form for the common case where all of B[beta] (K <= 64 summed
-// indices x N columns) fits in LDS: each workgroup stages B once, then walks
-// row-tile groups blockIdx.x, blockIdx.x + gridDim.x, ..., loading the next
-// group's A fragments into registers while the MFMAs of the current group run.
-template <typename T, int NT, int S>
-__global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, T *__restrict__ arena,
-                                                wmc_meta *meta) {
-    typedef typename Mfma<T>::acc_t acc_t;
-    extern __shared__ char smem_raw[];
-    __shared__ GemmDesc sd;
-    T *Bs = (T *)smem_raw;
-    // the descriptor lives in LDS so that run-list reads never wait on the
-    // vector-memory counter that tracks the A prefetches
-    for (int i = threadIdx.x; i < (int)(sizeof(GemmDesc) / sizeof(int)); i += 256)
-        ((int *)&sd)[i] = ((const int *)G)[i];
-    __syncthreads();
-    const GemmDesc &d = sd;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, l16 = lane & 15;
-    constexpr int K = 4 * S;
-    const int nk = d.nk;
-    const int N = 1 << d.nn;
-    constexpr int LDN = NT * 16 + (sizeof(T) == 8 ? 2 : 4);
-    const unsigned long long tiles = 1ull << (d.nm - 4);
-    const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;
-    const unsigned long long beta = blockIdx.y;
-    const long long a0 = d.a, c0 = d.c;
-    const int sA = scale_exp(meta[d.ta].maxbits);
-    const int sB = scale_exp(meta[d.tb].maxbits);
-    const unsigned long long rowBeta = pext_runs(beta, d.run[GR_BETA_A], d.nrun[GR_BETA_A]);
-    const unsigned long long colBeta = pext_runs(beta, d.run[GR_BETA_B], d.nrun[GR_BETA_B]);
-    const unsigned long long cBeta = pext_runs(beta, d.run[GR_BETA_C], d.nrun[GR_BETA_C]);
-    const double scale = ldexp(1.0, -(sA + sB));
-
-    // B[beta] as [k][column], columns N..16*NT-1 zero
-    for (int idx = threadIdx.x; idx < NT * 16 * K; idx += 256) {
-        int col = idx / K, k = idx - col * K;
-        T v = (T)0;
-        if (col < N) {
-            unsigned long long cb = pext_runs((unsigned long long)col, d.run[GR_NU_B], d.nrun[GR_NU_B]) | colBeta;
-            v = arena[d.b + (long long)(cb << nk) + k];
-        }
-        Bs[k * LDN + col] = v;
-    }
-    unsigned long long cols[NT];
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-        const int col = ct * 16 + l16;
-        cols[ct] = pext_runs((unsigned long long)(col < N ? col : 0), d.run[GR_NU_C], d.nrun[GR_NU_C]) | cBeta;
-    }
-    unsigned long long rlo[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-        rlo[v] = pext_runs((unsigned long long)Mfma<T>::out_row(g, v), d.run[GR_MU_C], d.nrun[GR_MU_C]);
-
-    // A fragments: loads are unconditional (a row tile past the end reads
-    // tile 0 and is discarded) so the compiler can count them precisely
-    T an[GEMM_TILES_PER_WAVE][S];
-    bool okn[GEMM_TILES_PER_WAVE];
-    auto load = [&](unsigned long long grp) {
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-            unsigned long long t = (grp * 4 + wave) * GEMM_TILES_PER_WAVE + rt;
-            okn[rt] = grp < groups && t < tiles;
-            long long base =
-                a0 + l16 + (long long)((pext_runs(okn[rt] ? t : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << (4 + nk));
-#pragma unroll
-            for (int s = 0; s < S; ++s) an[rt][s] = arena[base + 16 * (4 * s + g)];
-        }
-    };
-    load(blockIdx.x);
-    __syncthreads();
-    double vmax = 0.0;
-    for (unsigned long long grp = blockIdx.x; grp < groups; grp += gridDim.x) {
-        T a[GEMM_TILES_PER_WAVE][S];
-        bool ok[GEMM_TILES_PER_WAVE];
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-            ok[rt] = okn[rt];
-#pragma unroll
-            for (int s = 0; s < S; ++s) a[rt][s] = an[rt][s];
-        }
-        unsigned long long thi[GEMM_TILES_PER_WAVE];
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-            unsigned long long t = (grp * 4 + wave) * GEMM_TILES_PER_WAVE + rt;
-            thi[rt] = pext_runs(ok[rt] ? (t << 4) : 0, d.run[GR_MU_C], d.nrun[GR_MU_C]);
-        }
-        load(grp + gridDim.x);
-        acc_t acc[GEMM_TILES_PER_WAVE][NT];
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-#pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                T b = Bs[(4 * s + g) * LDN + ct * 16 + l16];
-#pragma unroll
-                for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
-                    acc[rt][ct] = Mfma<T>::step(a[rt][s], b, acc[rt][ct]);
-            }
-        }
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-            if (!ok[rt]) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const unsigned long long rc = thi[rt] | rlo[v];
-#pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    if (NT == 1 && l16 >= N) continue;
-                    T sv = (T)((double)acc[rt][ct][v] * scale);
-                    arena[c0 + (long long)(rc | cols[ct])] = sv;
-                    vmax = fmax(vmax, fabs((double)sv));
-                }
-            }
-        }
-    }
-    publish_max(meta, d.tc, vmax);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-        meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
-}
-
-// LDS a workgroup may use for B, from the device's per-block limit (kept to
-// at most 96 KiB so that two workgroups share a CU).
-static int lds_budget() {
-    static int budget[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return GEMM_LDS_BYTES;
-    if (!budget[dev]) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
-        budget[dev] = v >= 96 * 1024 ? 96 * 1024 : GEMM_LDS_BYTES;
-    }
-    return budget[dev];
-}
-
-template <typename T>
-static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_meta *meta, hipStream_t st) {
-    const int N = 1 << hd.nn, K = 1 << hd.nk;
-    const int NT = (N + 15) / 16;
-    const unsigned long long tiles = 1ull << (hd.nm - 4);
-    const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;
-    const size_t full = (size_t)K * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
-    const size_t padded = (size_t)K * (NT * 16 + (sizeof(T) == 8 ? 2 : 4)) * sizeof(T);
-    if (K >= 4 && K <= 64 && padded <= (size_t)lds_budget()) {
-        const unsigned long long per_beta = (512ull + (1ull << hd.nb) - 1) >> hd.nb;
-        dim3 grid((unsigned)(groups < per_beta ? groups : (per_beta ? per_beta : 1)), 1u << hd.nb);
-        const int NTp = NT <= 1 ? 1 : NT <= 2 ? 2 : NT <= 4 ? 4 : 8;
-#define WMC_GP(NTV, SV)                                                                                   \
-    if (NTp == NTV && K / 4 == SV) {                                                                       \
-        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV>), grid, dim3(256), padded, st, dd, arena, meta);       \
-        return;                                                                                        \
-    }
-#define WMC_GP_S(NTV) WMC_GP(NTV, 1) WMC_GP(NTV, 2) WMC_GP(NTV, 4) WMC_GP(NTV, 8) WMC_GP(NTV, 16)
-        WMC_GP_S(1) WMC_GP_S(2) WMC_GP_S(4) WMC_GP_S(8)
-#undef WMC_GP_S
-#undef WMC_GP
-    }
-    (void)full;
-    const int KC = gemm_kc(hd.nk, hd.nn, (int)sizeof(T));
-    const size_t smem = (size_t)KC * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
-    dim3 grid((unsigned)groups, 1u << hd.nb);
-    if (NT <= 1) hipLaunchKernelGGL((k_gemm<T, 1>), grid, dim3(256), smem, st, dd, arena, meta);
-    else if (NT <= 2) hipLaunchKernelGGL((k_gemm<T, 2>), grid, dim3(256), smem, st, dd, arena, meta);
-    else if (NT <= 4) hipLaunchKernelGGL((k_gemm<T, 4>), grid, dim3(256), smem, st, dd, arena, meta);
-    else hipLaunchKernelGGL((k_gemm<T, 8>), grid, dim3(256), smem, st, dd, arena, meta);
-}
-
-// ---------------------------------------------------------------------------
-// Streaming contraction for one big node with a small summed dimension
-// (K = 2^nk <= 8): Hadamard scaling, a single summed variable, outer
-// products.  HBM-bound.  The operands' storage orders follow C's, so the
-// address of A for output r is r with the bits A lacks (C's "holes" for A)
-// removed, times K; B's is the few bits of r that B owns, gathered, times K.
-// Both bit lists arrive by value in the kernel arguments (scalar registers).
-// Every thread produces 4 consecutive outputs (one 32-byte FP64 / 16-byte
-// FP32 store); when C's two lowest bits belong to A the 4 rows of A are one
-// contiguous run of 4K elements, loaded with 16-byte vector loads.  B is
-// staged in LDS (scaled by its power of two) when it has at most 2^12
-// entries.
-// ---------------------------------------------------------------------------
-#define STREAM_B_LDS 4096
-#define STREAM_MAX_HOLES 8
-#define STREAM_MAX_BBITS 14
-
-struct StreamArgs {
-    long long a, b, c;
-    int ta, tb, tc;
-    int rc;
-    int nhole;                      // C bit positions not in A, ascending
-    int hole[STREAM_MAX_HOLES];
-    int nbbit;                      // C bit positions owned by B, ascending
-    int bbit[STREAM_MAX_BBITS];
-    int rb;                         // storage rank of B
-    int b_lds;
-    int low_contig;                 // C bits 0 and 1 both belong to A
-};
-
-template <typename T> struct Vec4;
-template <> struct Vec4<double> {
-    static __device__ __forceinline__ void store(double *p, double a, double b, double c, double d) {
-        double2 *q = (double2 *)p;
-        q[0] = make_double2(a, b);
-        q[1] = make_double2(c, d);
-    }
-};
-template <> struct Vec4<float> {
-    static __device__ __forceinline__ void store(float *p, double a, double b, double c, double d) {
-        *(float4 *)p = make_float4((float)a, (float)b, (float)c, (float)d);
-    }
-};
-
-__device__ __forceinline__ unsigned long long drop_holes(unsigned long long r, const StreamArgs &s) {
-#pragma unroll
-    for (int i = STREAM_MAX_HOLES - 1; i >= 0; --i) {
-        if (i < s.nhole) {
-            const int h = s.hole[i];
-            r = ((r >> (h + 1)) << h) | (r & ((1ull << h) - 1ull));
-        }
-    }
-    return r;
-}
-
-__device__ __forceinline__ unsigned long long gather_bits(unsigned long long r, const StreamArgs &s) {
-    unsigned long long out = 0;
-#pragma unroll
-    for (int i = 0; i < STREAM_MAX_BBITS; ++i)
-        if (i < s.nbbit) out |= ((r >> s.bbit[i]) & 1ull) << i;
-    return out;
-}
-
-template <typename T, int NK>
-__global__ void __launch_bounds__(256) k_stream(const StreamArgs args, T *__restrict__ arena, wmc_meta *meta) {
-    __shared__ double Bs[STREAM_B_LDS];
-    constexpr int K = 1 << NK;
-    const int sA = scale_exp(meta[args.ta].maxbits);
-    const int sB = scale_exp(meta[args.tb].maxbits);
-    const double scaleB = ldexp(1.0, -sB), scaleA = ldexp(1.0, -sA);
-    const T *__restrict__ A = arena + args.a;
-    const T *__restrict__ B = arena + args.b;
-    T *__restrict__ C = arena + args.c;
-    if (args.b_lds) {
-        for (int i = threadIdx.x; i < (1 << args.rb); i += 256) Bs[i] = (double)B[i] * scaleB;
-        __syncthreads();
-    }
-    const unsigned long long quads = (1ull << args.rc) >> 2;
-    double vmax = 0.0;
-    for (unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; q < quads;
-         q += (unsigned long long)gridDim.x * blockDim.x) {
-        double av[4][K];
-        if (args.low_contig) {
-            const unsigned long long pa = drop_holes(q << 2, args) << NK;
-            const T *p = A + pa;
-            if (sizeof(T) == 8) {
-#pragma unroll
-                for (int i = 0; i < 2 * K; ++i) {
-                    double2 v = ((const double2 *)p)[i];
-                    av[(2 * i) / K][(2 * i) % K] = v.x;
-                    av[(2 * i + 1) / K][(2 * i + 1) % K] = v.y;
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    float4 v = ((const float4 *)p)[i];
-                    av[(4 * i) / K][(4 * i) % K] = v.x;
-                    av[(4 * i + 1) / K][(4 * i + 1) % K] = v.y;
-                    av[(4 * i + 2) / K][(4 * i + 2) % K] = v.z;
-                    av[(4 * i + 3) / K][(4 * i + 3) % K] = v.w;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const unsigned long long pa = drop_holes((q << 2) | (unsigned long long)e, args) << NK;
-#pragma unroll
-                for (int j = 0; j < K; ++j) av[e][j] = (double)A[pa + j];
-            }
-        }
-        double o[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const unsigned long long pb = gather_bits((q << 2) | (unsigned long long)e, args) << NK;
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const double bv = args.b_lds ? Bs[pb + j] : (double)B[pb + j] * scaleB;
-                acc = fma(av[e][j], bv, acc);
-            }
-            o[e] = acc * scaleA;
-        }
-        Vec4<T>::store(C + (q << 2), o[0], o[1], o[2], o[3]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs((double)(T)o[e]));
-    }
-    publish_max(meta, args.tc, vmax);
-    if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
-}
-
-// Streaming arguments for a single-node launch, if the node fits the kernel.
-static bool stream_args(const NodeDesc &d, StreamArgs *a) {
-    if (d.rc < 2 || d.nk > 3) return false;
-    std::memset(a, 0, sizeof *a);
-    a->a = d.a;
-    a->b = d.b;
-    a->c = d.c;
-    a->ta = d.ta;
-    a->tb = d.tb;
-    a->tc = d.tc;
-    a->rc = d.rc;
-    std::vector<int> inA((size_t)d.rc, 0);
-    for (int q = 0; q < d.nra; ++q)
-        for (int j = 0; j < d.ra[q][1]; ++j) inA[(size_t)(d.ra[q][0] + j)] = 1;
-    for (int p = 0; p < d.rc; ++p)
-        if (!inA[(size_t)p]) {
-            if (a->nhole >= STREAM_MAX_HOLES) return false;
-            a->hole[a->nhole++] = p;
-        }
-    for (int q = 0; q < d.nrb; ++q)
-        for (int j = 0; j < d.rb[q][1]; ++j) {
-            if (a->nbbit >= STREAM_MAX_BBITS) return false;
-            a->bbit[a->nbbit++] = d.rb[q][0] + j;
-        }
-    // gather order must match the runs' destination order (ascending in C)
-    for (int i = 1; i < a->nbbit; ++i)
-        if (a->bbit[i] < a->bbit[i - 1]) return false;
-    a->rb = d.nk + a->nbbit;
-    a->b_lds = a->rb <= 12;
-    a->low_contig = inA[0] && inA[1];
-    return true;
-}
-
-template <typename T>
-static void launch_stream(const StreamArgs &sa, T *arena, wmc_meta *meta, hipStream_t st, int nk) {
-    const unsigned long long quads = (1ull << sa.rc) >> 2;
-    unsigned long long blocks = (quads + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    switch (nk) {
-    case 0: hipLaunchKernelGGL((k_stream<T, 0>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    case 1: hipLaunchKernelGGL((k_stream<T, 1>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    case 2: hipLaunchKernelGGL((k_stream<T, 2>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    default: hipLaunchKernelGGL((k_stream<T, 3>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    }
-}
-
-// Root of one slice: fold its value into the running sum (s + c) * 2^e.
-template <typename T>
-__global__ void k_finish(const T *__restrict__ arena, long long root_off, const wmc_meta *meta, int root,
-                         wmc_acc *acc) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double v = (double)arena[root_off];
-    long long e = meta[root].exp;
-    if (v != 0.0) {
-        int k;
-        v = frexp(v, &k);
-        e += k;
-    } else {
-        e = 0;
-    }
-    acc->last_m = v;
-    acc->last_e = e;
-    if (v == 0.0) return;
-    if (acc->s == 0.0 && acc->c == 0.0) {
-        acc->s = v;
-        acc->c = 0.0;
-        acc->e = e;
-    } else {
-        if (e > acc->e) {
-            long long d = acc->e - e;
-            int di = d < -4000 ? -4000 : (int)d;
-            acc->s = ldexp(acc->s, di);
-            acc->c = ldexp(acc->c, di);
-            acc->e = e;
-        }
-        long long d = e - acc->e;
-        double t = ldexp(v, d < -4000 ? -4000 : (int)d);
-        double s = acc->s + t;
-        if (fabs(acc->s) >= fabs(t)) acc->c += (acc->s - s) + t;
-        else acc->c += (t - s) + acc->s;
-        acc->s = s;
-        if (acc->s != 0.0) {
-            int k;
-            acc->s = frexp(acc->s, &k);
-            acc->c = ldexp(acc->c, -k);
-            acc->e += k;
-        }
-    }
-    acc->n_added += 1;
-}
-
-// ---------------------------------------------------------------------------
-// host side
-// ---------------------------------------------------------------------------
-static wmc_value make_value(double m, long long e) {
-    wmc_value v;
-    if (m == 0.0 || !std::isfinite(m)) {
-        v.mantissa = m == 0.0 ? 0.0 : m;
-        v.exp2 = 0;
-        v.value = m;
-        v.log2_abs = m == 0.0 ? -INFINITY : NAN;
-        return v;
-    }
-    int k;
-    double mm = std::frexp(m, &k);
-    v.mantissa = mm;
-    v.exp2 = e + k;
-    long long ee = v.exp2;
-    v.value = std::ldexp(mm, ee > 5000 ? 5000 : (ee < -5000 ? -5000 : (int)ee));
-    v.log2_abs = std::log2(std::fabs(mm)) + (double)v.exp2;
-    return v;
-}
-
-static unsigned grid_for(long long work) {
-    long long b = (work + WMC_BLOCK - 1) / WMC_BLOCK;
-    if (b < 1) b = 1;
-    if (b > (1ll << 20)) b = 1ll << 20;
-    return (unsigned)b;
-}
-
-#define HIP_TRY(call)                                                                     \
-    do {                                                                                  \
-        hipError_t _e = (call);                                                           \
-        if (_e != hipSuccess) {                                                           \
-            wmc_set_error("%s failed: %s", #call, hipGetErrorString(_e));                 \
-            return WMC_ERR_DEVICE;                                                        \
-        }                                                                                 \
-    } while (0)
+// Execution stage on gfx950 for one plan: the pairwise contractions of
+// Algorithm 2 over the slices of Algorithm 3, all on the device.  Kernels
+// and their numerics are in wmc_kernels.h.
+#include "wmc_kernels.h"
 
 // Optional per-launch timing: an event is recorded on the stream after every
 // launch; ms[k] accumulates launch k's duration over the slices.

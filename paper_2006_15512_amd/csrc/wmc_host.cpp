@@ -341,11 +341,85 @@ struct TreeBuilder {
     }
 };
 
-// Bucket tree from an elimination order: for each block of `block`
-// consecutive variables, gather every live tensor that holds one of them
-// plus their weight leaves A_x, and merge the bucket pairwise.
+// Rank bookkeeping of a bucket merge without building tensors: the same
+// greedy pair choice as TreeBuilder::merge_all; returns the largest rank of
+// any tensor it would create.
+struct SimT {
+    std::vector<int32_t> vars, cnt;
+};
+
+static int32_t sim_merge_all(std::vector<SimT> b, const std::vector<int32_t> &total) {
+    int32_t mx = 0;
+    auto merged = [&](const SimT &A, const SimT &B, SimT *out) {
+        int32_t r = 0;
+        size_t i = 0, j = 0;
+        while (i < A.vars.size() || j < B.vars.size()) {
+            int32_t v, c;
+            if (j == B.vars.size() || (i < A.vars.size() && A.vars[i] < B.vars[j])) {
+                v = A.vars[i];
+                c = A.cnt[i++];
+            } else if (i == A.vars.size() || B.vars[j] < A.vars[i]) {
+                v = B.vars[j];
+                c = B.cnt[j++];
+            } else {
+                v = A.vars[i];
+                c = A.cnt[i++] + B.cnt[j++];
+            }
+            if (c < total[(size_t)v]) {
+                ++r;
+                if (out) {
+                    out->vars.push_back(v);
+                    out->cnt.push_back(c);
+                }
+            }
+        }
+        return r;
+    };
+    while (b.size() > 1) {
+        size_t bi = 0, bj = 1;
+        int64_t k0b = INT64_MAX, k1b = INT64_MAX;
+        for (size_t i = 0; i < b.size(); ++i)
+            for (size_t j = i + 1; j < b.size(); ++j) {
+                int64_t k0 = merged(b[i], b[j], nullptr);
+                int64_t k1 = (int64_t)b[i].vars.size() + (int64_t)b[j].vars.size();
+                if (k0 < k0b || (k0 == k0b && k1 < k1b)) {
+                    k0b = k0;
+                    k1b = k1;
+                    bi = i;
+                    bj = j;
+                }
+            }
+        SimT m;
+        merged(b[bi], b[bj], &m);
+        mx = std::max(mx, (int32_t)m.vars.size());
+        b.erase(b.begin() + (std::ptrdiff_t)bj);
+        b[bi] = std::move(m);
+    }
+    return mx;
+}
+
+static int32_t bucket_tree_fixed(const wmc_network &net, const std::vector<int32_t> &order, int32_t block,
+                                 int32_t rank_limit, std::vector<TNode> &T);
+
+// Bucket tree from an elimination order: each step gathers every live tensor
+// that holds one of the step's variables plus their weight leaves A_x, and
+// merges the bucket pairwise.  A step eliminates up to `block` consecutive
+// variables; a variable joins the current step only if it already occurs in
+// the step's tensors and the step's merges (simulated) create no tensor of
+// rank above the one-variable-per-step tree's maximum.
 static int32_t bucket_tree(const wmc_network &net, const std::vector<int32_t> &order, int32_t block,
                            std::vector<TNode> &T) {
+    if (block <= 1) return bucket_tree_fixed(net, order, 1, 0, T);
+    std::vector<TNode> probe;
+    int32_t r = bucket_tree_fixed(net, order, 1, 0, probe);
+    if (r < 0) return bucket_tree_fixed(net, order, 1, 0, T);
+    int32_t limit = 0;
+    for (const TNode &t : probe) limit = std::max(limit, (int32_t)t.vars.size());
+    return bucket_tree_fixed(net, order, block, limit, T);
+}
+
+static int32_t bucket_tree_fixed(const wmc_network &net, const std::vector<int32_t> &order, int32_t block,
+                                 int32_t rank_limit, std::vector<TNode> &T) {
     TreeBuilder tb(net, T);
     const int32_t n = net.n;
     std::vector<uint8_t> alive;
@@ -362,10 +436,49 @@ static int32_t bucket_tree(const wmc_network &net, const std::vector<int32_t> &o
     for (int32_t x = 1; x <= n; ++x)
         if (net.degree[(size_t)x - 1] == 0) add_alive(tb.leaf_weight(x));
     if (block < 1) block = 1;
-    std::vector<uint8_t> in_bucket;
-    for (size_t s = 0; s < order.size(); s += (size_t)block) {
+    // live tensors holding any of the variables order[s..e)
+    std::vector<int32_t> seen_stamp;
+    int32_t stamp = 0;
+    auto members = [&](size_t s, size_t e, std::vector<int32_t> &out) {
+        ++stamp;
+        if (seen_stamp.size() < T.size()) seen_stamp.resize(T.size(), 0);
+        out.clear();
+        for (size_t q = s; q < e; ++q) {
+            int32_t x = order[q];
+            for (int32_t id : holders[(size_t)x]) {
+                if (!alive[(size_t)id] || seen_stamp[(size_t)id] == stamp) continue;
+                const std::vector<int32_t> &vs = T[(size_t)id].vars;
+                if (!std::binary_search(vs.begin(), vs.end(), x)) continue;
+                seen_stamp[(size_t)id] = stamp;
+                out.push_back(id);
+            }
+        }
+    };
+    std::vector<int32_t> cand;
+    for (size_t s = 0; s < order.size();) {
+        size_t e = s + 1;
+        while (block > 1 && e < order.size() && e < s + (size_t)block) {
+            // the next variable must already occur in the step's tensors, so
+            // the step's result is what eliminating it next would give anyway
+            members(s, e, cand);
+            bool adjacent = false;
+            for (int32_t id : cand) {
+                const std::vector<int32_t> &vs = T[(size_t)id].vars;
+                if (std::binary_search(vs.begin(), vs.end(), order[e])) adjacent = true;
+            }
+            if (!adjacent) break;
+            members(s, e + 1, cand);
+            std::vector<SimT> sim;
+            for (int32_t id : cand) sim.push_back({T[(size_t)id].vars, T[(size_t)id].cnt});
+            for (size_t q = s; q <= e; ++q) {
+                int32_t x = order[q];
+                if (net.degree[(size_t)x - 1] > 0) sim.push_back({{x}, {1}});
+            }
+            if (sim_merge_all(sim, tb.total) > rank_limit) break;
+            ++e;
+        }
         std::vector<int32_t> bucket;
-        for (size_t q = s; q < std::min(order.size(), s + (size_t)block); ++q) {
+        for (size_t q = s; q < e; ++q) {
             int32_t x = order[q];
             if (net.degree[(size_t)x - 1] == 0) continue;
             for (int32_t id : holders[(size_t)x]) {
@@ -380,6 +493,7 @@ static int32_t bucket_tree(const wmc_network &net, const std::vector<int32_t> &o
             if ((size_t)wl >= alive.size()) alive.resize((size_t)wl + 1, 0);
             bucket.push_back(wl);
         }
+        s = e;
         if (bucket.empty()) continue;
         std::sort(bucket.begin(), bucket.end());
         int32_t r = tb.merge_all(bucket);
@@ -925,7 +1039,7 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
                 const TNode &X = T[(size_t)(which ? C.b : C.a)];
                 ++stamp;
                 for (int32_t v : X.vars) mark[(size_t)v] = stamp;
-                unsigned char(*runs)[3] = which ? d.rb : d.ra;
+                unsigned *runs = which ? d.rb : d.ra;
                 int nr = 0, dst = 0;
                 for (int j = 0; j < d.rc;) {
                     if (mark[(size_t)C.layout[(size_t)j]] != stamp) {
@@ -936,9 +1050,7 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
                     while (j < d.rc && mark[(size_t)C.layout[(size_t)j]] == stamp) ++j;
                     if (nr >= WMC_MAX_RUNS)
                         WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_plan: node %d needs more than %d runs", id, WMC_MAX_RUNS);
-                    runs[nr][0] = (unsigned char)s0;
-                    runs[nr][1] = (unsigned char)(j - s0);
-                    runs[nr][2] = (unsigned char)dst;
+                    runs[nr] = WMC_RUN(s0, j - s0, dst);
                     dst += j - s0;
                     ++nr;
                 }

@@ -20,9 +20,9 @@ LEAF = np.dtype([("out", "<i8"), ("work_begin", "<i8"), ("tensor", "<i4"), ("kin
 NODE = np.dtype({"names": ["a", "b", "c", "work_begin", "ta", "tb", "tc", "rc", "nk", "nra", "nrb", "cls",
                            "ra", "rb"],
                  "formats": ["<i8", "<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4",
-                             ("u1", (20, 3)), ("u1", (20, 3))],
-                 "offsets": [0, 8, 16, 24, 32, 36, 40, 44, 48, 52, 56, 60, 64, 124],
-                 "itemsize": 200})
+                             ("<u4", (20,)), ("<u4", (20,))],
+                 "offsets": [0, 8, 16, 24, 32, 36, 40, 44, 48, 52, 56, 60, 64, 144],
+                 "itemsize": 224})
 LAUNCH = np.dtype([("type", "<i4"), ("first", "<i4"), ("count", "<i4"), ("pad", "<i4"), ("work", "<i8")])
 GEMM = np.dtype({"names": ["a", "b", "c", "ta", "tb", "tc", "nk", "nm", "nn", "nb", "nrun", "run"],
                  "formats": ["<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", ("<i4", (7,)),
@@ -48,9 +48,16 @@ def parse(plan):
 
 
 def _pext(r: np.ndarray, runs, nr: int) -> np.ndarray:
+    """Bit extraction along runs given as (src, len, dst) triples or packed
+    words src | len << 8 | dst << 16."""
     out = np.zeros_like(r)
     for q in range(nr):
-        s, l, d = (int(x) for x in runs[q])
+        run = runs[q]
+        if np.ndim(run) == 0:
+            w = int(run)
+            s, l, d = w & 255, (w >> 8) & 255, w >> 16
+        else:
+            s, l, d = (int(x) for x in run)
         out |= ((r >> np.uint64(s)) & np.uint64((1 << l) - 1)) << np.uint64(d)
     return out
 
@@ -59,6 +66,86 @@ def _sexp(m: float) -> int:
     if not m > 0.0:
         return 0
     return math.frexp(m)[1]
+
+
+def _replay(leaves, nodes, launches, gemms, arena_elems, nt, w, store, eta, roots, root_offs):
+    """One pass of the launch list; returns the exact value of each root."""
+    arena = np.zeros(max(arena_elems, 1), dtype=store)
+    maxv = np.zeros(max(nt, 1))
+    ex = np.zeros(max(nt, 1), dtype=np.int64)
+    for d in leaves:
+        size = 1 << int(d["rank"])
+        e = np.arange(size, dtype=np.int64)
+        if d["kind"] == 0:
+            a = np.zeros(size, dtype=np.int64)
+            for q in range(int(d["k"])):
+                p = int(d["pos"][q])
+                bit = (e >> p) & 1 if p >= 0 else np.full(size, (eta >> (-p - 1)) & 1)
+                a |= bit << q
+            v = np.where((a != int(d["falsify"])) | bool(d["taut"]), 1.0, 0.0)
+        elif d["kind"] == 1:
+            p = int(d["pos"][0])
+            bit = (e >> p) & 1 if p >= 0 else np.full(size, (eta >> (-p - 1)) & 1)
+            v = w[2 * int(d["var"]) + bit]
+        else:
+            v = np.array([w[2 * int(d["var"])] + w[2 * int(d["var"]) + 1]])
+        s = v.astype(store)
+        arena[int(d["out"]): int(d["out"]) + size] = s
+        maxv[int(d["tensor"])] = float(np.max(np.abs(s.astype(np.float64))))
+    for L in launches[1:]:
+        results = []
+        if int(L["type"]) == 2:
+            g = gemms[int(L["pad"])]
+            nk, nm, nn, nb = (int(g[k]) for k in ("nk", "nm", "nn", "nb"))
+            runs = lambda q: (g["run"][q], int(g["nrun"][q]))
+            mu = np.arange(1 << nm, dtype=np.uint64)
+            nu = np.arange(1 << nn, dtype=np.uint64)
+            sA, sB = _sexp(maxv[int(g["ta"])]), _sexp(maxv[int(g["tb"])])
+            outs = []
+            for beta in range(1 << nb):
+                bt = np.array([beta], dtype=np.uint64)
+                # A is stored [4 lowest mu bits | kappa | rest]
+                rows = (mu & np.uint64(15)) | \
+                    ((_pext(mu >> np.uint64(4), *runs(GR_MU_A)) | _pext(bt, *runs(GR_BETA_A))) << np.uint64(4 + nk))
+                cols = (_pext(nu, *runs(GR_NU_B)) | _pext(bt, *runs(GR_BETA_B))) << np.uint64(nk)
+                kk = np.arange(1 << nk, dtype=np.uint64)
+                Am = arena[int(g["a"]) + (rows[:, None] + (kk[None, :] << np.uint64(4))).astype(np.int64)].astype(np.float64)
+                Bm = arena[int(g["b"]) + (cols[:, None] + kk[None, :]).astype(np.int64)].astype(np.float64)
+                Cm = np.ldexp(Am @ Bm.T, -(sA + sB)).astype(store)
+                addr = (_pext(mu, *runs(GR_MU_C))[:, None] | _pext(nu, *runs(GR_NU_C))[None, :] |
+                        _pext(bt, *runs(GR_BETA_C)))
+                outs.append((addr.astype(np.int64).ravel(), Cm.ravel()))
+            mx = 0.0
+            for addr, val in outs:
+                arena[int(g["c"]) + addr] = val
+                mx = max(mx, float(np.max(np.abs(val.astype(np.float64)))))
+            maxv[int(g["tc"])] = mx
+            ex[int(g["tc"])] = ex[int(g["ta"])] + ex[int(g["tb"])] + sA + sB
+            continue
+        for d in nodes[int(L["first"]): int(L["first"]) + int(L["count"])]:
+            rc, nk = int(d["rc"]), int(d["nk"])
+            r = np.arange(1 << rc, dtype=np.uint64)
+            pa = _pext(r, d["ra"], int(d["nra"])) << np.uint64(nk)
+            pb = _pext(r, d["rb"], int(d["nrb"])) << np.uint64(nk)
+            sA, sB = _sexp(maxv[int(d["ta"])]), _sexp(maxv[int(d["tb"])])
+            acc = np.zeros(1 << rc)
+            for j in range(1 << nk):
+                acc += arena[int(d["a"]) + (pa + np.uint64(j)).astype(np.int64)].astype(np.float64) * \
+                       arena[int(d["b"]) + (pb + np.uint64(j)).astype(np.int64)].astype(np.float64)
+            out = np.ldexp(acc, -(sA + sB)).astype(store)
+            results.append((d, out, int(ex[int(d["ta"])] + ex[int(d["tb"])] + sA + sB)))
+        for d, out, e in results:
+            arena[int(d["c"]): int(d["c"]) + out.size] = out
+            maxv[int(d["tc"])] = float(np.max(np.abs(out.astype(np.float64))))
+            ex[int(d["tc"])] = e
+    vals = []
+    for root, off in zip(roots, root_offs):
+        if root < 0:
+            vals.append(Fraction(1))
+            continue
+        v = float(arena[int(off)])
+        vals.append(Fraction(v) * (Fraction(2) ** int(ex[int(root)])))
+    return vals
 
 
 def emulate(plan, weights, store=np.float64, slices=None):
@@ -70,84 +157,36 @@ def emulate(plan, weights, store=np.float64, slices=None):
     root = info["root"]
     if root < 0:
         return Fraction(1), [Fraction(1)]
-    arena = np.zeros(max(info["arena_elems"], 1), dtype=store)
-    nt = info["n_tensors"]
     n_slices = 1 << len(plan.stats()["sliced_vars"])
     total = Fraction(0)
     per = []
     for eta in (range(n_slices) if slices is None else slices):
-        maxv = np.zeros(nt)
-        ex = np.zeros(nt, dtype=np.int64)
-        for d in leaves:
-            size = 1 << int(d["rank"])
-            e = np.arange(size, dtype=np.int64)
-            if d["kind"] == 0:
-                a = np.zeros(size, dtype=np.int64)
-                for q in range(int(d["k"])):
-                    p = int(d["pos"][q])
-                    bit = (e >> p) & 1 if p >= 0 else np.full(size, (eta >> (-p - 1)) & 1)
-                    a |= bit << q
-                v = np.where((a != int(d["falsify"])) | bool(d["taut"]), 1.0, 0.0)
-            elif d["kind"] == 1:
-                p = int(d["pos"][0])
-                bit = (e >> p) & 1 if p >= 0 else np.full(size, (eta >> (-p - 1)) & 1)
-                v = w[2 * int(d["var"]) + bit]
-            else:
-                v = np.array([w[2 * int(d["var"])] + w[2 * int(d["var"]) + 1]])
-            s = v.astype(store)
-            arena[int(d["out"]): int(d["out"]) + size] = s
-            maxv[int(d["tensor"])] = float(np.max(np.abs(s.astype(np.float64))))
-        for L in launches[1:]:
-            results = []
-            if int(L["type"]) == 2:
-                g = gemms[int(L["pad"])]
-                nk, nm, nn, nb = (int(g[k]) for k in ("nk", "nm", "nn", "nb"))
-                runs = lambda q: (g["run"][q], int(g["nrun"][q]))
-                mu = np.arange(1 << nm, dtype=np.uint64)
-                nu = np.arange(1 << nn, dtype=np.uint64)
-                sA, sB = _sexp(maxv[int(g["ta"])]), _sexp(maxv[int(g["tb"])])
-                outs = []
-                for beta in range(1 << nb):
-                    bt = np.array([beta], dtype=np.uint64)
-                    # A is stored [4 lowest mu bits | kappa | rest]
-                    rows = (mu & np.uint64(15)) | \
-                        ((_pext(mu >> np.uint64(4), *runs(GR_MU_A)) | _pext(bt, *runs(GR_BETA_A))) << np.uint64(4 + nk))
-                    cols = (_pext(nu, *runs(GR_NU_B)) | _pext(bt, *runs(GR_BETA_B))) << np.uint64(nk)
-                    kk = np.arange(1 << nk, dtype=np.uint64)
-                    Am = arena[int(g["a"]) + (rows[:, None] + (kk[None, :] << np.uint64(4))).astype(np.int64)].astype(np.float64)
-                    Bm = arena[int(g["b"]) + (cols[:, None] + kk[None, :]).astype(np.int64)].astype(np.float64)
-                    Cm = np.ldexp(Am @ Bm.T, -(sA + sB)).astype(store)
-                    addr = (_pext(mu, *runs(GR_MU_C))[:, None] | _pext(nu, *runs(GR_NU_C))[None, :] |
-                            _pext(bt, *runs(GR_BETA_C)))
-                    outs.append((addr.astype(np.int64).ravel(), Cm.ravel()))
-                mx = 0.0
-                for addr, val in outs:
-                    arena[int(g["c"]) + addr] = val
-                    mx = max(mx, float(np.max(np.abs(val.astype(np.float64)))))
-                maxv[int(g["tc"])] = mx
-                ex[int(g["tc"])] = ex[int(g["ta"])] + ex[int(g["tb"])] + sA + sB
-                continue
-            for d in nodes[int(L["first"]): int(L["first"]) + int(L["count"])]:
-                rc, nk = int(d["rc"]), int(d["nk"])
-                r = np.arange(1 << rc, dtype=np.uint64)
-                pa = _pext(r, d["ra"], int(d["nra"])) << np.uint64(nk)
-                pb = _pext(r, d["rb"], int(d["nrb"])) << np.uint64(nk)
-                sA, sB = _sexp(maxv[int(d["ta"])]), _sexp(maxv[int(d["tb"])])
-                acc = np.zeros(1 << rc)
-                for j in range(1 << nk):
-                    acc += arena[int(d["a"]) + (pa + np.uint64(j)).astype(np.int64)].astype(np.float64) * \
-                           arena[int(d["b"]) + (pb + np.uint64(j)).astype(np.int64)].astype(np.float64)
-                out = np.ldexp(acc, -(sA + sB)).astype(store)
-                results.append((d, out, int(ex[int(d["ta"])] + ex[int(d["tb"])] + sA + sB)))
-            for d, out, e in results:
-                arena[int(d["c"]): int(d["c"]) + out.size] = out
-                maxv[int(d["tc"])] = float(np.max(np.abs(out.astype(np.float64))))
-                ex[int(d["tc"])] = e
-        v = float(arena[info["root_off"]])
-        val = Fraction(v) * (Fraction(2) ** int(ex[root]))
+        (val,) = _replay(leaves, nodes, launches, gemms, info["arena_elems"], info["n_tensors"], w, store, eta,
+                         [root], [info["root_off"]])
         per.append(val)
         total += val
     return total, per
+
+
+def emulate_batch(batch, weights, store=np.float64):
+    """Replay a batch's merged descriptors; returns one exact value per instance."""
+    img, info = batch.image()
+    nl, nn, nla, ng, n = info["n_leaves"], info["n_nodes"], info["n_launches"], info["n_gemms"], info["n_instances"]
+    off = 0
+    leaves = np.frombuffer(img, LEAF, count=nl, offset=off)
+    off += nl * LEAF.itemsize
+    nodes = np.frombuffer(img, NODE, count=nn, offset=off)
+    off += nn * NODE.itemsize
+    launches = np.frombuffer(img, LAUNCH, count=nla, offset=off)
+    off += nla * LAUNCH.itemsize
+    gemms = np.frombuffer(img, GEMM, count=ng, offset=off)
+    off += ng * GEMM.itemsize
+    roots = np.frombuffer(img, "<i4", count=n, offset=off)
+    off += 4 * n
+    root_offs = np.frombuffer(img, "<i8", count=n, offset=off)
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    return _replay(leaves, nodes, launches, gemms, info["arena_elems"], info["meta_total"], w, store, 0,
+                   list(roots), list(root_offs))
 
 
 def to_float(x: Fraction) -> float:

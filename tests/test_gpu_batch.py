@@ -1,0 +1,102 @@
+"""GPU tests of batched execution (many plans in shared launches)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_15512_amd as W
+import wmc_workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def frac(v):
+    return Fraction(0) if v.mantissa == 0.0 else Fraction(v.mantissa) * Fraction(2) ** v.exp2
+
+
+def rel(a, b):
+    return 0.0 if a == b else float(abs(a - b) / max(abs(a), abs(b)))
+
+
+@pytest.fixture(scope="module")
+def instances():
+    fs = [wl.batch_instance(i) for i in range(64)]
+    refs = []
+    for f in fs:
+        m, e = oracle.bucket(f)
+        refs.append(Fraction(m) * Fraction(2) ** e)
+    return fs, refs
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_batch_instances_vs_oracle(instances, precision, tol):
+    """64 instances of the 512-instance batch recipe (n 30-150, ratio
+    3.0-4.2, banded window 20) in one batch, against the oracle."""
+    fs, refs = instances
+    say(f"batch64 {precision}")
+    plans = [W.Plan(W.Network.from_formula(f), seed=i, precision=precision) for i, f in enumerate(fs)]
+    b = W.Batch(plans)
+    vals = b.contract()
+    for i, (v, r) in enumerate(zip(vals, refs)):
+        got = frac(v)
+        assert (got == 0) if r == 0 else rel(got, r) <= tol, i
+
+
+def test_batch_equals_solo_bit_exact(instances):
+    """Every instance's value in the batch is bit-identical to its solo run:
+    the per-node reduction order does not depend on the batch composition."""
+    fs, _ = instances
+    plans = [W.Plan(W.Network.from_formula(f), seed=i, block=1 + i % 3) for i, f in enumerate(fs[:24])]
+    vals = W.Batch(plans).contract()
+    for i, p in enumerate(plans):
+        say(f"solo {i}")
+        solo = W.wmc_contract(p)
+        assert (solo.mantissa, solo.exp2) == (vals[i].mantissa, vals[i].exp2), i
+
+
+def test_batch_graph_replays_match_eager(instances):
+    """Graph capture: replay several times, with eager work in between; every
+    replay equals the eager result; resident descriptors are reused."""
+    import torch
+    fs, _ = instances
+    plans = [W.Plan(W.Network.from_formula(f), seed=i) for i, f in enumerate(fs[:32])]
+    b = W.Batch(plans)
+    ws = b.workspace()
+    eager = b.contract(ws=ws)
+    rng = np.random.default_rng(0)
+    for rep in range(4):
+        say(f"graph replay {rep}")
+        flags = W.BATCH_GRAPH | (W.BATCH_RESIDENT if rep else 0)
+        got = b.contract(ws=ws, flags=flags)
+        assert [(v.mantissa, v.exp2) for v in got] == [(v.mantissa, v.exp2) for v in eager]
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert float(x.sum()) == float(x.sum())
+        _ = W.wmc_contract(plans[rep])
+    # new weights through the same graph (weights are uploaded before each replay)
+    w = []
+    refs = []
+    for f in fs[:32]:
+        ww = rng.uniform(0.1, 0.9, size=f.n)
+        Wt = np.stack([1 - ww, ww], axis=1)
+        w.append(Wt.reshape(-1))
+        m, e = oracle.bucket(f.with_weights(Wt))
+        refs.append(Fraction(m) * Fraction(2) ** e)
+    got = b.contract(np.concatenate(w), ws=ws, flags=W.BATCH_GRAPH | W.BATCH_RESIDENT)
+    for v, r in zip(got, refs):
+        assert (frac(v) == 0) if r == 0 else rel(frac(v), r) <= 1e-12
+
+
+def test_batch_workspace_too_small(instances):
+    import torch
+    fs, _ = instances
+    b = W.Batch([W.Plan(W.Network.from_formula(fs[0]))])
+    ws = torch.empty(b.workspace_bytes - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(W.WmcError) as e:
+        b.contract(ws=ws)
+    assert e.value.status == 2

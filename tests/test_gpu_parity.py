@@ -242,8 +242,9 @@ def test_grid_blocks_vs_oracle(rows, cols, block, precision, tol):
     assert rel(value_fraction(v), Fraction(m) * Fraction(2) ** e) <= tol
 
 
+@pytest.mark.parametrize("block", [1, 3])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_banded300_sliced_vs_golden(precision, tol):
+def test_banded300_sliced_vs_golden(precision, tol, block):
     """Banded random 3-CNF, 300 variables, ratio 3.5: seeded min-fill tree of
     max storage rank 30 sliced to rank 27 (index slicing), against the
     oracle's stored value."""
@@ -251,7 +252,7 @@ def test_banded300_sliced_vs_golden(precision, tol):
     f = wl.banded_3cnf(300, 1050, 37, seed=0)
     assert f.digest() == g["digest"]
     say(f"banded300 {precision}")
-    v, p = run(f, kind="minfill", seed=0, rank_cap=27, precision=precision)
+    v, p = run(f, kind="minfill", seed=0, rank_cap=27, precision=precision, block=block)
     st = p.stats()
     assert st["max_rank"] <= 27 and st["max_rank_unsliced"] == 30 and st["n_slices"] >= 8
     ref = Fraction(float.fromhex(g["mantissa_hex"])) * Fraction(2) ** g["exp2"]
@@ -266,8 +267,8 @@ def test_banded_medium_stream_shapes(seed):
     f = wl.banded_3cnf(120, 400, 24, seed=seed)
     m, e = oracle.bucket(f)
     ref = Fraction(m) * Fraction(2) ** e
-    for kw in (dict(seed=seed), dict(kind="order", order=oracle.minfill_order(f), block=3, rank_cap=24),
-               dict(kind="order", order=oracle.minfill_order(f), block=5, rank_cap=24)):
-        say(f"banded120 seed={seed} {kw.get('block', 1)}")
+    for kw in (dict(seed=seed), dict(kind="order", order=oracle.minfill_order(f), block=3),
+               dict(kind="order", order=oracle.minfill_order(f), block=5), dict(seed=seed, block=4, rank_cap=18)):
+        say(f"banded120 seed={seed} {kw}")
         v, _ = run(f, **kw)
         assert rel(value_fraction(v), ref) <= 1e-12

@@ -285,3 +285,29 @@ def test_emulated_matrix_nodes(rows, cols, block):
     p32 = W.Plan(net, kind="order", order=order, block=block, precision="fp32")
     got32, _ = emulate(p32, f.weights, store=np.float32)
     assert rel_err(got32, ref) < 1e-5
+
+
+def test_emulated_batch_merging():
+    """A batch merges many plans' launch lists by index with patched offsets;
+    the merged descriptors replayed on the CPU give each instance's oracle value."""
+    from plan_emulator import emulate_batch
+    fs = [wl.random_mixed(s, n_max=12, m_max=24) for s in range(30)]
+    fs += [wl.grid_cnf(6, 8, 0.2, seed=1), wl.banded_3cnf(60, 200, 14, seed=3), Formula(0, [], np.zeros((0, 2)))]
+    plans = [W.Plan(W.Network.from_formula(f), seed=i, block=1 + i % 3) for i, f in enumerate(fs)]
+    b = W.Batch(plans)
+    w = np.concatenate([f.weights.reshape(-1) for f in fs])
+    vals = emulate_batch(b, w)
+    for f, v in zip(fs, vals):
+        ref = ref_fraction(f) if f.n else Fraction(1)
+        assert (v == 0) if ref == 0 else rel_err(v, ref) < 1e-12
+
+
+def test_batch_rejects_sliced_and_mixed():
+    f = wl.random_kcnf(14, 50, 3)
+    net = W.Network.from_formula(f)
+    with pytest.raises(W.WmcError) as e:
+        W.Batch([W.Plan(net, seed=0), W.Plan(net, seed=0, rank_cap=4)])
+    assert e.value.status == 6
+    with pytest.raises(W.WmcError) as e:
+        W.Batch([W.Plan(net, seed=0), W.Plan(net, seed=0, precision="fp32")])
+    assert e.value.status == 1
