@@ -232,6 +232,67 @@ void wmc_batch_destroy(wmc_batch *b);
 wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, uint64_t *needed,
                            int64_t *info /* 9 entries */);
 
+/* ------------------------------------------------------------------ */
+/* Serving: weight queries on registered structures, continuous batching */
+/* ------------------------------------------------------------------ */
+/* A server owns a caller-supplied device buffer: a staging area for step
+ * descriptors, a result table, and the request regions (at most
+ * hbm_budget_bytes).  Registered structures are unsliced plans of the
+ * server's precision.  A request (structure, weight vector) waits in a FIFO
+ * queue until a slot is free and a region of its footprint (its plan's meta
+ * table + arena) fits in the budget: admission by HBM footprint.  Each step
+ * runs the next launch of every admitted request's plan in shared kernels;
+ * requests join and leave between steps (continuous batching).  A request's
+ * descriptors are its plan's shifted into its region, so its value is the
+ * same alone or in any mix.  A server is driven by one thread. */
+typedef struct wmc_server wmc_server;
+
+typedef struct {
+    int32_t precision;          /* wmc_precision of every registered plan */
+    int32_t max_slots;          /* requests in flight at once */
+    int32_t max_queue;          /* waiting requests; WMC_ERR_BUSY beyond */
+    int32_t reserved0;
+    uint64_t hbm_budget_bytes;  /* request regions; 0 = all of the buffer left */
+    uint64_t step_bytes;        /* staging per step; 0 = 16 MiB */
+} wmc_serve_options;
+
+typedef struct {
+    uint64_t request_id;
+    int32_t structure;
+    int32_t status;             /* wmc_status */
+    wmc_value value;
+    double t_arrive, t_admit, t_done;  /* seconds from the server's clock origin */
+} wmc_response;
+
+typedef struct {
+    double t_arrive;            /* seconds from the start of the replay */
+    int32_t structure;
+    int32_t reserved0;
+    uint64_t request_id;
+    const double *weights;      /* 2 * n_vars of the structure, host; copied at submission */
+} wmc_request;
+
+typedef struct {
+    uint64_t region_bytes, used_bytes, peak_used_bytes;
+    int64_t peak_active, steps, n_active, n_queued, n_structures;
+} wmc_serve_info;
+
+wmc_status wmc_serve_create(const wmc_serve_options *opts, void *device_buffer, uint64_t bytes,
+                            void *stream, wmc_server **out);
+wmc_status wmc_serve_register(wmc_server *s, const wmc_plan_t *plan, int32_t *structure_id);
+/* Non-blocking: queue one request (WMC_ERR_BUSY if the queue is full). */
+wmc_status wmc_serve_submit(wmc_server *s, int32_t structure, const double *weights,
+                            uint64_t request_id);
+/* Admit what fits, run one step, collect completions (blocks for the step). */
+wmc_status wmc_serve_step(wmc_server *s, int32_t *n_active, int32_t *n_queued);
+/* Move up to max completed responses into out. */
+wmc_status wmc_serve_poll(wmc_server *s, wmc_response *out, int32_t max, int32_t *n_out);
+/* Replay timed arrivals (sorted by t_arrive) until all n complete; out gets
+ * the n responses in completion order. */
+wmc_status wmc_serve(wmc_server *s, const wmc_request *trace, int64_t n, wmc_response *out);
+wmc_status wmc_serve_stats(const wmc_server *s, wmc_serve_info *out);
+void wmc_serve_destroy(wmc_server *s);
+
 /* Thread-local description of the last non-OK status on this thread. */
 const char *wmc_last_error(void);
 

@@ -93,13 +93,20 @@ def lib():
             "wmc_batch_info": [P, P, P, P],
             "wmc_batch_contract": [P, P, P, u64, P, ctypes.c_uint32, P],
             "wmc_batch_image": [P, P, u64, P, P],
+            "wmc_serve_create": [P, P, u64, P, P],
+            "wmc_serve_register": [P, P, P],
+            "wmc_serve_submit": [P, i32, P, u64],
+            "wmc_serve_step": [P, P, P],
+            "wmc_serve_poll": [P, P, i32, P],
+            "wmc_serve": [P, P, i64, P],
+            "wmc_serve_stats": [P, P],
             "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
-        for name in ("wmc_network_destroy", "wmc_plan_destroy", "wmc_batch_destroy"):
+        for name in ("wmc_network_destroy", "wmc_plan_destroy", "wmc_batch_destroy", "wmc_serve_destroy"):
             getattr(L, name).argtypes = [P]
             getattr(L, name).restype = None
         L.wmc_last_error.restype = ctypes.c_char_p
@@ -400,4 +407,121 @@ class Batch:
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None:
             _lib.wmc_batch_destroy(h)
+            self._h = None
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+class wmc_serve_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64), ("step_bytes", ctypes.c_uint64)]
+
+
+class wmc_response(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("structure", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("value", wmc_value), ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class wmc_request(ctypes.Structure):
+    _fields_ = [("t_arrive", ctypes.c_double), ("structure", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("request_id", ctypes.c_uint64), ("weights", ctypes.c_void_p)]
+
+
+class wmc_serve_info(ctypes.Structure):
+    _fields_ = [("region_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64),
+                ("peak_used_bytes", ctypes.c_uint64), ("peak_active", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("n_active", ctypes.c_int64), ("n_queued", ctypes.c_int64), ("n_structures", ctypes.c_int64)]
+
+
+class Response(NamedTuple):
+    request_id: int
+    structure: int
+    status: int
+    value: Value
+    t_arrive: float
+    t_admit: float
+    t_done: float
+
+    @staticmethod
+    def of(r: wmc_response) -> "Response":
+        return Response(int(r.request_id), int(r.structure), int(r.status), Value.of(r.value), r.t_arrive,
+                        r.t_admit, r.t_done)
+
+
+class Server:
+    """wmc_serve_create over a caller-owned device buffer (a torch tensor)."""
+
+    def __init__(self, precision: str = "fp64", max_slots: int = 64, max_queue: int = 1 << 20,
+                 hbm_budget_bytes: int = 0, buffer_bytes: int = 1 << 30, step_bytes: int = 0,
+                 device: str = "cuda:0", stream=None):
+        import torch
+        o = wmc_serve_options()
+        o.precision = {"fp64": FP64, "fp32": FP32_SCALED, "fp32_scaled": FP32_SCALED}[precision]
+        o.max_slots = int(max_slots)
+        o.max_queue = int(max_queue)
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.step_bytes = int(step_bytes)
+        self.buf = torch.empty(int(buffer_bytes), dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().wmc_serve_create(ctypes.byref(o), ctypes.c_void_p(self.buf.data_ptr()), int(buffer_bytes),
+                                      _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.plans = []
+
+    def register(self, plan: Plan) -> int:
+        sid = ctypes.c_int32()
+        _check(lib().wmc_serve_register(self._h, plan._h, ctypes.byref(sid)))
+        self.plans.append(plan)
+        return int(sid.value)
+
+    def submit(self, structure: int, weights, request_id: int) -> None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        _check(lib().wmc_serve_submit(self._h, int(structure), _p(w), int(request_id)))
+
+    def step(self):
+        na, nq = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().wmc_serve_step(self._h, ctypes.byref(na), ctypes.byref(nq)))
+        return int(na.value), int(nq.value)
+
+    def poll(self, max_n: int = 1 << 16) -> List[Response]:
+        arr = (wmc_response * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().wmc_serve_poll(self._h, arr, int(max_n), ctypes.byref(n)))
+        return [Response.of(arr[i]) for i in range(n.value)]
+
+    def drain(self) -> List[Response]:
+        out = []
+        while True:
+            na, nq = self.step()
+            out += self.poll()
+            if na == 0 and nq == 0:
+                return out
+
+    def run(self, arrivals, structures, weights, ids=None) -> List[Response]:
+        """Replay timed arrivals (wmc_serve): arrivals sorted (seconds),
+        structures (ints), weights (list of arrays)."""
+        n = len(arrivals)
+        ws = [np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(-1)) for w in weights]
+        reqs = (wmc_request * max(n, 1))()
+        for i in range(n):
+            reqs[i].t_arrive = float(arrivals[i])
+            reqs[i].structure = int(structures[i])
+            reqs[i].request_id = int(ids[i]) if ids is not None else i
+            reqs[i].weights = ws[i].ctypes.data_as(ctypes.c_void_p)
+        out = (wmc_response * max(n, 1))()
+        _check(lib().wmc_serve(self._h, reqs, n, out))
+        return [Response.of(out[i]) for i in range(n)]
+
+    def stats(self) -> Dict:
+        i = wmc_serve_info()
+        _check(lib().wmc_serve_stats(self._h, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in wmc_serve_info._fields_}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.wmc_serve_destroy(h)
             self._h = None

@@ -22,7 +22,7 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 HOST_SOURCES = ["wmc_host.cpp"]
-DEVICE_SOURCES = ["wmc_device.hip", "wmc_batch.hip"]
+DEVICE_SOURCES = ["wmc_device.hip", "wmc_batch.hip", "wmc_serve.hip"]
 
 
 def _run(cmd, verbose):

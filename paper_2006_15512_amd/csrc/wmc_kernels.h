@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "wmc_internal.h"
@@ -72,7 +73,7 @@ __device__ __forceinline__ double ld(const T *p) { return (double)*p; }
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-static __global__ void k_begin(wmc_meta *meta, int nt, wmc_acc *acc, int reset) {
+static __global__ __attribute__((unused)) void k_begin(wmc_meta *meta, int nt, wmc_acc *acc, int reset) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nt) {
         meta[i].maxbits = 0ull;
@@ -502,7 +503,7 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
 // ---------------------------------------------------------------------------
 #define STREAM_B_LDS 4096
 #define STREAM_MAX_HOLES 8
-#define STREAM_MAX_BBITS 14
+#define STREAM_MAX_BRUNS 10
 
 struct StreamArgs {
     long long a, b, c;
@@ -510,8 +511,8 @@ struct StreamArgs {
     int rc;
     int nhole;                      // C bit positions not in A, ascending
     int hole[STREAM_MAX_HOLES];
-    int nbbit;                      // C bit positions owned by B, ascending
-    int bbit[STREAM_MAX_BBITS];
+    int nbrun;                      // B's bits of C as runs (src | len << 8 | dst << 16)
+    unsigned brun[STREAM_MAX_BRUNS];
     int rb;                         // storage rank of B
     int b_lds;
     int low_contig;                 // C bits 0 and 1 both belong to A
@@ -545,8 +546,11 @@ __device__ __forceinline__ unsigned long long drop_holes(unsigned long long r, c
 __device__ __forceinline__ unsigned long long gather_bits(unsigned long long r, const StreamArgs &s) {
     unsigned long long out = 0;
 #pragma unroll
-    for (int i = 0; i < STREAM_MAX_BBITS; ++i)
-        if (i < s.nbbit) out |= ((r >> s.bbit[i]) & 1ull) << i;
+    for (int i = 0; i < STREAM_MAX_BRUNS; ++i)
+        if (i < s.nbrun) {
+            const unsigned w = s.brun[i];
+            out |= ((r >> (w & 255u)) & ((1ull << ((w >> 8) & 255u)) - 1ull)) << (w >> 16);
+        }
     return out;
 }
 
@@ -618,8 +622,21 @@ __global__ void __launch_bounds__(256) k_stream(const StreamArgs args, T *__rest
 }
 
 // Streaming arguments for a single-node launch, if the node fits the kernel.
-static inline bool stream_args(const NodeDesc &d, StreamArgs *a) {
-    if (d.rc < 2 || d.nk > 3) return false;
+static inline bool stream_args(const NodeDesc &d0, StreamArgs *a) {
+    if (d0.rc < 2 || d0.nk > 3) return false;
+    // the contraction is symmetric: stream the larger operand as A
+    auto rank_of = [](const unsigned *runs, int nr, int nk) {
+        int r = nk;
+        for (int q = 0; q < nr; ++q) r += (int)((runs[q] >> 8) & 255u);
+        return r;
+    };
+    NodeDesc d = d0;
+    if (rank_of(d0.ra, d0.nra, d0.nk) < rank_of(d0.rb, d0.nrb, d0.nk)) {
+        std::swap(d.a, d.b);
+        std::swap(d.ta, d.tb);
+        std::swap(d.nra, d.nrb);
+        for (int q = 0; q < WMC_MAX_RUNS; ++q) std::swap(d.ra[q], d.rb[q]);
+    }
     std::memset(a, 0, sizeof *a);
     a->a = d.a;
     a->b = d.b;
@@ -636,15 +653,14 @@ static inline bool stream_args(const NodeDesc &d, StreamArgs *a) {
             if (a->nhole >= STREAM_MAX_HOLES) return false;
             a->hole[a->nhole++] = p;
         }
-    for (int q = 0; q < d.nrb; ++q)
-        for (unsigned j = 0; j < ((d.rb[q] >> 8) & 255u); ++j) {
-            if (a->nbbit >= STREAM_MAX_BBITS) return false;
-            a->bbit[a->nbbit++] = (int)((d.rb[q] & 255u) + j);
-        }
-    // gather order must match the runs' destination order (ascending in C)
-    for (int i = 1; i < a->nbbit; ++i)
-        if (a->bbit[i] < a->bbit[i - 1]) return false;
-    a->rb = d.nk + a->nbbit;
+    if (d.nrb > STREAM_MAX_BRUNS) return false;
+    int nbbit = 0;
+    for (int q = 0; q < d.nrb; ++q) {
+        a->brun[q] = d.rb[q];
+        nbbit += (int)((d.rb[q] >> 8) & 255u);
+    }
+    a->nbrun = d.nrb;
+    a->rb = d.nk + nbbit;
     a->b_lds = a->rb <= 12;
     a->low_contig = inA[0] && inA[1];
     return true;
@@ -655,6 +671,13 @@ static void launch_stream(const StreamArgs &sa, T *arena, wmc_meta *meta, hipStr
     const unsigned long long quads = (1ull << sa.rc) >> 2;
     unsigned long long blocks = (quads + 255) / 256;
     if (blocks > 8192) blocks = 8192;
+    // every workgroup stages B in LDS: keep that below a quarter of the
+    // outputs, but keep at least four workgroups per CU when there is work
+    if (sa.b_lds && sa.rc - sa.rb >= 2) {
+        unsigned long long cap = 1ull << (sa.rc - sa.rb - 2);
+        if (cap < 1024) cap = 1024;
+        if (blocks > cap) blocks = cap;
+    }
     if (blocks < 1) blocks = 1;
     switch (nk) {
     case 0: hipLaunchKernelGGL((k_stream<T, 0>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;

@@ -1,0 +1,146 @@
+"""GPU tests of the serving engine (continuous batching, admission by HBM
+footprint)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_15512_amd as W
+import wmc_workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def frac(v):
+    return Fraction(0) if v.mantissa == 0.0 else Fraction(v.mantissa) * Fraction(2) ** v.exp2
+
+
+def rel(a, b):
+    return 0.0 if a == b else float(abs(a - b) / max(abs(a), abs(b)))
+
+
+STRUCTS = [0, 1, 2, 3, 4, 5]  # the rank <= 19 serving structures (6, 7 reach rank 23-24)
+
+
+@pytest.fixture(scope="module")
+def structures():
+    return [wl.serve_structure(s) for s in STRUCTS]
+
+
+def make_server(structures, precision="fp64", **kw):
+    srv = W.Server(precision=precision, **kw)
+    plans = [W.Plan(W.Network.from_formula(f), seed=0, precision=precision) for f in structures]
+    ids = [srv.register(p) for p in plans]
+    return srv, plans, ids
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_serve_results_vs_oracle(structures, precision, tol):
+    """Requests over 6 structures with their own weight vectors, all queued at
+    once, against the oracle."""
+    srv, plans, ids = make_server(structures, precision, max_slots=16, buffer_bytes=1 << 29)
+    rng = np.random.default_rng(1)
+    reqs = []
+    for q in range(24):
+        s = int(rng.integers(0, len(structures)))
+        w = rng.uniform(0.1, 0.9, size=structures[s].n)
+        Wt = np.stack([1 - w, w], axis=1)
+        reqs.append((s, Wt))
+        srv.submit(ids[s], Wt, q)
+    say(f"serve {precision}: submitted")
+    got = {r.request_id: r for r in srv.drain()}
+    assert len(got) == len(reqs)
+    for q, (s, Wt) in enumerate(reqs):
+        m, e = oracle.bucket(structures[s].with_weights(Wt))
+        ref = Fraction(m) * Fraction(2) ** e
+        assert got[q].status == 0
+        assert rel(frac(got[q].value), ref) <= tol, q
+
+
+def test_serve_alone_equals_in_mix(structures):
+    """Each result in a mix equals the same request served alone, bit for bit."""
+    srv, plans, ids = make_server(structures, max_slots=32, buffer_bytes=1 << 29)
+    rng = np.random.default_rng(2)
+    reqs = []
+    for q in range(40):
+        s = int(rng.integers(0, len(structures)))
+        w = rng.uniform(0.1, 0.9, size=structures[s].n)
+        reqs.append((s, np.stack([1 - w, w], axis=1)))
+    # staggered submission: requests join while others are mid-flight
+    mix = {}
+    it = iter(enumerate(reqs))
+    pending = True
+    while pending or srv.stats()["n_active"]:
+        for _ in range(3):
+            nxt = next(it, None)
+            if nxt is None:
+                pending = False
+                break
+            q, (s, Wt) = nxt
+            srv.submit(ids[s], Wt, q)
+        srv.step()
+        for r in srv.poll():
+            mix[r.request_id] = r.value
+    assert len(mix) == len(reqs)
+    assert srv.stats()["peak_active"] > 4
+    say("mix done")
+    for q, (s, Wt) in enumerate(reqs):
+        alone = W.Server(precision="fp64", max_slots=1, buffer_bytes=1 << 27)
+        sid = alone.register(plans[s])
+        alone.submit(sid, Wt, 0)
+        (r,) = alone.drain()
+        assert (r.value.mantissa, r.value.exp2) == (mix[q].mantissa, mix[q].exp2), q
+        solo = W.wmc_contract(plans[s], Wt)
+        assert (solo.mantissa, solo.exp2) == (mix[q].mantissa, mix[q].exp2), q
+
+
+def test_serve_admission_respects_budget(structures):
+    """A budget that fits only a few footprints: requests wait in the queue,
+    the peak of used region bytes stays within the budget, all complete."""
+    plans = [W.Plan(W.Network.from_formula(f), seed=0) for f in structures]
+    fp = max(p.stats()["arena_bytes"] for p in plans)
+    budget = int(3.5 * fp) + (1 << 20)
+    srv = W.Server(precision="fp64", max_slots=64, hbm_budget_bytes=budget, buffer_bytes=1 << 29)
+    ids = [srv.register(p) for p in plans]
+    rng = np.random.default_rng(3)
+    for q in range(30):
+        s = int(rng.integers(0, len(structures)))
+        w = rng.uniform(0.1, 0.9, size=structures[s].n)
+        srv.submit(ids[s], np.stack([1 - w, w], axis=1), q)
+    out = srv.drain()
+    st = srv.stats()
+    assert len(out) == 30
+    assert st["peak_used_bytes"] <= st["region_bytes"] <= budget + 256
+    assert st["peak_active"] < 30
+
+
+def test_serve_queue_full_is_busy(structures):
+    srv, plans, ids = make_server(structures[:1], max_slots=2, max_queue=3, buffer_bytes=1 << 27)
+    w = np.full((structures[0].n, 2), 0.5)
+    for q in range(3):
+        srv.submit(ids[0], w, q)
+    with pytest.raises(W.WmcError) as e:
+        srv.submit(ids[0], w, 99)
+    assert e.value.status == 5
+    assert len(srv.drain()) == 3
+
+
+def test_serve_trace_replay(structures):
+    """Timed Poisson arrivals replayed by the native loop: every request
+    completes once, after it arrived, with its oracle value."""
+    srv, plans, ids = make_server(structures, max_slots=32, buffer_bytes=1 << 29)
+    n = 60
+    arr, st_, w = wl.serve_queries(n, rate=2000.0, seed=5, n_structures=len(structures))
+    out = srv.run(arr, [ids[s] for s in st_], list(w))
+    assert sorted(r.request_id for r in out) == list(range(n))
+    for r in out:
+        assert r.t_done >= r.t_admit >= r.t_arrive - 1e-9
+    for r in out[:12]:
+        f = structures[int(st_[r.request_id])].with_weights(w[r.request_id])
+        m, e = oracle.bucket(f)
+        assert rel(frac(r.value), Fraction(m) * Fraction(2) ** e) <= 1e-12
