@@ -227,17 +227,19 @@ wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, void *workspa
 void wmc_batch_destroy(wmc_batch *b);
 /* Raw descriptor image of a batch (tools and tests): [leaf descriptors][node
  * descriptors][launch list][matrix-node descriptors][root tensor int32 x n]
- * [root offset int64 x n]; info[0..8] = {n_leaves, n_nodes, n_launches,
- * arena_elems, n_instances, meta_total, elem_bytes, n_gemms, n_vars_total}. */
+ * [root offset int64 x n][streaming tasks][per launch: first task and the
+ * start of each summed-rank group, 6 x int32]; info[0..9] = {n_leaves,
+ * n_nodes, n_launches, arena_elems, n_instances, meta_total, elem_bytes,
+ * n_gemms, n_vars_total, n_tasks}. */
 wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, uint64_t *needed,
-                           int64_t *info /* 9 entries */);
+                           int64_t *info /* 10 entries */);
 
 /* ------------------------------------------------------------------ */
 /* Serving: weight queries on registered structures, continuous batching */
 /* ------------------------------------------------------------------ */
-/* A server owns a caller-supplied device buffer: a staging area for step
- * descriptors, a result table, and the request regions (at most
- * hbm_budget_bytes).  Registered structures are unsliced plans of the
+/* A server owns a caller-supplied device buffer: two staging areas for step
+ * descriptors (2 * step_bytes), a result table, and the request regions (at
+ * most hbm_budget_bytes).  Registered structures are unsliced plans of the
  * server's precision.  A request (structure, weight vector) waits in a FIFO
  * queue until a slot is free and a region of its footprint (its plan's meta
  * table + arena) fits in the budget: admission by HBM footprint.  Each step
@@ -283,7 +285,11 @@ wmc_status wmc_serve_register(wmc_server *s, const wmc_plan_t *plan, int32_t *st
 /* Non-blocking: queue one request (WMC_ERR_BUSY if the queue is full). */
 wmc_status wmc_serve_submit(wmc_server *s, int32_t structure, const double *weights,
                             uint64_t request_id);
-/* Admit what fits, run one step, collect completions (blocks for the step). */
+/* Admit what fits and issue one step on the server's stream, then wait for
+ * the step issued by the previous call and collect its completions, so the
+ * host prepares step k+1 while the device runs step k.  *n_active counts
+ * admitted requests, including those whose last launch is still in flight:
+ * call until both counts are zero to drain. */
 wmc_status wmc_serve_step(wmc_server *s, int32_t *n_active, int32_t *n_queued);
 /* Move up to max completed responses into out. */
 wmc_status wmc_serve_poll(wmc_server *s, wmc_response *out, int32_t max, int32_t *n_out);

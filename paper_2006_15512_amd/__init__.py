@@ -76,6 +76,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise WmcLibraryMissing(f"{LIB_PATH} not built: run `python -m paper_2006_15512_amd.build`")
+        # torch ships its own HIP runtime under the same soname.  Loading torch
+        # first makes libwmc.so bind to that runtime, so device buffers and
+        # streams created by torch are valid in library calls; loading the
+        # library first would put a second HIP runtime in the process.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         sigs = {
@@ -384,12 +389,12 @@ class Batch:
     def image(self):
         """Raw descriptor image: (bytes, info dict)."""
         need = ctypes.c_uint64()
-        info = (ctypes.c_int64 * 9)()
+        info = (ctypes.c_int64 * 10)()
         _check(lib().wmc_batch_image(self._h, None, 0, ctypes.byref(need), info))
         buf = (ctypes.c_uint8 * max(int(need.value), 1))()
         _check(lib().wmc_batch_image(self._h, buf, int(need.value), ctypes.byref(need), info))
         keys = ["n_leaves", "n_nodes", "n_launches", "arena_elems", "n_instances", "meta_total", "elem",
-                "n_gemms", "n_vars_total"]
+                "n_gemms", "n_vars_total", "n_tasks"]
         return bytes(buf)[: int(need.value)], dict(zip(keys, list(info)))
 
     def contract(self, weights=None, ws=None, stream=None, flags: int = 0) -> List[Value]:

@@ -9,6 +9,7 @@
 // launch and every matrix node in its own MFMA launch, and finishes all
 // roots with one kernel.  The whole sequence can be captured once as a HIP
 // graph and replayed.
+#include <array>
 #include <mutex>
 
 #include "wmc_kernels.h"
@@ -54,6 +55,11 @@ struct wmc_batch {
     std::vector<NodeDesc> nodes;
     std::vector<GemmDesc> gemms;
     std::vector<Launch> launches;  // [0] = leaves; then LAUNCH_NODES / LAUNCH_GEMM
+    // streaming tasks of each NODES launch: tasks[task_first[k] ...], grouped by nk
+    std::vector<StreamTask> tasks;
+    std::vector<int> task_first;         // per launch
+    std::vector<std::array<int, 5>> task_nk;  // per launch, relative to task_first
+    uint64_t off_tasks = 0;
     std::vector<int32_t> roots;
     std::vector<long long> root_off;
     int64_t meta_total = 0;
@@ -134,10 +140,13 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
             }
         }
         B->launches[0].work = B->leaf_work;
-        // node launches, merged by index
+        // node launches, merged by index; big streaming nodes become tasks
+        B->task_first.push_back(0);
+        B->task_nk.push_back({0, 0, 0, 0, 0});
         for (size_t k = 1; k < kmax; ++k) {
             Launch merged{LAUNCH_NODES, (int32_t)B->nodes.size(), 0, 0, 0};
             std::vector<Launch> gemm_launches;
+            std::vector<NodeDesc> step_nodes;
             for (int64_t i = 0; i < n; ++i) {
                 const wmc_plan_t &P = *plans[i];
                 if (k >= P.launches.size()) continue;
@@ -162,14 +171,27 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
                     d.ta += (int)mbase[(size_t)i];
                     d.tb += (int)mbase[(size_t)i];
                     d.tc += (int)mbase[(size_t)i];
-                    d.work_begin = merged.work;
-                    merged.work += (int64_t)bal((uint64_t)1 << d.rc, WMC_WAVE);
-                    B->nodes.push_back(d);
-                    ++merged.count;
+                    step_nodes.push_back(d);
                 }
             }
-            if (merged.count) B->launches.push_back(merged);
-            for (const Launch &g : gemm_launches) B->launches.push_back(g);
+            std::vector<StreamTask> tasks;
+            std::vector<int> nkf;
+            int64_t work = 0;
+            split_stream(step_nodes, tasks, nkf, work, WMC_STREAM_MIN_RANK);
+            merged.count = (int32_t)step_nodes.size();
+            merged.work = work;
+            B->nodes.insert(B->nodes.end(), step_nodes.begin(), step_nodes.end());
+            if (merged.count || !tasks.empty()) {
+                B->launches.push_back(merged);
+                B->task_first.push_back((int)B->tasks.size());
+                B->task_nk.push_back({nkf[0], nkf[1], nkf[2], nkf[3], nkf[4]});
+                B->tasks.insert(B->tasks.end(), tasks.begin(), tasks.end());
+            }
+            for (const Launch &g : gemm_launches) {
+                B->launches.push_back(g);
+                B->task_first.push_back((int)B->tasks.size());
+                B->task_nk.push_back({0, 0, 0, 0, 0});
+            }
         }
         for (int64_t i = 0; i < n; ++i) {
             const wmc_plan_t &P = *plans[i];
@@ -190,6 +212,8 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         off += bal(sizeof(NodeDesc) * std::max<size_t>(B->nodes.size(), 1), 256);
         B->off_gemm = off;
         off += bal(sizeof(GemmDesc) * std::max<size_t>(B->gemms.size(), 1), 256);
+        B->off_tasks = off;
+        off += bal(sizeof(StreamTask) * std::max<size_t>(B->tasks.size(), 1), 256);
         B->off_roots = off;
         off += bal(sizeof(int) * (uint64_t)n, 256);
         B->off_rootoff = off;
@@ -206,6 +230,7 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         put(B->off_leaf, B->leaves.data(), sizeof(LeafDesc) * B->leaves.size());
         put(B->off_node, B->nodes.data(), sizeof(NodeDesc) * B->nodes.size());
         put(B->off_gemm, B->gemms.data(), sizeof(GemmDesc) * B->gemms.size());
+        put(B->off_tasks, B->tasks.data(), sizeof(StreamTask) * B->tasks.size());
         put(B->off_roots, B->roots.data(), sizeof(int) * B->roots.size());
         put(B->off_rootoff, B->root_off.data(), sizeof(long long) * B->root_off.size());
         *out = B;
@@ -246,11 +271,17 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
                            (long long)B.leaf_work, w, arena, meta, 0ull);
     for (size_t k = 1; k < B.launches.size(); ++k) {
         const Launch &Ln = B.launches[k];
-        if (Ln.type == LAUNCH_GEMM)
+        if (Ln.type == LAUNCH_GEMM) {
             launch_gemm<T>(B.gemms[(size_t)Ln.pad], G + Ln.pad, arena, meta, st);
-        else
+            continue;
+        }
+        if (Ln.count)
             hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first, Ln.count,
                                (long long)Ln.work, arena, meta);
+        const int tf = B.task_first[k];
+        if (B.task_nk[k][4] > 0)
+            launch_stream_multi<T>((const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf,
+                                   B.task_nk[k].data(), arena, meta, st);
     }
     hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n + 255) / 256)), dim3(256), 0, st, arena,
                        (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n,
@@ -322,9 +353,10 @@ extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, vo
 }
 
 // Raw descriptor image of a batch, for tools and tests:
-// [LeafDesc][NodeDesc][Launch][GemmDesc][root tensor int32][root offset int64];
+// [LeafDesc][NodeDesc][Launch][GemmDesc][root tensor int32][root offset int64]
+// [StreamTask][per launch: task_first, nk group starts x5 (int32)];
 // info[] = {n_leaves, n_nodes, n_launches, arena_elems, n_instances,
-//           meta_total, elem_bytes, n_gemms, n_vars_total}.
+//           meta_total, elem_bytes, n_gemms, n_vars_total, n_tasks}.
 extern "C" wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, uint64_t *needed,
                                       int64_t *info) {
     if (!b) {
@@ -334,7 +366,8 @@ extern "C" wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t ds
     const wmc_batch &B = *b;
     const uint64_t need = sizeof(LeafDesc) * B.leaves.size() + sizeof(NodeDesc) * B.nodes.size() +
                           sizeof(Launch) * B.launches.size() + sizeof(GemmDesc) * B.gemms.size() +
-                          sizeof(int) * B.roots.size() + sizeof(long long) * B.root_off.size();
+                          sizeof(int) * B.roots.size() + sizeof(long long) * B.root_off.size() +
+                          sizeof(StreamTask) * B.tasks.size() + sizeof(int) * 6 * B.launches.size();
     if (needed) *needed = need;
     if (info) {
         info[0] = (int64_t)B.leaves.size();
@@ -346,6 +379,7 @@ extern "C" wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t ds
         info[6] = B.elem;
         info[7] = (int64_t)B.gemms.size();
         info[8] = B.n_vars_total;
+        info[9] = (int64_t)B.tasks.size();
     }
     if (!dst) return WMC_OK;
     if (dst_bytes < need) {
@@ -363,5 +397,11 @@ extern "C" wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t ds
     put(B.gemms.data(), sizeof(GemmDesc) * B.gemms.size());
     put(B.roots.data(), sizeof(int) * B.roots.size());
     put(B.root_off.data(), sizeof(long long) * B.root_off.size());
+    put(B.tasks.data(), sizeof(StreamTask) * B.tasks.size());
+    for (size_t k = 0; k < B.launches.size(); ++k) {
+        int row[6] = {B.task_first[k], B.task_nk[k][0], B.task_nk[k][1], B.task_nk[k][2], B.task_nk[k][3],
+                      B.task_nk[k][4]};
+        put(row, sizeof row);
+    }
     return WMC_OK;
 }

@@ -465,12 +465,23 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
     const size_t full = (size_t)K * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
     const size_t padded = (size_t)K * (NT * 16 + (sizeof(T) == 8 ? 2 : 4)) * sizeof(T);
     if (K >= 4 && K <= 64 && padded <= (size_t)lds_budget()) {
-        const unsigned long long per_beta = (512ull + (1ull << hd.nb) - 1) >> hd.nb;
-        dim3 grid((unsigned)(groups < per_beta ? groups : (per_beta ? per_beta : 1)), 1u << hd.nb);
         const int NTp = NT <= 1 ? 1 : NT <= 2 ? 2 : NT <= 4 ? 4 : 8;
+        // persistent grid: as many workgroups as fit on the device at once
+        auto grid_of = [&](const void *fn) {
+            int dev = 0, cus = 256, per_cu = 2;
+            if (hipGetDevice(&dev) == hipSuccess)
+                (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, padded) != hipSuccess || per_cu < 1)
+                per_cu = 2;
+            const unsigned long long total = (unsigned long long)cus * (unsigned long long)per_cu;
+            unsigned long long per_beta = (total + (1ull << hd.nb) - 1) >> hd.nb;
+            if (per_beta < 1) per_beta = 1;
+            return dim3((unsigned)(groups < per_beta ? groups : per_beta), 1u << hd.nb);
+        };
 #define WMC_GP(NTV, SV)                                                                                   \
     if (NTp == NTV && K / 4 == SV) {                                                                       \
-        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV>), grid, dim3(256), padded, st, dd, arena, meta);       \
+        const void *fn = (const void *)&k_gemm_p<T, NTV, SV>;                                            \
+        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV>), grid_of(fn), dim3(256), padded, st, dd, arena, meta); \
         return;                                                                                        \
     }
 #define WMC_GP_S(NTV) WMC_GP(NTV, 1) WMC_GP(NTV, 2) WMC_GP(NTV, 4) WMC_GP(NTV, 8) WMC_GP(NTV, 16)
@@ -685,6 +696,138 @@ static void launch_stream(const StreamArgs &sa, T *arena, wmc_meta *meta, hipStr
     case 2: hipLaunchKernelGGL((k_stream<T, 2>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
     default: hipLaunchKernelGGL((k_stream<T, 3>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
     }
+}
+
+// Many streaming nodes in one launch (the merged steps of batches and
+// serving).  Task t owns workgroups [block_begin_t, block_begin_{t+1}); each
+// workgroup produces STREAM_MULTI_QUADS consecutive quads of its node.  Tasks
+// share NK; B is staged in LDS only when it is small (at most 2^9 entries),
+// since every workgroup stages it.
+#define STREAM_MULTI_QUADS 1024
+#define STREAM_MULTI_B 512
+#define WMC_STREAM_MIN_RANK 12  // merged-step nodes with at least 2^12 outputs stream
+
+struct StreamTask {
+    StreamArgs a;
+    long long block_begin;
+};
+static_assert(sizeof(StreamArgs) == 136, "StreamArgs layout");
+static_assert(sizeof(StreamTask) == 144, "StreamTask layout");
+
+template <typename T, int NK>
+__global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restrict__ tasks, int ntasks,
+                                                      T *__restrict__ arena, wmc_meta *meta) {
+    __shared__ double Bs[STREAM_MULTI_B];
+    constexpr int K = 1 << NK;
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].block_begin <= (long long)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const StreamArgs &args = tasks[lo].a;
+    const unsigned long long lb = (unsigned long long)((long long)blockIdx.x - tasks[lo].block_begin);
+    const int sA = scale_exp(meta[args.ta].maxbits);
+    const int sB = scale_exp(meta[args.tb].maxbits);
+    const double scaleB = ldexp(1.0, -sB), scaleA = ldexp(1.0, -sA);
+    const T *__restrict__ A = arena + args.a;
+    const T *__restrict__ B = arena + args.b;
+    T *__restrict__ C = arena + args.c;
+    const bool b_lds = args.rb <= 9;
+    if (b_lds) {
+        for (int i = threadIdx.x; i < (1 << args.rb); i += 256) Bs[i] = (double)B[i] * scaleB;
+        __syncthreads();
+    }
+    const unsigned long long quads = (1ull << args.rc) >> 2;
+    const unsigned long long q0 = lb * STREAM_MULTI_QUADS;
+    double vmax = 0.0;
+    for (unsigned long long q = q0 + threadIdx.x; q < quads && q < q0 + STREAM_MULTI_QUADS; q += 256) {
+        double av[4][K];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const unsigned long long pa = drop_holes((q << 2) | (unsigned long long)e, args) << NK;
+#pragma unroll
+            for (int j = 0; j < K; ++j) av[e][j] = (double)A[pa + j];
+        }
+        double o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const unsigned long long pb = gather_bits((q << 2) | (unsigned long long)e, args) << NK;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const double bv = b_lds ? Bs[pb + j] : (double)B[pb + j] * scaleB;
+                acc = fma(av[e][j], bv, acc);
+            }
+            o[e] = acc * scaleA;
+        }
+        Vec4<T>::store(C + (q << 2), o[0], o[1], o[2], o[3]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs((double)(T)o[e]));
+    }
+    publish_max(meta, args.tc, vmax);
+    if (lb == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
+}
+
+// Build the streaming tasks of a node list; returns false for a node the
+// streaming kernel cannot take.  Workgroup ranges are assigned per NK group.
+static inline bool stream_task(const NodeDesc &d, StreamTask *t) {
+    std::memset(t, 0, sizeof *t);
+    return stream_args(d, &t->a) && d.nk <= 3;
+}
+
+template <typename T>
+static void launch_stream_multi(const StreamTask *dev_tasks, const StreamTask *host_tasks, const int *nk_first,
+                                T *arena, wmc_meta *meta, hipStream_t st) {
+    // nk_first[k] .. nk_first[k+1] is the group of tasks with nk == k
+    for (int k = 0; k < 4; ++k) {
+        const int f = nk_first[k], l = nk_first[k + 1];
+        if (f == l) continue;
+        const StreamTask &last = host_tasks[l - 1];
+        const unsigned g = (unsigned)(last.block_begin +
+                                      (long long)((((1ull << last.a.rc) >> 2) + STREAM_MULTI_QUADS - 1) /
+                                                  STREAM_MULTI_QUADS));
+        switch (k) {
+        case 0: hipLaunchKernelGGL((k_stream_multi<T, 0>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
+        case 1: hipLaunchKernelGGL((k_stream_multi<T, 1>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
+        case 2: hipLaunchKernelGGL((k_stream_multi<T, 2>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
+        default: hipLaunchKernelGGL((k_stream_multi<T, 3>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
+        }
+    }
+}
+
+// Split a merged node list into (generic nodes, streaming tasks grouped by
+// nk).  Nodes with at least 2^min_rank outputs that the streaming kernel
+// accepts become tasks; work_begin of the generic ones is recomputed.
+static inline void split_stream(std::vector<NodeDesc> &generic, std::vector<StreamTask> &tasks,
+                                std::vector<int> &nk_first, int64_t &generic_work, int min_rank) {
+    std::vector<NodeDesc> keep;
+    std::vector<StreamTask> by_nk[4];
+    generic_work = 0;
+    for (const NodeDesc &d : generic) {
+        StreamTask t;
+        if (d.rc >= min_rank && d.cls != WMC_CLASS_GEMM && stream_task(d, &t)) {
+            by_nk[d.nk].push_back(t);
+            continue;
+        }
+        NodeDesc e = d;
+        e.work_begin = generic_work;
+        generic_work += (int64_t)(((1ull << e.rc) + WMC_WAVE - 1) / WMC_WAVE * WMC_WAVE);
+        keep.push_back(e);
+    }
+    generic.swap(keep);
+    tasks.clear();
+    nk_first.assign(5, 0);
+    for (int k = 0; k < 4; ++k) {
+        nk_first[(size_t)k] = (int)tasks.size();
+        long long blocks = 0;
+        for (StreamTask &t : by_nk[k]) {
+            t.block_begin = blocks;
+            blocks += (long long)((((1ull << t.a.rc) >> 2) + STREAM_MULTI_QUADS - 1) / STREAM_MULTI_QUADS);
+            tasks.push_back(t);
+        }
+    }
+    nk_first[4] = (int)tasks.size();
 }
 
 // Root of one slice: fold its value into the running sum (s + c) * 2^e.

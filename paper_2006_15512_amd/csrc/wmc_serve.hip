@@ -110,16 +110,24 @@ struct wmc_server {
     std::map<uint64_t, uint64_t> free_regions;  // offset -> size
     uint64_t used_bytes = 0, peak_used = 0;
     int64_t peak_active = 0, steps = 0;
-    uint8_t *stage = nullptr;  // pinned
-    ServeRes *res_host = nullptr;  // pinned
+    uint8_t *stage[2] = {nullptr, nullptr};     // pinned staging, one per step parity
+    ServeRes *res_host[2] = {nullptr, nullptr};  // pinned results, one per step parity
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool inflight = false;                       // a step was issued and not yet collected
+    int parity = 0;                              // parity of the step in flight
+    std::vector<SReq> finishing;                 // requests whose last launch is in flight
     std::vector<wmc_response> done;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     ~wmc_server() {
-        if (stage) (void)hipHostFree(stage);
-        if (res_host) (void)hipHostFree(res_host);
+        if (inflight && ev[parity]) (void)hipEventSynchronize(ev[parity]);
+        for (int i = 0; i < 2; ++i) {
+            if (stage[i]) (void)hipHostFree(stage[i]);
+            if (res_host[i]) (void)hipHostFree(res_host[i]);
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        }
     }
 };
 
@@ -141,7 +149,7 @@ extern "C" wmc_status wmc_serve_create(const wmc_serve_options *opts, void *devi
     }
     const uint64_t step_cap = sal(opts->step_bytes ? opts->step_bytes : (16ull << 20), 256);
     const uint64_t res_bytes = sal(sizeof(ServeRes) * (uint64_t)opts->max_slots, 256);
-    if (bytes < step_cap + res_bytes + 4096) {
+    if (bytes < 2 * step_cap + res_bytes + 4096) {
         wmc_set_error("wmc_serve_create: device buffer too small (%llu bytes)", (unsigned long long)bytes);
         return WMC_ERR_OUT_OF_MEMORY;
     }
@@ -152,21 +160,23 @@ extern "C" wmc_status wmc_serve_create(const wmc_serve_options *opts, void *devi
         V->dev = (char *)device_buffer;
         V->dev_bytes = bytes;
         V->st = (hipStream_t)stream;
-        V->off_step = 0;
+        V->off_step = 0;  // two halves of step_cap, one per step parity
         V->step_cap = step_cap;
-        V->off_res = step_cap;
-        V->off_regions = step_cap + res_bytes;
+        V->off_res = 2 * step_cap;
+        V->off_regions = 2 * step_cap + res_bytes;
         V->regions_bytes = (bytes - V->off_regions) / 256 * 256;
         if (opts->hbm_budget_bytes && opts->hbm_budget_bytes < V->regions_bytes)
             V->regions_bytes = sal(opts->hbm_budget_bytes, 256);
         V->free_regions[0] = V->regions_bytes;
         for (int32_t s = opts->max_slots - 1; s >= 0; --s) V->free_slots.push_back(s);
-        if (hipHostMalloc((void **)&V->stage, step_cap, 0) != hipSuccess ||
-            hipHostMalloc((void **)&V->res_host, res_bytes, 0) != hipSuccess) {
-            delete V;
-            wmc_set_error("wmc_serve_create: pinned host allocation failed");
-            return WMC_ERR_OUT_OF_MEMORY;
-        }
+        for (int i = 0; i < 2; ++i)
+            if (hipHostMalloc((void **)&V->stage[i], step_cap, 0) != hipSuccess ||
+                hipHostMalloc((void **)&V->res_host[i], res_bytes, 0) != hipSuccess ||
+                hipEventCreateWithFlags(&V->ev[i], hipEventDisableTiming) != hipSuccess) {
+                delete V;
+                wmc_set_error("wmc_serve_create: pinned host allocation or event creation failed");
+                return WMC_ERR_OUT_OF_MEMORY;
+            }
         *out = V;
     } catch (std::bad_alloc &) {
         wmc_set_error("wmc_serve_create: host allocation failed");
@@ -297,10 +307,42 @@ static void region_free(wmc_server *v, uint64_t off, uint64_t size) {
     }
 }
 
+// Collect the step in flight: wait for it, publish its finished requests and
+// release their slots and regions.
+static wmc_status serve_collect(wmc_server *v) {
+    if (!v->inflight) return WMC_OK;
+    HIP_TRY(hipEventSynchronize(v->ev[v->parity]));
+    v->inflight = false;
+    const double t = v->now();
+    const ServeRes *res = v->res_host[v->parity];
+    for (SReq &r : v->finishing) {
+        const SStruct &s = v->S[(size_t)r.s];
+        wmc_response resp;
+        std::memset(&resp, 0, sizeof resp);
+        resp.request_id = r.id;
+        resp.structure = r.s;
+        resp.status = WMC_OK;
+        resp.value = s.root < 0 ? make_value(1.0, 0) : make_value(res[r.slot].m, res[r.slot].e);
+        resp.t_arrive = r.t_arrive;
+        resp.t_admit = r.t_admit;
+        resp.t_done = t;
+        v->done.push_back(resp);
+        region_free(v, r.region, s.footprint);
+        v->free_slots.push_back(r.slot);
+    }
+    v->finishing.clear();
+    return WMC_OK;
+}
+
+// Issue one step: admit what fits, run the next launch of every admitted
+// request in shared kernels.  Requests issuing their last launch move to the
+// finishing list; their slot and region are released when the step is
+// collected (after the next step has been issued, so host preparation of step
+// k+1 overlaps the GPU running step k).
 template <typename T>
-static wmc_status serve_step_t(wmc_server *v) {
+static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishing, bool *issued) {
+    *issued = false;
     const uint64_t elem = (uint64_t)v->elem;
-    // admission: FIFO, while a slot, a region and staging room are free
     uint64_t stage_need = 0;
     for (const SReq &r : v->active) stage_need += v->S[(size_t)r.s].max_step_bytes;
     while (!v->queue.empty() && !v->free_slots.empty()) {
@@ -321,15 +363,15 @@ static wmc_status serve_step_t(wmc_server *v) {
     if (v->active.empty()) return WMC_OK;
     v->peak_active = std::max<int64_t>(v->peak_active, (int64_t)v->active.size());
 
-    // gather this step's descriptors
     std::vector<double> wts;
     std::vector<ClearRange> clears;
     std::vector<LeafDesc> leaves;
     std::vector<NodeDesc> nodes;
     std::vector<GemmDesc> gemms;
     std::vector<FinishEntry> fin;
-    std::vector<size_t> finishing;
     int64_t leaf_work = 0, node_work = 0;
+    std::vector<SReq> keep;
+    keep.reserve(v->active.size());
     for (size_t i = 0; i < v->active.size(); ++i) {
         SReq &r = v->active[i];
         const SStruct &s = v->S[(size_t)r.s];
@@ -367,18 +409,24 @@ static wmc_status serve_step_t(wmc_server *v) {
                     d.ta += (int)mbase;
                     d.tb += (int)mbase;
                     d.tc += (int)mbase;
-                    d.work_begin = node_work;
-                    node_work += (int64_t)sal((uint64_t)1 << d.rc, WMC_WAVE);
                     nodes.push_back(d);
                 }
             }
         }
         if (r.k + 1 >= s.launches.size()) {
             fin.push_back({s.root < 0 ? -1 : s.root + (int)mbase, r.slot, s.root_off + abase});
-            finishing.push_back(i);
+            finishing.push_back(std::move(r));
+        } else {
+            r.k += 1;
+            keep.push_back(std::move(r));
         }
     }
-    // staging image: [weights][clears][leaves][nodes][gemms][finish]
+    v->active.swap(keep);
+    // big streaming nodes of the merged step run in the multi-node streaming kernel
+    std::vector<StreamTask> tasks;
+    std::vector<int> nkf;
+    split_stream(nodes, tasks, nkf, node_work, WMC_STREAM_MIN_RANK);
+    // staging image: [weights][clears][leaves][nodes][gemms][finish][tasks]
     uint64_t o = 0;
     auto place = [&](size_t bytes) {
         uint64_t at = o;
@@ -391,13 +439,15 @@ static wmc_status serve_step_t(wmc_server *v) {
     const uint64_t o_n = place(sizeof(NodeDesc) * nodes.size());
     const uint64_t o_g = place(sizeof(GemmDesc) * gemms.size());
     const uint64_t o_f = place(sizeof(FinishEntry) * fin.size());
+    const uint64_t o_t = place(sizeof(StreamTask) * tasks.size());
     if (o > v->step_cap) {
         wmc_set_error("wmc_serve: step staging overflow (%llu > %llu)", (unsigned long long)o,
                       (unsigned long long)v->step_cap);
         return WMC_ERR_OUT_OF_MEMORY;
     }
+    uint8_t *stage = v->stage[h];
     auto cp = [&](uint64_t at, const void *src, size_t bytes) {
-        if (bytes) std::memcpy(v->stage + at, src, bytes);
+        if (bytes) std::memcpy(stage + at, src, bytes);
     };
     cp(o_w, wts.data(), sizeof(double) * wts.size());
     cp(o_c, clears.data(), sizeof(ClearRange) * clears.size());
@@ -405,9 +455,10 @@ static wmc_status serve_step_t(wmc_server *v) {
     cp(o_n, nodes.data(), sizeof(NodeDesc) * nodes.size());
     cp(o_g, gemms.data(), sizeof(GemmDesc) * gemms.size());
     cp(o_f, fin.data(), sizeof(FinishEntry) * fin.size());
+    cp(o_t, tasks.data(), sizeof(StreamTask) * tasks.size());
     hipStream_t st = v->st;
-    char *stp = v->dev + v->off_step;
-    HIP_TRY(hipMemcpyAsync(stp, v->stage, o, hipMemcpyHostToDevice, st));
+    char *stp = v->dev + v->off_step + (uint64_t)h * v->step_cap;
+    HIP_TRY(hipMemcpyAsync(stp, stage, o, hipMemcpyHostToDevice, st));
     wmc_meta *meta = (wmc_meta *)(v->dev + v->off_regions);
     T *arena = (T *)(v->dev + v->off_regions);
     if (!clears.empty())
@@ -420,45 +471,40 @@ static wmc_status serve_step_t(wmc_server *v) {
     if (!nodes.empty())
         hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(node_work)), dim3(WMC_BLOCK), 0, st,
                            (const NodeDesc *)(stp + o_n), (int)nodes.size(), (long long)node_work, arena, meta);
+    if (!tasks.empty())
+        launch_stream_multi<T>((const StreamTask *)(stp + o_t), tasks.data(), nkf.data(), arena, meta, st);
     for (size_t q = 0; q < gemms.size(); ++q)
         launch_gemm<T>(gemms[q], (const GemmDesc *)(stp + o_g) + q, arena, meta, st);
     ServeRes *res = (ServeRes *)(v->dev + v->off_res);
     if (!fin.empty()) {
         hipLaunchKernelGGL(k_finish_serve<T>, dim3((unsigned)((fin.size() + 255) / 256)), dim3(256), 0, st,
                            (const FinishEntry *)(stp + o_f), (int)fin.size(), arena, meta, res);
-        HIP_TRY(hipMemcpyAsync(v->res_host, res, sizeof(ServeRes) * (size_t)v->opt.max_slots,
+        HIP_TRY(hipMemcpyAsync(v->res_host[h], res, sizeof(ServeRes) * (size_t)v->opt.max_slots,
                                hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipEventRecord(v->ev[h], st));
     ++v->steps;
-    const double t = v->now();
-    std::vector<uint8_t> gone(v->active.size(), 0);
-    for (size_t j = 0; j < finishing.size(); ++j) {
-        SReq &r = v->active[finishing[j]];
-        const SStruct &s = v->S[(size_t)r.s];
-        wmc_response resp;
-        std::memset(&resp, 0, sizeof resp);
-        resp.request_id = r.id;
-        resp.structure = r.s;
-        resp.status = WMC_OK;
-        resp.value = s.root < 0 ? make_value(1.0, 0) : make_value(v->res_host[r.slot].m, v->res_host[r.slot].e);
-        resp.t_arrive = r.t_arrive;
-        resp.t_admit = r.t_admit;
-        resp.t_done = t;
-        v->done.push_back(resp);
-        region_free(v, r.region, s.footprint);
-        v->free_slots.push_back(r.slot);
-        gone[finishing[j]] = 1;
+    *issued = true;
+    return WMC_OK;
+}
+
+// One call: issue the next step into the staging half not used by the step in
+// flight, then collect the step in flight.
+template <typename T>
+static wmc_status serve_step_t(wmc_server *v) {
+    std::vector<SReq> fin_now;
+    const int h = v->parity ^ 1;
+    bool issued = false;
+    wmc_status st = serve_issue_t<T>(v, h, fin_now, &issued);
+    if (st != WMC_OK) return st;
+    st = serve_collect(v);
+    if (st != WMC_OK) return st;
+    if (issued) {
+        v->parity = h;
+        v->inflight = true;
+        v->finishing.swap(fin_now);
     }
-    std::vector<SReq> keep;
-    keep.reserve(v->active.size());
-    for (size_t i = 0; i < v->active.size(); ++i) {
-        if (gone[i]) continue;
-        v->active[i].k += 1;
-        keep.push_back(std::move(v->active[i]));
-    }
-    v->active.swap(keep);
     return WMC_OK;
 }
 
@@ -468,7 +514,8 @@ extern "C" wmc_status wmc_serve_step(wmc_server *v, int32_t *n_active, int32_t *
         return WMC_ERR_INVALID_ARGUMENT;
     }
     wmc_status s = v->elem == 8 ? serve_step_t<double>(v) : serve_step_t<float>(v);
-    if (n_active) *n_active = (int32_t)v->active.size();
+    // requests whose last launch is still in flight count as active
+    if (n_active) *n_active = (int32_t)(v->active.size() + v->finishing.size());
     if (n_queued) *n_queued = (int32_t)v->queue.size();
     return s;
 }
@@ -496,7 +543,7 @@ extern "C" wmc_status wmc_serve_stats(const wmc_server *v, wmc_serve_info *out) 
     out->peak_used_bytes = v->peak_used;
     out->peak_active = v->peak_active;
     out->steps = v->steps;
-    out->n_active = (int64_t)v->active.size();
+    out->n_active = (int64_t)(v->active.size() + v->finishing.size());
     out->n_queued = (int64_t)v->queue.size();
     out->n_structures = (int64_t)v->S.size();
     return WMC_OK;
@@ -527,7 +574,7 @@ extern "C" wmc_status wmc_serve(wmc_server *v, const wmc_request *trace, int64_t
             if (s != WMC_OK) return s;
             ++next;
         }
-        if (v->active.empty() && v->queue.empty()) {
+        if (v->active.empty() && v->queue.empty() && !v->inflight) {
             if (next < n) {
                 // idle until the next arrival
                 while (v->now() < trace[next].t_arrive) {

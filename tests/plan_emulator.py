@@ -30,6 +30,12 @@ GEMM = np.dtype({"names": ["a", "b", "c", "ta", "tb", "tc", "nk", "nm", "nn", "n
                  "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 48, 52, 80],
                  "itemsize": 336})
 GR_MU_A, GR_BETA_A, GR_NU_B, GR_BETA_B, GR_MU_C, GR_NU_C, GR_BETA_C = range(7)
+STREAM = np.dtype({"names": ["a", "b", "c", "ta", "tb", "tc", "rc", "nhole", "hole", "nbrun", "brun", "rb",
+                             "b_lds", "low_contig", "block_begin"],
+                   "formats": ["<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", ("<i4", (8,)), "<i4",
+                               ("<u4", (10,)), "<i4", "<i4", "<i4", "<i8"],
+                   "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 76, 80, 120, 124, 128, 136],
+                   "itemsize": 144})
 
 
 def parse(plan):
@@ -68,7 +74,27 @@ def _sexp(m: float) -> int:
     return math.frexp(m)[1]
 
 
-def _replay(leaves, nodes, launches, gemms, arena_elems, nt, w, store, eta, roots, root_offs):
+def _stream_task_as_node(t, nk):
+    """A streaming task (A = the operand whose bits are C minus the holes, B
+    via run words) rewritten as (a, b, c, ta, tb, tc, rc, nk, A-runs, B-runs)
+    so the generic replay below can execute it."""
+    rc = int(t["rc"])
+    holes = set(int(h) for h in t["hole"][: int(t["nhole"])])
+    a_bits = [p for p in range(rc) if p not in holes]
+    runs_a = []
+    i = 0
+    while i < len(a_bits):
+        j = i
+        while j + 1 < len(a_bits) and a_bits[j + 1] == a_bits[j] + 1:
+            j += 1
+        runs_a.append(a_bits[i] | ((j - i + 1) << 8) | (i << 16))
+        i = j + 1
+    return dict(a=int(t["a"]), b=int(t["b"]), c=int(t["c"]), ta=int(t["ta"]), tb=int(t["tb"]), tc=int(t["tc"]),
+                rc=rc, nk=nk, ra=np.array(runs_a, dtype=np.uint32), nra=len(runs_a),
+                rb=np.array(t["brun"][: int(t["nbrun"])], dtype=np.uint32), nrb=int(t["nbrun"]))
+
+
+def _replay(leaves, nodes, launches, gemms, arena_elems, nt, w, store, eta, roots, root_offs, tasks_of=None):
     """One pass of the launch list; returns the exact value of each root."""
     arena = np.zeros(max(arena_elems, 1), dtype=store)
     maxv = np.zeros(max(nt, 1))
@@ -92,7 +118,8 @@ def _replay(leaves, nodes, launches, gemms, arena_elems, nt, w, store, eta, root
         s = v.astype(store)
         arena[int(d["out"]): int(d["out"]) + size] = s
         maxv[int(d["tensor"])] = float(np.max(np.abs(s.astype(np.float64))))
-    for L in launches[1:]:
+    for li in range(1, len(launches)):
+        L = launches[li]
         results = []
         if int(L["type"]) == 2:
             g = gemms[int(L["pad"])]
@@ -122,7 +149,10 @@ def _replay(leaves, nodes, launches, gemms, arena_elems, nt, w, store, eta, root
             maxv[int(g["tc"])] = mx
             ex[int(g["tc"])] = ex[int(g["ta"])] + ex[int(g["tb"])] + sA + sB
             continue
-        for d in nodes[int(L["first"]): int(L["first"]) + int(L["count"])]:
+        step = list(nodes[int(L["first"]): int(L["first"]) + int(L["count"])])
+        if tasks_of is not None:
+            step += tasks_of(li)
+        for d in step:
             rc, nk = int(d["rc"]), int(d["nk"])
             r = np.arange(1 << rc, dtype=np.uint64)
             pa = _pext(r, d["ra"], int(d["nra"])) << np.uint64(nk)
@@ -184,9 +214,22 @@ def emulate_batch(batch, weights, store=np.float64):
     roots = np.frombuffer(img, "<i4", count=n, offset=off)
     off += 4 * n
     root_offs = np.frombuffer(img, "<i8", count=n, offset=off)
+    off += 8 * n
+    nt = info["n_tasks"]
+    tasks = np.frombuffer(img, STREAM, count=nt, offset=off)
+    off += nt * STREAM.itemsize
+    groups = np.frombuffer(img, "<i4", count=6 * nla, offset=off).reshape(nla, 6)
+
+    def tasks_of(k):
+        tf = int(groups[k, 0])
+        out = []
+        for nk in range(4):
+            for t in tasks[tf + int(groups[k, 1 + nk]): tf + int(groups[k, 2 + nk])]:
+                out.append(_stream_task_as_node(t, nk))
+        return out
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
     return _replay(leaves, nodes, launches, gemms, info["arena_elems"], info["meta_total"], w, store, 0,
-                   list(roots), list(root_offs))
+                   list(roots), list(root_offs), tasks_of)
 
 
 def to_float(x: Fraction) -> float:
