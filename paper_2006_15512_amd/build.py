@@ -35,17 +35,26 @@ def build(verbose: bool = False, debug: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     inc = ["-I", CSRC, "-I", os.path.join(ROOT, "include")]
     opt = ["-O0", "-g"] if debug else ["-O3"]
-    objs = []
+    objs, cmds = [], []
     for s in HOST_SOURCES:
         o = os.path.join(BUILD_DIR, s + ".o")
-        _run(["g++", "-std=c++17", *opt, "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter", *inc, "-c",
-              os.path.join(CSRC, s), "-o", o], verbose)
+        cmds.append(["g++", "-std=c++17", *opt, "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter", *inc, "-c",
+                     os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     for s in DEVICE_SOURCES:
         o = os.path.join(BUILD_DIR, s + ".o")
-        _run([HIPCC, "-std=c++17", *opt, "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-Wall",
-              "-Wno-unused-command-line-argument", *inc, "-c", os.path.join(CSRC, s), "-o", o], verbose)
+        cmds.append([HIPCC, "-std=c++17", *opt, "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-Wall",
+                     "-Wno-unused-command-line-argument", *inc, "-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
+    # the translation units are independent: compile them side by side
+    procs = []
+    for c in cmds:
+        if verbose:
+            print(" ".join(c), flush=True)
+        procs.append(subprocess.Popen(c))
+    failed = [c for c, p in zip(cmds, procs) if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

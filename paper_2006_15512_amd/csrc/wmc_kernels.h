@@ -321,7 +321,19 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T 
 // indices x N columns) fits in LDS: each workgroup stages B once, then walks
 // row-tile groups blockIdx.x, blockIdx.x + gridDim.x, ..., loading the next
 // group's A fragments into registers while the MFMAs of the current group run.
-template <typename T, int NT, int S>
+// 64-bit value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// SW selects the orientation of the matrix instruction.  SW = false: lane l
+// of an output tile holds column l%16 and rows out_row(l/16, v).  SW = true
+// computes the transposed tile (operands swapped: B^T A^T), so lane l holds
+// row l%16 and columns out_row(l/16, v); used when C's lowest address bits
+// belong to rows, so that 16 lanes store 16 consecutive elements.
+template <typename T, int NT, int S, bool SW>
 __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, T *__restrict__ arena,
                                                 wmc_meta *meta) {
     typedef typename Mfma<T>::acc_t acc_t;
@@ -361,16 +373,32 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
         }
         Bs[k * LDN + col] = v;
     }
-    unsigned long long cols[NT];
+    // Output addresses.  Bit extraction is an OR over disjoint source bits, so
+    // the address of (row, col) splits into per-lane and wave-uniform parts:
+    // out_row(g, v) = out_row(g, 0) | out_row(0, v), col = 16 ct | (col % 16).
+    unsigned long long cols[SW ? 1 : NT];  // !SW: per-lane column part per column tile
+    unsigned long long rlo[SW ? 1 : 4];    // !SW: per-lane row part per register
+    unsigned long long lrow = 0, lcol = 0;  // SW: per-lane row and column parts
+    unsigned long long ucol_v[SW ? 4 : 1], ucol_t[SW ? NT : 1];  // SW: uniform column parts
+    if constexpr (!SW) {
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-        const int col = ct * 16 + l16;
-        cols[ct] = pext_runs((unsigned long long)(col < N ? col : 0), d.run[GR_NU_C], d.nrun[GR_NU_C]) | cBeta;
+        for (int ct = 0; ct < NT; ++ct) {
+            const int col = ct * 16 + l16;
+            cols[ct] = pext_runs((unsigned long long)(col < N ? col : 0), d.run[GR_NU_C], d.nrun[GR_NU_C]) | cBeta;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            rlo[v] = pext_runs((unsigned long long)Mfma<T>::out_row(g, v), d.run[GR_MU_C], d.nrun[GR_MU_C]);
+    } else {
+        lrow = pext_runs((unsigned long long)l16, d.run[GR_MU_C], d.nrun[GR_MU_C]);
+        lcol = pext_runs((unsigned long long)Mfma<T>::out_row(g, 0), d.run[GR_NU_C], d.nrun[GR_NU_C]) | cBeta;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            ucol_v[v] = uniform64(pext_runs((unsigned long long)Mfma<T>::out_row(0, v), d.run[GR_NU_C], d.nrun[GR_NU_C]));
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+            ucol_t[ct] = uniform64(pext_runs((unsigned long long)(ct * 16), d.run[GR_NU_C], d.nrun[GR_NU_C]));
     }
-    unsigned long long rlo[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-        rlo[v] = pext_runs((unsigned long long)Mfma<T>::out_row(g, v), d.run[GR_MU_C], d.nrun[GR_MU_C]);
 
     // A fragments: loads are unconditional (a row tile past the end reads
     // tile 0 and is discarded) so the compiler can count them precisely
@@ -417,8 +445,12 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
             for (int ct = 0; ct < NT; ++ct) {
                 T b = Bs[(4 * s + g) * LDN + ct * 16 + l16];
 #pragma unroll
-                for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
-                    acc[rt][ct] = Mfma<T>::step(a[rt][s], b, acc[rt][ct]);
+                for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+                    if constexpr (SW)
+                        acc[rt][ct] = Mfma<T>::step(b, a[rt][s], acc[rt][ct]);
+                    else
+                        acc[rt][ct] = Mfma<T>::step(a[rt][s], b, acc[rt][ct]);
+                }
             }
         }
 #pragma unroll
@@ -426,13 +458,25 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
             if (!ok[rt]) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const unsigned long long rc = thi[rt] | rlo[v];
+                if constexpr (!SW) {
+                    const unsigned long long rc = thi[rt] | rlo[v];
 #pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    if (NT == 1 && l16 >= N) continue;
-                    T sv = (T)((double)acc[rt][ct][v] * scale);
-                    arena[c0 + (long long)(rc | cols[ct])] = sv;
-                    vmax = fmax(vmax, fabs((double)sv));
+                    for (int ct = 0; ct < NT; ++ct) {
+                        if (NT == 1 && l16 >= N) continue;
+                        T sv = (T)((double)acc[rt][ct][v] * scale);
+                        arena[c0 + (long long)(rc | cols[ct])] = sv;
+                        vmax = fmax(vmax, fabs((double)sv));
+                    }
+                } else {
+                    const unsigned long long rc = thi[rt] | lrow | lcol | ucol_v[v];
+                    const bool live = NT > 1 || Mfma<T>::out_row(g, v) < N;
+#pragma unroll
+                    for (int ct = 0; ct < NT; ++ct) {
+                        if (!live) continue;
+                        T sv = (T)((double)acc[rt][ct][v] * scale);
+                        arena[c0 + (long long)(rc | ucol_t[ct])] = sv;
+                        vmax = fmax(vmax, fabs((double)sv));
+                    }
                 }
             }
         }
@@ -478,16 +522,22 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
             if (per_beta < 1) per_beta = 1;
             return dim3((unsigned)(groups < per_beta ? groups : per_beta), 1u << hd.nb);
         };
-#define WMC_GP(NTV, SV)                                                                                   \
-    if (NTp == NTV && K / 4 == SV) {                                                                       \
-        const void *fn = (const void *)&k_gemm_p<T, NTV, SV>;                                            \
-        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV>), grid_of(fn), dim3(256), padded, st, dd, arena, meta); \
-        return;                                                                                        \
+        // transposed tiles when C's lowest address bit is a row bit
+        bool sw = false;
+        for (int q = 0; q < hd.nrun[GR_MU_C]; ++q)
+            if (hd.run[GR_MU_C][q][2] == 0) sw = true;
+#define WMC_GP1(NTV, SV, SWV)                                                                                   \
+    if (NTp == NTV && K / 4 == SV && sw == SWV) {                                                              \
+        const void *fn = (const void *)&k_gemm_p<T, NTV, SV, SWV>;                                            \
+        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV, SWV>), grid_of(fn), dim3(256), padded, st, dd, arena, meta); \
+        return;                                                                                               \
     }
+#define WMC_GP(NTV, SV) WMC_GP1(NTV, SV, false) WMC_GP1(NTV, SV, true)
 #define WMC_GP_S(NTV) WMC_GP(NTV, 1) WMC_GP(NTV, 2) WMC_GP(NTV, 4) WMC_GP(NTV, 8) WMC_GP(NTV, 16)
         WMC_GP_S(1) WMC_GP_S(2) WMC_GP_S(4) WMC_GP_S(8)
 #undef WMC_GP_S
 #undef WMC_GP
+#undef WMC_GP1
     }
     (void)full;
     const int KC = gemm_kc(hd.nk, hd.nn, (int)sizeof(T));
