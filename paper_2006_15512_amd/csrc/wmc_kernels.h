@@ -748,6 +748,246 @@ static void launch_stream(const StreamArgs &sa, T *arena, wmc_meta *meta, hipStr
     }
 }
 
+// Register-tiled streaming contraction for one big node,
+//
+//   C[beta, sigma, omega] = sum_kappa S[beta, sigma, kappa] * O[beta, omega, kappa]
+//
+// with S the larger operand, sigma the output bits only S has and omega the
+// output bits only O has.  Each thread owns P = 2^np values of (up to two,
+// high) sigma bits and Q = 2^nq values of (up to two, high) omega bits: it
+// loads P rows of S and Q rows of O (2^nk contiguous summed entries each, in
+// chunks of up to 4) and produces the P x Q outputs, so each S row is read
+// once per Q outputs and each O row once per P.  The remaining output bits
+// enumerate threads in C order, so for a fixed (p, q) the lanes of a wave
+// store consecutive outputs.  The bits chosen for P and Q are the ones whose
+// reuse distance in C order is largest.  O is staged in LDS when it has at
+// most 2^12 entries.  Every product is summed in the order of the summed
+// index and scaled once at the end, exactly as the generic node kernel does.
+#define STREAM2_RUNS 16
+#define STREAM2_O_LDS 4096
+
+struct Stream2Args {
+    long long s, o, c;                 // element offsets in the arena
+    int ts, to, tc;                    // meta entries of S, O, C
+    int rc;                            // output rank
+    int np, nq;                        // sigma bits and omega bits handled inside a thread
+    int pbit[2], qbit[2];              // their positions in C
+    int nlrun, nsrun, norun;
+    unsigned lrun[6];                  // thread index -> C address (runs src | len << 8 | dst << 16)
+    unsigned srun[STREAM2_RUNS];       // C address -> S row
+    unsigned orun[STREAM2_RUNS];       // C address -> O row
+    int ro;                            // storage rank of O, summed bits included
+    int o_lds;                         // O staged in LDS
+};
+
+// Bit extraction along at most MAX runs (unrolled with static indices, so
+// run words passed in kernel arguments stay in scalar registers).
+template <int MAX>
+__device__ __forceinline__ unsigned long long apply_runs(unsigned long long r, const unsigned *runs, int n) {
+    unsigned long long out = 0;
+#pragma unroll
+    for (int i = 0; i < MAX; ++i)
+        if (i < n) {
+            const unsigned w = runs[i];
+            out |= ((r >> (w & 255u)) & ((1ull << ((w >> 8) & 255u)) - 1ull)) << (w >> 16);
+        }
+    return out;
+}
+
+// KC consecutive entries of a row, widened to double.
+template <typename T, int KC>
+__device__ __forceinline__ void load_chunk(const T *__restrict__ p, double *v) {
+    if constexpr (sizeof(T) == 8 && KC >= 2) {
+#pragma unroll
+        for (int h = 0; h < KC / 2; ++h) {
+            const double2 x = ((const double2 *)p)[h];
+            v[2 * h] = x.x;
+            v[2 * h + 1] = x.y;
+        }
+    } else if constexpr (sizeof(T) == 4 && KC == 4) {
+        const float4 x = *(const float4 *)p;
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    } else if constexpr (sizeof(T) == 4 && KC == 2) {
+        const float2 x = *(const float2 *)p;
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) v[k] = (double)p[k];
+    }
+}
+
+template <typename T, int NK>
+__global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta) {
+    __shared__ double Os[STREAM2_O_LDS];
+    constexpr int K = 1 << NK;
+    constexpr int KC = K < 4 ? K : 4;
+    const int sS = scale_exp(meta[args.ts].maxbits);
+    const int sO = scale_exp(meta[args.to].maxbits);
+    const T *__restrict__ S = arena + args.s;
+    const T *__restrict__ O = arena + args.o;
+    T *__restrict__ C = arena + args.c;
+    if (args.o_lds) {
+        for (int i = threadIdx.x; i < (1 << args.ro); i += 256) Os[i] = (double)O[i];
+        __syncthreads();
+    }
+    const int P = 1 << args.np, Q = 1 << args.nq;
+    unsigned long long cP[4], sP[4], cQ[4], oQ[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        unsigned long long cp = 0, cq = 0;
+        for (int t = 0; t < args.np; ++t) cp |= (unsigned long long)((i >> t) & 1) << args.pbit[t];
+        for (int t = 0; t < args.nq; ++t) cq |= (unsigned long long)((i >> t) & 1) << args.qbit[t];
+        cP[i] = uniform64(cp);
+        cQ[i] = uniform64(cq);
+        sP[i] = uniform64(apply_runs<STREAM2_RUNS>(cp, args.srun, args.nsrun));
+        oQ[i] = uniform64(apply_runs<STREAM2_RUNS>(cq, args.orun, args.norun));
+    }
+    const unsigned long long threads = 1ull << (args.rc - args.np - args.nq);
+    double vmax = 0.0;
+    for (unsigned long long u = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; u < threads;
+         u += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long r0 = apply_runs<6>(u, args.lrun, args.nlrun);
+        const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
+        const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
+        double acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+#pragma unroll
+        for (int kc = 0; kc < K; kc += KC) {
+            double sv[4][KC], ov[4][KC];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < P) load_chunk<T, KC>(S + (((s0 | sP[i]) << NK) + kc), sv[i]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < Q) {
+                    const unsigned long long ob = ((o0 | oQ[j]) << NK) + kc;
+                    if (args.o_lds) {
+#pragma unroll
+                        for (int k = 0; k < KC; ++k) ov[j][k] = Os[ob + k];
+                    } else {
+                        load_chunk<T, KC>(O + ob, ov[j]);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (i < P && j < Q)
+#pragma unroll
+                        for (int k = 0; k < KC; ++k) acc[i][j] = fma(sv[i][k], ov[j][k], acc[i][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (i < P && j < Q) {
+                    const T v = (T)ldexp(acc[i][j], -(sS + sO));
+                    C[r0 | cP[i] | cQ[j]] = v;
+                    vmax = fmax(vmax, fabs((double)v));
+                }
+    }
+    publish_max(meta, args.tc, vmax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
+}
+
+// Arguments of the register-tiled streaming kernel for a single-node launch,
+// if the node fits it (at most 2^5 summed entries, run lists that fit).
+static inline bool stream2_args(const NodeDesc &d, Stream2Args *a) {
+    if (d.rc < 2 || d.nk > 5) return false;
+    auto bits_of = [&](const unsigned *runs, int nr, std::vector<int> &in) {
+        int n = 0;
+        for (int q = 0; q < nr; ++q) {
+            const unsigned src = runs[q] & 255u, len = (runs[q] >> 8) & 255u;
+            for (unsigned j = 0; j < len; ++j) in[(size_t)(src + j)] = 1;
+            n += (int)len;
+        }
+        return n;
+    };
+    std::vector<int> inA((size_t)d.rc + 1, 0), inB((size_t)d.rc + 1, 0);
+    const int na = bits_of(d.ra, d.nra, inA), nb = bits_of(d.rb, d.nrb, inB);
+    const bool a_is_s = na >= nb;
+    const std::vector<int> &inS = a_is_s ? inA : inB, &inO = a_is_s ? inB : inA;
+    const int nsr = a_is_s ? d.nra : d.nrb, nor = a_is_s ? d.nrb : d.nra;
+    if (nsr > STREAM2_RUNS || nor > STREAM2_RUNS) return false;
+    std::memset(a, 0, sizeof *a);
+    a->s = a_is_s ? d.a : d.b;
+    a->o = a_is_s ? d.b : d.a;
+    a->c = d.c;
+    a->ts = a_is_s ? d.ta : d.tb;
+    a->to = a_is_s ? d.tb : d.ta;
+    a->tc = d.tc;
+    a->rc = d.rc;
+    for (int q = 0; q < nsr; ++q) a->srun[q] = a_is_s ? d.ra[q] : d.rb[q];
+    for (int q = 0; q < nor; ++q) a->orun[q] = a_is_s ? d.rb[q] : d.ra[q];
+    a->nsrun = nsr;
+    a->norun = nor;
+    a->ro = (a_is_s ? nb : na) + d.nk;
+    // bits looped inside a thread: the highest S-only and O-only bits at or
+    // above bit 4 (lower ones are reused from cache between neighbouring
+    // lanes), while keeping at least 2^14 threads
+    const int budget = std::max(0, std::min(4, d.rc - 14));
+    int taken = 0;
+    for (int p = d.rc - 1; p >= 4 && taken < budget; --p) {
+        if (inS[(size_t)p] && !inO[(size_t)p] && a->np < 2) {
+            a->pbit[a->np++] = p;
+            ++taken;
+        } else if (inO[(size_t)p] && !inS[(size_t)p] && a->nq < 2) {
+            a->qbit[a->nq++] = p;
+            ++taken;
+        }
+    }
+    // remaining C bits, ascending, numbered by the thread index
+    std::vector<int> rest;
+    for (int p = 0; p < d.rc; ++p) {
+        bool used = false;
+        for (int t = 0; t < a->np; ++t) used |= a->pbit[t] == p;
+        for (int t = 0; t < a->nq; ++t) used |= a->qbit[t] == p;
+        if (!used) rest.push_back(p);
+    }
+    int nl = 0;
+    for (size_t t = 0; t < rest.size();) {
+        size_t e = t + 1;
+        while (e < rest.size() && rest[e] == rest[e - 1] + 1) ++e;
+        if (nl >= 6) return false;
+        a->lrun[nl++] = WMC_RUN(t, e - t, rest[t]);
+        t = e;
+    }
+    a->nlrun = nl;
+    a->o_lds = a->ro <= 12 && d.rc >= 16;
+    return true;
+}
+
+template <typename T>
+static void launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st) {
+    const unsigned long long threads = 1ull << (sa.rc - sa.np - sa.nq);
+    unsigned long long blocks = (threads + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    // every workgroup stages O in LDS: keep that below a quarter of the
+    // outputs, but keep at least four workgroups per CU
+    if (sa.o_lds && sa.rc - sa.ro >= 2) {
+        unsigned long long cap = 1ull << (sa.rc - sa.ro - 2);
+        if (cap < 1024) cap = 1024;
+        if (blocks > cap) blocks = cap;
+    }
+    if (blocks < 1) blocks = 1;
+    const dim3 g((unsigned)blocks), b(256);
+    switch (nk) {
+    case 0: hipLaunchKernelGGL((k_stream2<T, 0>), g, b, 0, st, sa, arena, meta); break;
+    case 1: hipLaunchKernelGGL((k_stream2<T, 1>), g, b, 0, st, sa, arena, meta); break;
+    case 2: hipLaunchKernelGGL((k_stream2<T, 2>), g, b, 0, st, sa, arena, meta); break;
+    case 3: hipLaunchKernelGGL((k_stream2<T, 3>), g, b, 0, st, sa, arena, meta); break;
+    case 4: hipLaunchKernelGGL((k_stream2<T, 4>), g, b, 0, st, sa, arena, meta); break;
+    default: hipLaunchKernelGGL((k_stream2<T, 5>), g, b, 0, st, sa, arena, meta); break;
+    }
+}
+
 // Many streaming nodes in one launch (the merged steps of batches and
 // serving).  Task t owns workgroups [block_begin_t, block_begin_{t+1}); each
 // workgroup produces STREAM_MULTI_QUADS consecutive quads of its node.  Tasks
