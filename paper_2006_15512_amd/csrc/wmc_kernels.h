@@ -820,11 +820,14 @@ __device__ __forceinline__ void load_chunk(const T *__restrict__ p, double *v) {
     }
 }
 
-template <typename T, int NK>
+// NP and NQ are compile-time so that the tile loops are straight-line code:
+// all loads issue before the first wait and no store waits on another.
+template <typename T, int NK, int NP, int NQ>
 __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta) {
     __shared__ double Os[STREAM2_O_LDS];
     constexpr int K = 1 << NK;
     constexpr int KC = K < 4 ? K : 4;
+    constexpr int P = 1 << NP, Q = 1 << NQ;
     const int sS = scale_exp(meta[args.ts].maxbits);
     const int sO = scale_exp(meta[args.to].maxbits);
     const T *__restrict__ S = arena + args.s;
@@ -834,64 +837,72 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
         for (int i = threadIdx.x; i < (1 << args.ro); i += 256) Os[i] = (double)O[i];
         __syncthreads();
     }
-    const int P = 1 << args.np, Q = 1 << args.nq;
-    unsigned long long cP[4], sP[4], cQ[4], oQ[4];
+    unsigned long long cP[P], sP[P], cQ[Q], oQ[Q];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        unsigned long long cp = 0, cq = 0;
-        for (int t = 0; t < args.np; ++t) cp |= (unsigned long long)((i >> t) & 1) << args.pbit[t];
-        for (int t = 0; t < args.nq; ++t) cq |= (unsigned long long)((i >> t) & 1) << args.qbit[t];
-        cP[i] = uniform64(cp);
-        cQ[i] = uniform64(cq);
-        sP[i] = uniform64(apply_runs<STREAM2_RUNS>(cp, args.srun, args.nsrun));
-        oQ[i] = uniform64(apply_runs<STREAM2_RUNS>(cq, args.orun, args.norun));
+    for (int i = 0; i < P; ++i) {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) c |= (unsigned long long)((i >> t) & 1) << args.pbit[t];
+        cP[i] = uniform64(c);
+        sP[i] = uniform64(apply_runs<STREAM2_RUNS>(c, args.srun, args.nsrun));
     }
-    const unsigned long long threads = 1ull << (args.rc - args.np - args.nq);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) c |= (unsigned long long)((j >> t) & 1) << args.qbit[t];
+        cQ[j] = uniform64(c);
+        oQ[j] = uniform64(apply_runs<STREAM2_RUNS>(c, args.orun, args.norun));
+    }
+    const int se = -(sS + sO);
+    const unsigned long long threads = 1ull << (args.rc - NP - NQ);
+    // workgroups are dealt to the 8 XCDs round-robin; renumber them so that
+    // each XCD walks one contiguous slab of threads per sweep and rows shared
+    // by nearby threads meet in that XCD's L2
+    const unsigned G = gridDim.x;
+    const unsigned lb = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
     double vmax = 0.0;
-    for (unsigned long long u = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; u < threads;
-         u += (unsigned long long)gridDim.x * blockDim.x) {
+    for (unsigned long long u = (unsigned long long)lb * blockDim.x + threadIdx.x; u < threads;
+         u += (unsigned long long)G * blockDim.x) {
         const unsigned long long r0 = apply_runs<6>(u, args.lrun, args.nlrun);
         const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
         const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
-        double acc[4][4];
+        double acc[P][Q];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < P; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+            for (int j = 0; j < Q; ++j) acc[i][j] = 0.0;
 #pragma unroll
         for (int kc = 0; kc < K; kc += KC) {
-            double sv[4][KC], ov[4][KC];
+            double sv[P][KC], ov[Q][KC];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (i < P) load_chunk<T, KC>(S + (((s0 | sP[i]) << NK) + kc), sv[i]);
+            for (int i = 0; i < P; ++i) load_chunk<T, KC>(S + (((s0 | sP[i]) << NK) + kc), sv[i]);
+            if (args.o_lds) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (j < Q) {
+                for (int j = 0; j < Q; ++j) {
                     const unsigned long long ob = ((o0 | oQ[j]) << NK) + kc;
-                    if (args.o_lds) {
 #pragma unroll
-                        for (int k = 0; k < KC; ++k) ov[j][k] = Os[ob + k];
-                    } else {
-                        load_chunk<T, KC>(O + ob, ov[j]);
-                    }
+                    for (int k = 0; k < KC; ++k) ov[j][k] = Os[ob + k];
                 }
+            } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < Q; ++j) load_chunk<T, KC>(O + (((o0 | oQ[j]) << NK) + kc), ov[j]);
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (i < P && j < Q)
+            for (int i = 0; i < P; ++i)
 #pragma unroll
-                        for (int k = 0; k < KC; ++k) acc[i][j] = fma(sv[i][k], ov[j][k], acc[i][j]);
+                for (int j = 0; j < Q; ++j)
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) acc[i][j] = fma(sv[i][k], ov[j][k], acc[i][j]);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < P; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (i < P && j < Q) {
-                    const T v = (T)ldexp(acc[i][j], -(sS + sO));
-                    C[r0 | cP[i] | cQ[j]] = v;
-                    vmax = fmax(vmax, fabs((double)v));
-                }
+            for (int j = 0; j < Q; ++j) {
+                const T v = (T)ldexp(acc[i][j], se);
+                C[r0 | cP[i] | cQ[j]] = v;
+                vmax = fmax(vmax, fabs((double)v));
+            }
     }
     publish_max(meta, args.tc, vmax);
     if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
@@ -964,8 +975,9 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a) {
     return true;
 }
 
+// Returns false (nothing launched) if no instance covers the arguments.
 template <typename T>
-static void launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st) {
+static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st) {
     const unsigned long long threads = 1ull << (sa.rc - sa.np - sa.nq);
     unsigned long long blocks = (threads + 255) / 256;
     if (blocks > 4096) blocks = 4096;
@@ -977,15 +989,20 @@ static void launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
         if (blocks > cap) blocks = cap;
     }
     if (blocks < 1) blocks = 1;
+    if (blocks >= 64) blocks = (blocks + 7) & ~7ull;  // whole XCD rounds; threads past the end idle
     const dim3 g((unsigned)blocks), b(256);
-    switch (nk) {
-    case 0: hipLaunchKernelGGL((k_stream2<T, 0>), g, b, 0, st, sa, arena, meta); break;
-    case 1: hipLaunchKernelGGL((k_stream2<T, 1>), g, b, 0, st, sa, arena, meta); break;
-    case 2: hipLaunchKernelGGL((k_stream2<T, 2>), g, b, 0, st, sa, arena, meta); break;
-    case 3: hipLaunchKernelGGL((k_stream2<T, 3>), g, b, 0, st, sa, arena, meta); break;
-    case 4: hipLaunchKernelGGL((k_stream2<T, 4>), g, b, 0, st, sa, arena, meta); break;
-    default: hipLaunchKernelGGL((k_stream2<T, 5>), g, b, 0, st, sa, arena, meta); break;
+#define WMC_S2(NKV, NPV, NQV)                                                                  \
+    if (nk == NKV && sa.np == NPV && sa.nq == NQV) {                                           \
+        hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, 0, st, sa, arena, meta);       \
+        return true;                                                                           \
     }
+#define WMC_S2_PQ(NKV)                                                                         \
+    WMC_S2(NKV, 0, 0) WMC_S2(NKV, 0, 1) WMC_S2(NKV, 0, 2) WMC_S2(NKV, 1, 0) WMC_S2(NKV, 1, 1) \
+    WMC_S2(NKV, 1, 2) WMC_S2(NKV, 2, 0) WMC_S2(NKV, 2, 1) WMC_S2(NKV, 2, 2)
+    WMC_S2_PQ(0) WMC_S2_PQ(1) WMC_S2_PQ(2) WMC_S2_PQ(3) WMC_S2_PQ(4) WMC_S2_PQ(5)
+#undef WMC_S2_PQ
+#undef WMC_S2
+    return false;
 }
 
 // Many streaming nodes in one launch (the merged steps of batches and
