@@ -40,10 +40,32 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Raise the running max of tensor t to v.  The max only grows, so a value
+// read without the atomic is never above the true one: when v does not
+// exceed it the atomic is skipped, and after the first few waves almost
+// every wave skips it (many waves updating one address serialise there).
+__device__ __forceinline__ void raise_max(wmc_meta *meta, int t, double v) {
+    if (!(v > 0.0)) return;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b > __atomic_load_n(&meta[t].maxbits, __ATOMIC_RELAXED)) atomicMax(&meta[t].maxbits, b);
+}
+
 __device__ __forceinline__ void publish_max(wmc_meta *meta, int t, double v) {
     v = wave_max(v);
-    if ((threadIdx.x & (WMC_WAVE - 1)) == 0 && v > 0.0)
-        atomicMax(&meta[t].maxbits, (unsigned long long)__double_as_longlong(v));
+    if ((threadIdx.x & (WMC_WAVE - 1)) == 0) raise_max(meta, t, v);
+}
+
+// The same for a whole workgroup; every thread of the block must call it.
+__device__ __forceinline__ void publish_max_block(wmc_meta *meta, int t, double v) {
+    __shared__ double red[16];
+    v = wave_max(v);
+    const int nw = (int)((blockDim.x + WMC_WAVE - 1) / WMC_WAVE);
+    if ((threadIdx.x & (WMC_WAVE - 1)) == 0) red[threadIdx.x / WMC_WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < nw; ++i) v = fmax(v, red[i]);
+        raise_max(meta, t, v);
+    }
 }
 
 // bit extraction of r along runs (src bit, length, dst bit)
@@ -312,7 +334,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T 
             }
         }
     }
-    publish_max(meta, d.tc, vmax);
+    publish_max_block(meta, d.tc, vmax);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
 }
@@ -481,7 +503,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
             }
         }
     }
-    publish_max(meta, d.tc, vmax);
+    publish_max_block(meta, d.tc, vmax);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
 }
@@ -678,7 +700,7 @@ __global__ void __launch_bounds__(256) k_stream(const StreamArgs args, T *__rest
 #pragma unroll
         for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs((double)(T)o[e]));
     }
-    publish_max(meta, args.tc, vmax);
+    publish_max_block(meta, args.tc, vmax);
     if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
 }
 
@@ -824,7 +846,8 @@ __device__ __forceinline__ void load_chunk(const T *__restrict__ p, double *v) {
 // all loads issue before the first wait and no store waits on another.
 template <typename T, int NK, int NP, int NQ>
 __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta) {
-    __shared__ double Os[STREAM2_O_LDS];
+    extern __shared__ char smem_raw[];
+    double *Os = (double *)smem_raw;  // 2^ro entries when O is staged, else none
     constexpr int K = 1 << NK;
     constexpr int KC = K < 4 ? K : 4;
     constexpr int P = 1 << NP, Q = 1 << NQ;
@@ -904,7 +927,7 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
                 vmax = fmax(vmax, fabs((double)v));
             }
     }
-    publish_max(meta, args.tc, vmax);
+    publish_max_block(meta, args.tc, vmax);
     if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
 }
 
@@ -971,7 +994,7 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a) {
         t = e;
     }
     a->nlrun = nl;
-    a->o_lds = a->ro <= 12 && d.rc >= 16;
+    a->o_lds = (1 << a->ro) <= STREAM2_O_LDS && d.rc >= 16;
     return true;
 }
 
@@ -981,19 +1004,18 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
     const unsigned long long threads = 1ull << (sa.rc - sa.np - sa.nq);
     unsigned long long blocks = (threads + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    // every workgroup stages O in LDS: keep that below a quarter of the
-    // outputs, but keep at least four workgroups per CU
-    if (sa.o_lds && sa.rc - sa.ro >= 2) {
-        unsigned long long cap = 1ull << (sa.rc - sa.ro - 2);
-        if (cap < 1024) cap = 1024;
-        if (blocks > cap) blocks = cap;
-    }
     if (blocks < 1) blocks = 1;
     if (blocks >= 64) blocks = (blocks + 7) & ~7ull;  // whole XCD rounds; threads past the end idle
+    // stage O in LDS only where each workgroup reuses it at least 16 times
+    // over; smaller reuse is served by the caches without the staging pass
+    Stream2Args a = sa;
+    const unsigned long long outs_per_wg = (1ull << sa.rc) / blocks;
+    if (a.o_lds && outs_per_wg < (16ull << sa.ro)) a.o_lds = 0;
+    const size_t lds = a.o_lds ? sizeof(double) << a.ro : 0;
     const dim3 g((unsigned)blocks), b(256);
 #define WMC_S2(NKV, NPV, NQV)                                                                  \
-    if (nk == NKV && sa.np == NPV && sa.nq == NQV) {                                           \
-        hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, 0, st, sa, arena, meta);       \
+    if (nk == NKV && a.np == NPV && a.nq == NQV) {                                             \
+        hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, lds, st, a, arena, meta);      \
         return true;                                                                           \
     }
 #define WMC_S2_PQ(NKV)                                                                         \
@@ -1072,7 +1094,7 @@ __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restri
 #pragma unroll
         for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs((double)(T)o[e]));
     }
-    publish_max(meta, args.tc, vmax);
+    publish_max_block(meta, args.tc, vmax);
     if (lb == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
 }
 
