@@ -229,7 +229,9 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int out_row(int g, int v) { return 4 * g + v; }
 };
 
+#ifndef GEMM_TILES_PER_WAVE
 #define GEMM_TILES_PER_WAVE 2
+#endif
 #define GEMM_TILES (4 * GEMM_TILES_PER_WAVE)
 #define GEMM_LDS_BYTES (48 * 1024)
 
@@ -350,6 +352,12 @@ __device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Row tiles per wave and tile group of the persistent kernel: two for FP64
+// with at most 32 columns, else one (measured: the FP32 and the wide FP64
+// variants run faster with more, smaller groups per workgroup).
+template <typename T>
+__host__ __device__ constexpr int gemm_tpw(int nt) { return (sizeof(T) == 8 && nt <= 2) ? 2 : 1; }
+
 // SW selects the orientation of the matrix instruction.  SW = false: lane l
 // of an output tile holds column l%16 and rows out_row(l/16, v).  SW = true
 // computes the transposed tile (operands swapped: B^T A^T), so lane l holds
@@ -375,7 +383,8 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
     const int N = 1 << d.nn;
     constexpr int LDN = NT * 16 + (sizeof(T) == 8 ? 2 : 4);
     const unsigned long long tiles = 1ull << (d.nm - 4);
-    const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;
+    constexpr int TPW = gemm_tpw<T>(NT);
+    const unsigned long long groups = (tiles + 4 * TPW - 1) / (4 * TPW);
     const unsigned long long beta = blockIdx.y;
     const long long a0 = d.a, c0 = d.c;
     const int sA = scale_exp(meta[d.ta].maxbits);
@@ -384,6 +393,23 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
     const unsigned long long colBeta = pext_runs(beta, d.run[GR_BETA_B], d.nrun[GR_BETA_B]);
     const unsigned long long cBeta = pext_runs(beta, d.run[GR_BETA_C], d.nrun[GR_BETA_C]);
     const double scale = ldexp(1.0, -(sA + sB));
+
+    // A fragments: loads are unconditional (a row tile past the end reads
+    // tile 0 and is discarded) so the compiler can count them precisely
+    T an[TPW][S];
+    bool okn[TPW];
+    auto load = [&](unsigned long long grp) {
+#pragma unroll
+        for (int rt = 0; rt < TPW; ++rt) {
+            unsigned long long t = (grp * 4 + wave) * TPW + rt;
+            okn[rt] = grp < groups && t < tiles;
+            long long base =
+                a0 + l16 + (long long)((pext_runs(okn[rt] ? t : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << (4 + nk));
+#pragma unroll
+            for (int s = 0; s < S; ++s) an[rt][s] = arena[base + 16 * (4 * s + g)];
+        }
+    };
+    load(blockIdx.x);  // first A tile group in flight while B is staged
 
     // B[beta] as [k][column], columns N..16*NT-1 zero
     for (int idx = threadIdx.x; idx < NT * 16 * K; idx += 256) {
@@ -422,43 +448,27 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
             ucol_t[ct] = uniform64(pext_runs((unsigned long long)(ct * 16), d.run[GR_NU_C], d.nrun[GR_NU_C]));
     }
 
-    // A fragments: loads are unconditional (a row tile past the end reads
-    // tile 0 and is discarded) so the compiler can count them precisely
-    T an[GEMM_TILES_PER_WAVE][S];
-    bool okn[GEMM_TILES_PER_WAVE];
-    auto load = [&](unsigned long long grp) {
-#pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-            unsigned long long t = (grp * 4 + wave) * GEMM_TILES_PER_WAVE + rt;
-            okn[rt] = grp < groups && t < tiles;
-            long long base =
-                a0 + l16 + (long long)((pext_runs(okn[rt] ? t : 0, d.run[GR_MU_A], d.nrun[GR_MU_A]) | rowBeta) << (4 + nk));
-#pragma unroll
-            for (int s = 0; s < S; ++s) an[rt][s] = arena[base + 16 * (4 * s + g)];
-        }
-    };
-    load(blockIdx.x);
     __syncthreads();
     double vmax = 0.0;
     for (unsigned long long grp = blockIdx.x; grp < groups; grp += gridDim.x) {
-        T a[GEMM_TILES_PER_WAVE][S];
-        bool ok[GEMM_TILES_PER_WAVE];
+        T a[TPW][S];
+        bool ok[TPW];
 #pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+        for (int rt = 0; rt < TPW; ++rt) {
             ok[rt] = okn[rt];
 #pragma unroll
             for (int s = 0; s < S; ++s) a[rt][s] = an[rt][s];
         }
-        unsigned long long thi[GEMM_TILES_PER_WAVE];
+        unsigned long long thi[TPW];
 #pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
-            unsigned long long t = (grp * 4 + wave) * GEMM_TILES_PER_WAVE + rt;
+        for (int rt = 0; rt < TPW; ++rt) {
+            unsigned long long t = (grp * 4 + wave) * TPW + rt;
             thi[rt] = pext_runs(ok[rt] ? (t << 4) : 0, d.run[GR_MU_C], d.nrun[GR_MU_C]);
         }
         load(grp + gridDim.x);
-        acc_t acc[GEMM_TILES_PER_WAVE][NT];
+        acc_t acc[TPW][NT];
 #pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt)
+        for (int rt = 0; rt < TPW; ++rt)
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
 #pragma unroll
@@ -467,7 +477,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
             for (int ct = 0; ct < NT; ++ct) {
                 T b = Bs[(4 * s + g) * LDN + ct * 16 + l16];
 #pragma unroll
-                for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+                for (int rt = 0; rt < TPW; ++rt) {
                     if constexpr (SW)
                         acc[rt][ct] = Mfma<T>::step(b, a[rt][s], acc[rt][ct]);
                     else
@@ -476,7 +486,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
             }
         }
 #pragma unroll
-        for (int rt = 0; rt < GEMM_TILES_PER_WAVE; ++rt) {
+        for (int rt = 0; rt < TPW; ++rt) {
             if (!ok[rt]) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -527,7 +537,7 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
     const int N = 1 << hd.nn, K = 1 << hd.nk;
     const int NT = (N + 15) / 16;
     const unsigned long long tiles = 1ull << (hd.nm - 4);
-    const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;
+    const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;  // fallback kernel
     const size_t full = (size_t)K * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
     const size_t padded = (size_t)K * (NT * 16 + (sizeof(T) == 8 ? 2 : 4)) * sizeof(T);
     if (K >= 4 && K <= 64 && padded <= (size_t)lds_budget()) {
@@ -542,7 +552,9 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
             const unsigned long long total = (unsigned long long)cus * (unsigned long long)per_cu;
             unsigned long long per_beta = (total + (1ull << hd.nb) - 1) >> hd.nb;
             if (per_beta < 1) per_beta = 1;
-            return dim3((unsigned)(groups < per_beta ? groups : per_beta), 1u << hd.nb);
+            const unsigned long long tg = 4ull * (unsigned long long)gemm_tpw<T>(NTp);
+            const unsigned long long pgroups = (tiles + tg - 1) / tg;
+            return dim3((unsigned)(pgroups < per_beta ? pgroups : per_beta), 1u << hd.nb);
         };
         // transposed tiles when C's lowest address bit is a row bit
         bool sw = false;
