@@ -40,6 +40,10 @@ def workload(name: str):
         return f, dict(kind="order", order=wl.row_major_order(24, 24), block=5), \
             "grid CNF 24x24 lattice (576 vars, 2 planted-sign binary clauses per edge + 110 local ternary), " \
             "w~U(0.1,0.9), seed 0, row-major sweep tree"
+    if name == "grid24_minfill":
+        f = wl.grid_cnf(24, 24, 0.10, seed=0)
+        return f, dict(kind="minfill", seed=0, rank_cap=26, block=3), \
+            "grid CNF 24x24 lattice (as grid24), seeded min-fill tree (max rank 34) sliced to rank 26"
     if name == "grid12":
         f = wl.grid_cnf(12, 24, 0.10, seed=1)
         return f, dict(kind="order", order=wl.row_major_order(12, 24)), "grid CNF 12x24, seed 1, row-major sweep"
@@ -82,7 +86,7 @@ def cpu_baseline(name: str):
     workload, scaled to solves/s of the full workload."""
     import oracle
     if name.startswith("grid"):
-        rows_full = 24 if name == "grid24" else 12
+        rows_full = 24 if name.startswith("grid24") else 12
         rows = 4
         f = wl.grid_cnf(rows, 24, 0.10, seed=0)
         t0 = time.perf_counter()
@@ -106,6 +110,39 @@ def cpu_baseline(name: str):
         sample = f"oracle bucket elimination, {k} full solves in {dt:.1f}s"
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample}
+
+
+def achievable(torch, precision: str):
+    """What the device reaches on plain work, measured live: a 1 GiB
+    device-to-device copy (bytes read + written per second) and a library
+    GEMM of 8192^3 in the path's precision."""
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * n * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    m = 8192
+    a = torch.rand(m, m, dtype=dt, device="cuda")
+    b = torch.rand(m, m, dtype=dt, device="cuda")
+    c = a @ b
+    e0.record()
+    for _ in range(3):
+        c = a @ b
+    e1.record()
+    torch.cuda.synchronize()
+    gemm_tf = 3 * 2 * m ** 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(copy_gbs, 1), "gemm_tflops": round(gemm_tf, 2),
+            "gemm": f"torch.matmul {m}^3 {'f64' if precision == 'fp64' else 'f32'}"}
 
 
 def bench_batch(args, W, torch):
@@ -232,6 +269,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--block", type=int, default=0, help="variables per elimination step (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true", help="skip the achievable copy/GEMM probes")
     ap.add_argument("--queries", type=int, default=10000, help="serving: queries per rate")
     ap.add_argument("--slots", type=int, default=128, help="serving: requests in flight")
     ap.add_argument("--rates", type=float, nargs="+", default=[1000, 4000, 16000, 32000],
@@ -320,6 +358,11 @@ def main():
     else:
         roof = {"bound": "mfma", "achieved": round(ach_tf, 2), "peak": peak_tf, "unit": "TFLOP/s",
                 "frac": round(ach_tf / peak_tf, 4), "traffic": traffic}
+    if not args.no_probes:
+        ach = achievable(torch, args.precision)
+        roof["achievable"] = ach
+        roof["frac_of_achievable"] = round(ach_gbs / ach["copy_gbs"], 4) if bound == "hbm" else \
+            round(ach_tf / ach["gemm_tflops"], 4)
     roof["kernel"] = KERNEL_OF_CLASS[dom]
     roof["launches_per_solve"] = d["launches"]
     roof["bytes_per_launch"] = d["bytes"] / d["launches"]
@@ -351,7 +394,7 @@ def main():
         "roofline": roof,
     }
     gpath = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
-    gname = {"grid24": "grid24x24_t0.10_s0", "grid12": "grid12x24_t0.10_s1",
+    gname = {"grid24": "grid24x24_t0.10_s0", "grid24_minfill": "grid24x24_t0.10_s0", "grid12": "grid12x24_t0.10_s1",
              "banded300": "banded300_m1050_W37_s0"}.get(args.workload)
     if gname and os.path.exists(gpath):
         with open(gpath) as fh:

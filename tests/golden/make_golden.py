@@ -6,6 +6,7 @@ power-of-two exponent) on inputs from the seeded generators; nothing here
 touches the GPU library.  Usage:
 
     python tests/golden/make_golden.py [name ...]
+    python tests/golden/make_golden.py batch512
 """
 from __future__ import annotations
 
@@ -37,7 +38,30 @@ def cases():
     }
 
 
+BATCH_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch512_oracle.json")
+
+
+def make_batch512():
+    """Oracle values of all 512 instances of the batch recipe
+    (`wmc_workloads.batch_instance(i)`, oracle min-fill order)."""
+    t0 = time.time()
+    rows = []
+    for i in range(512):
+        f = wl.batch_instance(i)
+        m, e = oracle.bucket(f)
+        rows.append({"i": i, "digest": f.digest(), "n": f.n, "m": f.m, "mantissa_hex": float(m).hex(),
+                     "exp2": int(e)})
+    with open(BATCH_OUT, "w") as fh:
+        json.dump({"description": "batch_instance(i), i < 512; oracle bucket elimination (FP64, carried exponent)",
+                   "instances": rows}, fh, indent=0)
+    print("batch512", f"{time.time() - t0:.1f}s", sum(1 for r in rows if float.fromhex(r["mantissa_hex"]) == 0.0),
+          "zero", flush=True)
+
+
 def main(names):
+    if names == ["batch512"]:
+        make_batch512()
+        return
     data = {}
     if os.path.exists(OUT):
         with open(OUT) as fh:

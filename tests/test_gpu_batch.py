@@ -1,4 +1,6 @@
 """GPU tests of batched execution (many plans in shared launches)."""
+import json
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -100,3 +102,29 @@ def test_batch_workspace_too_small(instances):
     with pytest.raises(W.WmcError) as e:
         b.contract(ws=ws)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_batch512_all_instances_vs_stored_oracle(precision, tol):
+    """Every instance of the 512-instance batch in one batch against the
+    oracle values stored by tests/golden/make_golden.py (half the recipe's
+    instances are unsatisfiable: those must come back exactly 0)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch512_oracle.json")
+    with open(path) as fh:
+        rows = json.load(fh)["instances"]
+    fs = [wl.batch_instance(i) for i in range(512)]
+    for f, r in zip(fs, rows):
+        assert f.digest() == r["digest"]
+    plans = [W.Plan(W.Network.from_formula(f), seed=i, precision=precision) for i, f in enumerate(fs)]
+    b = W.Batch(plans)
+    say(f"batch512 {precision}: {b.n_launches} launches")
+    vals = b.contract(flags=W.BATCH_GRAPH)
+    zeros = 0
+    for q, (v, r) in enumerate(zip(vals, rows)):
+        ref = Fraction(float.fromhex(r["mantissa_hex"])) * Fraction(2) ** r["exp2"]
+        if ref == 0:
+            zeros += 1
+            assert v.mantissa == 0.0, q
+        else:
+            assert rel(frac(v), ref) <= tol, q
+    assert zeros == sum(1 for r in rows if float.fromhex(r["mantissa_hex"]) == 0.0)

@@ -259,6 +259,37 @@ def test_banded300_sliced_vs_golden(precision, tol, block):
     assert rel(value_fraction(v), ref) <= tol
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_grid24_minfill_sliced_vs_golden(precision, tol):
+    """The same 24x24 lattice on its seeded min-fill tree (max storage rank
+    34) sliced to rank 26: 128 slices, against the oracle's stored value."""
+    g = _golden("grid24x24_t0.10_s0")
+    f = wl.grid_cnf(24, 24, 0.10, seed=0)
+    assert f.digest() == g["digest"]
+    say(f"grid24 minfill sliced {precision}")
+    v, p = run(f, kind="minfill", seed=0, rank_cap=26, block=3, precision=precision)
+    st = p.stats()
+    assert st["max_rank"] <= 26 and st["max_rank_unsliced"] >= 32 and st["n_slices"] >= 64
+    ref = Fraction(float.fromhex(g["mantissa_hex"])) * Fraction(2) ** g["exp2"]
+    assert rel(value_fraction(v), ref) <= tol
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_banded_medium_stream_shapes_fp32(seed):
+    """Scaled FP32 through the streaming and matrix kernels on irregular
+    layouts (banded 3-CNF, 140 variables, ratio 2.8, satisfiable, min-fill
+    trees, blocks 1-4)."""
+    f = wl.banded_3cnf(140, 390, 26, seed=seed)
+    m, e = oracle.bucket(f)
+    ref = Fraction(m) * Fraction(2) ** e
+    assert ref > 0
+    for kw in (dict(seed=seed), dict(seed=seed, block=2), dict(seed=seed, block=4),
+               dict(seed=seed, block=3, rank_cap=17)):
+        say(f"banded140 fp32 seed={seed} {kw}")
+        v, _ = run(f, precision="fp32", **kw)
+        assert rel(value_fraction(v), ref) <= 1e-5
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_banded_medium_stream_shapes(seed):
     """Banded 3-CNF of 120 variables (max rank ~20): min-fill trees with
