@@ -55,7 +55,8 @@ typedef enum {
     WMC_TREE_EXPLICIT = 2  /* caller-supplied contraction tree (parent array) */
 } wmc_tree_kind;
 
-#define WMC_MAX_CLAUSE 24   /* distinct variables per clause */
+#define WMC_MAX_CLAUSE 24   /* distinct variables of a clause tensor */
+#define WMC_FACTOR_ABOVE 8  /* longer clauses are factored into chains of 3-literal clauses */
 #define WMC_MAX_RANK 34     /* largest storage rank of any intermediate */
 #define WMC_MAX_SLICED 40   /* largest number of sliced variables */
 
@@ -82,9 +83,13 @@ typedef struct wmc_plan_t wmc_plan_t;
  *   weights:    2*n_vars doubles {W(x,0), W(x,1)} for x = 1..n_vars (finite)
  * Repeated literals collapse; a clause holding x and not-x is always true;
  * an empty clause makes W = 0; a variable in no clause contributes
- * W(x,0)+W(x,1).  Clauses with more than WMC_MAX_CLAUSE distinct variables
- * return WMC_ERR_UNSUPPORTED.  The COPY tensors A_x are kept symbolically
- * (degree, W(x,0), W(x,1)) and never materialised. */
+ * W(x,0)+W(x,1).  A clause with more than WMC_FACTOR_ABOVE distinct
+ * variables is factored into a chain of clauses of at most 3 literals over
+ * k-2 auxiliary variables of weight (1, 1) that record the OR of a prefix of
+ * the clause (exact: W is unchanged); the caller still passes 2*n_vars
+ * weights everywhere, and auxiliary variables never appear in its orders.
+ * The COPY tensors A_x are kept symbolically (degree, W(x,0), W(x,1)) and
+ * never materialised. */
 wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
                              const int32_t *lits, const double *weights, wmc_network **out);
 
@@ -137,6 +142,8 @@ typedef struct {
     int64_t class_hist[WMC_N_CLASSES];
     int64_t n_launches;         /* kernel launches per slice */
     double max_node_bytes;      /* largest single-node traffic */
+    int32_t n_aux_vars;         /* auxiliary variables of factored long clauses */
+    int32_t reserved0;
 } wmc_plan_info;
 
 wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *opts, wmc_plan_t **out);

@@ -64,7 +64,7 @@ class wmc_plan_info(ctypes.Structure):
                 ("bytes_per_slice", ctypes.c_double), ("peak_live_bytes", ctypes.c_double),
                 ("arena_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
                 ("class_hist", ctypes.c_int64 * N_CLASSES), ("n_launches", ctypes.c_int64),
-                ("max_node_bytes", ctypes.c_double)]
+                ("max_node_bytes", ctypes.c_double), ("n_aux_vars", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 _lib = None

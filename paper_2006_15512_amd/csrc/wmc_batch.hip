@@ -46,10 +46,12 @@ struct wmc_batch {
     int32_t precision = WMC_FP64;
     int32_t elem = 8;
     int64_t n = 0;
-    int64_t n_vars_total = 0;
+    int64_t n_vars_total = 0;          // auxiliary variables included
+    int64_t n_user_total = 0;          // caller weights: 2 * n_user of each plan, in plan order
     std::vector<int64_t> var_off;
-    std::vector<int32_t> nvars;
+    std::vector<int32_t> nvars, nuser;
     std::vector<double> w;
+    std::vector<double> wstage;        // caller weights expanded with the auxiliary (1, 1)
     std::vector<LeafDesc> leaves;
     int64_t leaf_work = 0;
     std::vector<NodeDesc> nodes;
@@ -118,6 +120,8 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
             mbase[(size_t)i] = meta;
             B->var_off.push_back(vars);
             B->nvars.push_back(P.n);
+            B->nuser.push_back(P.n_user);
+            B->n_user_total += P.n_user;
             B->w.insert(B->w.end(), P.w.begin(), P.w.end());
             arena_elems += (int64_t)bal(P.arena_bytes / (uint64_t)P.elem, 64);
             meta += (int64_t)P.T.size();
@@ -304,9 +308,8 @@ extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, vo
                       (unsigned long long)workspace_bytes, (unsigned long long)B.workspace_bytes);
         return WMC_ERR_OUT_OF_MEMORY;
     }
-    const double *w = weights ? weights : B.w.data();
     if (weights)
-        for (int64_t i = 0; i < 2 * B.n_vars_total; ++i)
+        for (int64_t i = 0; i < 2 * B.n_user_total; ++i)
             if (!std::isfinite(weights[i])) {
                 wmc_set_error("wmc_batch_contract: weight %lld is not finite", (long long)i);
                 return WMC_ERR_INVALID_ARGUMENT;
@@ -314,6 +317,17 @@ extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, vo
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
     std::lock_guard<std::mutex> lock(B.mu);
+    const double *w = B.w.data();
+    if (weights) {
+        // the caller's weights per instance, then each instance's auxiliary (1, 1)
+        B.wstage = B.w;
+        int64_t u = 0;
+        for (size_t i = 0; i < B.nvars.size(); ++i) {
+            std::copy(weights + 2 * u, weights + 2 * (u + B.nuser[i]), B.wstage.begin() + 2 * B.var_off[i]);
+            u += B.nuser[i];
+        }
+        w = B.wstage.data();
+    }
     if (B.n_vars_total > 0)
         HIP_TRY(hipMemcpyAsync(ws + B.off_w, w, sizeof(double) * 2 * (size_t)B.n_vars_total, hipMemcpyHostToDevice, st));
     if (!(flags & WMC_BATCH_RESIDENT))

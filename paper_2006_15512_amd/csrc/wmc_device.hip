@@ -18,6 +18,18 @@ struct LaunchTimer {
     }
 };
 
+// Weights into the workspace: the caller's 2 * n_user (or the network's),
+// then the constant (1, 1) of auxiliary variables from the plan.
+static hipError_t upload_weights(const wmc_plan_t &P, const double *weights, char *ws, hipStream_t st) {
+    const double *w = weights ? weights : P.w.data();
+    hipError_t e = hipSuccess;
+    if (P.n_user > 0) e = hipMemcpyAsync(ws + P.off_w, w, sizeof(double) * 2 * (size_t)P.n_user, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && P.n > P.n_user)
+        e = hipMemcpyAsync(ws + P.off_w + sizeof(double) * 2 * (size_t)P.n_user, P.w.data() + 2 * (size_t)P.n_user,
+                           sizeof(double) * 2 * (size_t)(P.n - P.n_user), hipMemcpyHostToDevice, st);
+    return e;
+}
+
 template <typename T>
 static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long long b, long long e,
                              wmc_value *per_slice, LaunchTimer *tm = nullptr) {
@@ -92,7 +104,7 @@ extern "C" wmc_status wmc_contract_slices(const wmc_plan_t *plan, const double *
         return WMC_ERR_INVALID_ARGUMENT;
     }
     if (weights)
-        for (int64_t i = 0; i < 2 * (int64_t)P.n; ++i)
+        for (int64_t i = 0; i < 2 * (int64_t)P.n_user; ++i)
             if (!std::isfinite(weights[i])) {
                 wmc_set_error("wmc_contract: weight %lld is not finite", (long long)i);
                 return WMC_ERR_INVALID_ARGUMENT;
@@ -118,8 +130,7 @@ extern "C" wmc_status wmc_contract_slices(const wmc_plan_t *plan, const double *
     }
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
-    const double *w = weights ? weights : P.w.data();
-    if (P.n > 0) HIP_TRY(hipMemcpyAsync(ws + P.off_w, w, sizeof(double) * 2 * (size_t)P.n, hipMemcpyHostToDevice, st));
+    HIP_TRY(upload_weights(P, weights, ws, st));
     HIP_TRY(hipMemcpyAsync(ws + P.off_leaf, P.desc_image.data(), P.desc_bytes, hipMemcpyHostToDevice, st));
     wmc_status s = P.precision == WMC_FP64 ? run_slices<double>(P, ws, st, slice_begin, slice_end, per_slice)
                                            : run_slices<float>(P, ws, st, slice_begin, slice_end, per_slice);
@@ -172,10 +183,8 @@ extern "C" wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double 
     tm.ev.resize((size_t)n + 1);
     for (auto &e : tm.ev) HIP_TRY(hipEventCreate(&e));
     for (int64_t k = 0; k < cap; ++k) ms[k] = 0.f;
-    const double *w = weights ? weights : P.w.data();
     wmc_status s = WMC_OK;
-    if (P.n > 0 && hipMemcpyAsync(ws + P.off_w, w, sizeof(double) * 2 * (size_t)P.n, hipMemcpyHostToDevice, st) != hipSuccess)
-        s = WMC_ERR_DEVICE;
+    if (upload_weights(P, weights, ws, st) != hipSuccess) s = WMC_ERR_DEVICE;
     if (s == WMC_OK && hipMemcpyAsync(ws + P.off_leaf, P.desc_image.data(), P.desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
         s = WMC_ERR_DEVICE;
     const long long ns = 1ll << P.sliced.size();

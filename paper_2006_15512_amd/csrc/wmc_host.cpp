@@ -64,33 +64,77 @@ extern "C" wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const
     for (int64_t i = 0; i < 2 * (int64_t)n_vars; ++i)
         if (!std::isfinite(weights[i]))
             WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: weight %lld is not finite", (long long)i);
+    for (int64_t j = n_clauses > 0 ? clause_ptr[0] : 0; n_clauses > 0 && j < clause_ptr[n_clauses]; ++j)
+        if (lits[j] == 0 || lits[j] > n_vars || lits[j] < -n_vars)
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: literal %d out of range", (int)lits[j]);
     try {
-        wmc_network *net = new wmc_network();
-        net->n = n_vars;
-        net->w.assign(weights, weights + 2 * (size_t)n_vars);
-        net->degree.assign((size_t)n_vars, 0);
-        net->clauses.resize((size_t)n_clauses);
-        std::vector<int8_t> sign((size_t)n_vars + 1, 0);  // bit0: positive seen, bit1: negative seen
-        for (int64_t c = 0; c < n_clauses; ++c) {
-            WClause &cl = net->clauses[(size_t)c];
-            for (int64_t j = clause_ptr[c]; j < clause_ptr[c + 1]; ++j) {
-                int32_t l = lits[j];
-                if (l == 0 || l > n_vars || l < -n_vars) {
-                    delete net;
-                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: literal %d out of range in clause %lld",
-                             (int)l, (long long)c);
+        // Clauses with more than WMC_FACTOR_ABOVE distinct variables are
+        // factored into a chain of clauses of at most three literals over
+        // auxiliary variables a_1..a_{k-2} (the clause is a COPY-like OR, and
+        // an OR is tree-factorable, Def. 4): a_1 <-> l_1 v l_2,
+        // a_i <-> a_{i-1} v l_{i+1}, and the clause a_{k-2} v l_k.  Each
+        // assignment of the formula's variables extends to exactly one
+        // assignment of the a_i, and the a_i weigh (1, 1), so W is unchanged.
+        std::vector<std::vector<int32_t>> cls;
+        std::vector<std::vector<int32_t>> aux_prefix;
+        cls.reserve((size_t)n_clauses);
+        {
+            std::vector<int8_t> sign((size_t)n_vars + 1, 0);
+            for (int64_t c = 0; c < n_clauses; ++c) {
+                std::vector<int32_t> lv;  // distinct literals, first occurrence order
+                bool taut = false;
+                for (int64_t j = clause_ptr[c]; j < clause_ptr[c + 1]; ++j) {
+                    const int32_t l = lits[j], v = l > 0 ? l : -l;
+                    const int8_t bit = l > 0 ? 1 : 2;
+                    if (!(sign[v] & bit)) {
+                        if (sign[v]) taut = true;
+                        else lv.push_back(l);
+                        sign[v] |= bit;
+                    }
                 }
+                for (int32_t l : lv) sign[(size_t)(l > 0 ? l : -l)] = 0;
+                if (lv.size() <= WMC_FACTOR_ABOVE || taut) {
+                    // short clauses (and tautologies, which weigh 1) keep their literals
+                    std::vector<int32_t> raw(lits + clause_ptr[c], lits + clause_ptr[c + 1]);
+                    if (taut && lv.size() > WMC_FACTOR_ABOVE) raw.clear(), raw.push_back(lv[0]), raw.push_back(-lv[0]);
+                    cls.push_back(std::move(raw));
+                    continue;
+                }
+                const int32_t k = (int32_t)lv.size();
+                int32_t prev = 0;
+                for (int32_t i = 1; i <= k - 2; ++i) {
+                    const int32_t a = n_vars + (int32_t)aux_prefix.size() + 1;
+                    aux_prefix.emplace_back();
+                    for (int32_t t = 0; t <= i; ++t) aux_prefix.back().push_back(lv[(size_t)t] > 0 ? lv[(size_t)t] : -lv[(size_t)t]);
+                    const int32_t x = i == 1 ? lv[0] : prev, y = lv[(size_t)i];
+                    cls.push_back({-a, x, y});
+                    cls.push_back({a, -x});
+                    cls.push_back({a, -y});
+                    prev = a;
+                }
+                cls.push_back({prev, lv[(size_t)k - 1]});
+            }
+        }
+        const int32_t n_aux = (int32_t)aux_prefix.size();
+        if ((int64_t)n_vars + n_aux > (int64_t)INT32_MAX / 2)
+            WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_build_network: too many variables after clause factoring");
+        wmc_network *net = new wmc_network();
+        net->n = n_vars + n_aux;
+        net->n_user = n_vars;
+        net->aux_prefix = std::move(aux_prefix);
+        net->w.assign(weights, weights + 2 * (size_t)n_vars);
+        net->w.resize(2 * (size_t)net->n, 1.0);
+        net->degree.assign((size_t)net->n, 0);
+        net->clauses.resize(cls.size());
+        std::vector<int8_t> sign((size_t)net->n + 1, 0);  // bit0: positive seen, bit1: negative seen
+        for (size_t c = 0; c < cls.size(); ++c) {
+            WClause &cl = net->clauses[c];
+            for (int32_t l : cls[c]) {
                 int32_t v = l > 0 ? l : -l;
                 if (!sign[v]) cl.vars.push_back(v);
                 sign[v] |= (l > 0) ? 1 : 2;
             }
             std::sort(cl.vars.begin(), cl.vars.end());
-            if (cl.vars.size() > WMC_MAX_CLAUSE) {
-                for (int32_t v : cl.vars) sign[v] = 0;
-                delete net;
-                WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_build_network: clause %lld has %zu distinct variables (max %d)",
-                         (long long)c, cl.vars.size(), WMC_MAX_CLAUSE);
-            }
             for (size_t i = 0; i < cl.vars.size(); ++i) {
                 int32_t v = cl.vars[i];
                 if (sign[v] == 3) cl.taut = true;
@@ -110,7 +154,7 @@ extern "C" wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const
 
 extern "C" wmc_status wmc_network_info(const wmc_network *net, int64_t *n_tensors, int64_t *n_indices) {
     if (!net) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_network_info: net is NULL");
-    if (n_tensors) *n_tensors = (int64_t)net->n + (int64_t)net->clauses.size();
+    if (n_tensors) *n_tensors = (int64_t)net->n + (int64_t)net->clauses.size();  // auxiliary tensors included
     if (n_indices) *n_indices = net->n_indices;
     return WMC_OK;
 }
@@ -1093,7 +1137,8 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     // ---- statistics
     wmc_plan_info &I = P.info;
     std::memset(&I, 0, sizeof I);
-    I.n_vars = n;
+    I.n_vars = net.n_user;
+    I.n_aux_vars = n - net.n_user;
     I.precision = P.precision;
     I.n_clauses = (int64_t)net.clauses.size();
     I.n_tensors = (int64_t)NT;
@@ -1135,30 +1180,47 @@ extern "C" wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *o
     try {
         wmc_plan_t *P = new wmc_plan_t();
         P->n = net->n;
+        P->n_user = net->n_user;
         P->m = (int64_t)net->clauses.size();
         P->precision = opts->precision;
         P->elem = opts->precision == WMC_FP64 ? 8 : 4;
         P->w = net->w;
         wmc_status st = WMC_OK;
         if (opts->kind == WMC_TREE_EXPLICIT) {
+            if (net->n != net->n_user) {
+                delete P;
+                WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_plan: a supplied tree cannot cover factored long clauses");
+            }
             st = explicit_tree(*net, opts->parent, opts->n_tree_nodes, P->T, &P->root);
         } else if (opts->kind == WMC_TREE_ORDER || opts->kind == WMC_TREE_MINFILL) {
             std::vector<int32_t> order;
             if (opts->kind == WMC_TREE_ORDER) {
-                if (!opts->order || opts->order_len != net->n) {
+                const int32_t nu = net->n_user;
+                if (!opts->order || opts->order_len != nu) {
                     delete P;
-                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: order must list all %d variables", net->n);
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: order must list all %d variables", nu);
                 }
-                std::vector<uint8_t> seen((size_t)net->n + 1, 0);
-                for (int32_t i = 0; i < net->n; ++i) {
+                std::vector<int32_t> pos((size_t)nu + 1, -1);
+                for (int32_t i = 0; i < nu; ++i) {
                     int32_t v = opts->order[i];
-                    if (v < 1 || v > net->n || seen[(size_t)v]) {
+                    if (v < 1 || v > nu || pos[(size_t)v] >= 0) {
                         delete P;
                         WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: order is not a permutation (entry %d = %d)", i, v);
                     }
-                    seen[(size_t)v] = 1;
+                    pos[(size_t)v] = i;
                 }
-                order.assign(opts->order, opts->order + net->n);
+                // an auxiliary variable of a factored clause is eliminated
+                // right after the last of the caller's variables it depends on
+                std::vector<std::vector<int32_t>> after((size_t)nu);
+                for (size_t a = 0; a < net->aux_prefix.size(); ++a) {
+                    int32_t last = 0;
+                    for (int32_t v : net->aux_prefix[a]) last = std::max(last, pos[(size_t)v]);
+                    after[(size_t)last].push_back(nu + 1 + (int32_t)a);
+                }
+                for (int32_t i = 0; i < nu; ++i) {
+                    order.push_back(opts->order[i]);
+                    for (int32_t a : after[(size_t)i]) order.push_back(a);
+                }
             } else {
                 order = minfill_order(*net, opts->seed);
             }

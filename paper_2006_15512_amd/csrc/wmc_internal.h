@@ -19,11 +19,15 @@ struct WClause {
 };
 
 struct wmc_network {
-    int32_t n = 0;
+    int32_t n = 0;                // variables, auxiliary ones included
+    int32_t n_user = 0;           // variables of the caller's formula: 1..n_user
     std::vector<WClause> clauses;
-    std::vector<double> w;        // 2n: {W(x,0), W(x,1)}
+    std::vector<double> w;        // 2n: {W(x,0), W(x,1)}; (1, 1) for auxiliary variables
     std::vector<int32_t> degree;  // clauses containing x (index x-1)
     int64_t n_indices = 0;
+    // auxiliary variable n_user+1+i stands for the OR of the literals over
+    // aux_prefix[i] (caller variables), the leading part of a long clause
+    std::vector<std::vector<int32_t>> aux_prefix;
 };
 
 // A tensor of the contraction tree (leaf or internal node output).
@@ -54,7 +58,8 @@ struct Launch {
 static_assert(sizeof(Launch) == 24, "Launch layout");
 
 struct wmc_plan_t {
-    int32_t n = 0;
+    int32_t n = 0;                    // variables, auxiliary ones included
+    int32_t n_user = 0;               // weights a caller passes: 2 * n_user
     int64_t m = 0;
     int32_t precision = WMC_FP64;
     int32_t elem = 8;

@@ -21,7 +21,9 @@
 namespace {
 
 struct SStruct {
-    int32_t n = 0;
+    int32_t n = 0;                // variables, auxiliary ones included
+    int32_t n_user = 0;           // a request brings 2 * n_user weights
+    std::vector<double> w_aux;    // (1, 1) per auxiliary variable
     std::vector<LeafDesc> leaves;
     std::vector<NodeDesc> nodes;
     std::vector<GemmDesc> gemms;
@@ -203,6 +205,8 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
     try {
         SStruct s;
         s.n = plan->n;
+        s.n_user = plan->n_user;
+        s.w_aux.assign(plan->w.begin() + 2 * (size_t)plan->n_user, plan->w.end());
         s.leaves = plan->leaves;
         s.nodes = plan->nodes;
         s.gemms = plan->gemms;
@@ -251,18 +255,19 @@ static wmc_status serve_submit_at(wmc_server *v, int32_t structure, const double
     r.id = request_id;
     r.s = structure;
     r.t_arrive = t_arrive;
-    if (s.n > 0) {
+    if (s.n_user > 0) {
         if (!weights) {
             wmc_set_error("wmc_serve_submit: weights are NULL");
             return WMC_ERR_INVALID_ARGUMENT;
         }
-        r.w.assign(weights, weights + 2 * (size_t)s.n);
+        r.w.assign(weights, weights + 2 * (size_t)s.n_user);
         for (double x : r.w)
             if (!std::isfinite(x)) {
                 wmc_set_error("wmc_serve_submit: non-finite weight");
                 return WMC_ERR_INVALID_ARGUMENT;
             }
     }
+    r.w.insert(r.w.end(), s.w_aux.begin(), s.w_aux.end());
     v->queue.push_back(std::move(r));
     return WMC_OK;
 }

@@ -178,12 +178,19 @@ def _replay(leaves, nodes, launches, gemms, arena_elems, nt, w, store, eta, root
     return vals
 
 
+def full_weights(plan, weights) -> np.ndarray:
+    """The device weight array: the caller's 2*n weights, then (1, 1) for
+    each auxiliary variable of a factored long clause."""
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    return np.concatenate([w, np.ones(2 * plan.stats()["n_aux_vars"])])
+
+
 def emulate(plan, weights, store=np.float64, slices=None):
     """Contract ``plan`` on the CPU exactly as the kernels would.  Returns the
     exact rational sum over the requested slices (default: all) of the slice
     values as they would be produced, plus the list of per-slice values."""
     leaves, nodes, launches, gemms, info = parse(plan)
-    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    w = full_weights(plan, weights)
     root = info["root"]
     if root < 0:
         return Fraction(1), [Fraction(1)]
@@ -227,7 +234,13 @@ def emulate_batch(batch, weights, store=np.float64):
             for t in tasks[tf + int(groups[k, 1 + nk]): tf + int(groups[k, 2 + nk])]:
                 out.append(_stream_task_as_node(t, nk))
         return out
-    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    wu = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    parts, u = [], 0
+    for p in batch.plans:
+        k = 2 * p.stats()["n_vars"]
+        parts.append(full_weights(p, wu[u:u + k]))
+        u += k
+    w = np.concatenate(parts) if parts else wu
     return _replay(leaves, nodes, launches, gemms, info["arena_elems"], info["meta_total"], w, store, 0,
                    list(roots), list(root_offs), tasks_of)
 

@@ -128,3 +128,21 @@ def test_batch512_all_instances_vs_stored_oracle(precision, tol):
         else:
             assert rel(frac(v), ref) <= tol, q
     assert zeros == sum(1 for r in rows if float.fromhex(r["mantissa_hex"]) == 0.0)
+
+
+def test_batch_long_clauses_with_new_weights():
+    """Instances with factored long clauses in one batch; caller weights
+    (2n per instance) are expanded with the auxiliary variables' (1, 1)."""
+    fs = [wl.random_long(s) for s in range(10)] + [wl.batch_instance(i) for i in range(6)]
+    plans = [W.Plan(W.Network.from_formula(f), seed=i) for i, f in enumerate(fs)]
+    b = W.Batch(plans)
+    rng = np.random.default_rng(11)
+    news = []
+    for f in fs:
+        w = rng.uniform(0.1, 0.9, size=f.n)
+        news.append(np.stack([1 - w, w], axis=1))
+    for flags in (0, W.BATCH_GRAPH):
+        vals = b.contract(np.concatenate([x.reshape(-1) for x in news]), flags=flags)
+        for q, (f, Wt, v) in enumerate(zip(fs, news, vals)):
+            m, e = oracle.bucket(f.with_weights(Wt))
+            assert rel(frac(v), Fraction(m) * Fraction(2) ** e) <= 1e-12, q

@@ -303,3 +303,43 @@ def test_banded_medium_stream_shapes(seed):
         say(f"banded120 seed={seed} {kw}")
         v, _ = run(f, **kw)
         assert rel(value_fraction(v), ref) <= 1e-12
+
+
+# ------------------------------------------------------------------ long clauses
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_long_clauses_vs_brute(precision, tol):
+    """Clauses of 9-11 literals factored into chains over auxiliary
+    variables: results (network weights and new weights) against brute force."""
+    rng = np.random.default_rng(7)
+    for s in range(12):
+        f = wl.random_long(s)
+        say(f"long seed={s} {precision}")
+        net = W.Network.from_formula(f)
+        for kw in (dict(seed=s), dict(kind="order", order=oracle.minfill_order(f), block=3)):
+            p = W.Plan(net, precision=precision, **kw)
+            assert p.stats()["n_aux_vars"] > 0
+            v = W.wmc_contract(p)
+            assert rel(value_fraction(v), Fraction(oracle.brute(f))) <= tol
+            w = rng.uniform(0.1, 0.9, size=f.n)
+            Wt = np.stack([1 - w, w], axis=1)
+            v = W.wmc_contract(p, Wt)
+            assert rel(value_fraction(v), Fraction(oracle.brute(f.with_weights(Wt)))) <= tol
+
+
+def test_one_clause_of_200_literals_closed_form():
+    """W of a single 200-literal clause: prod (W0+W1) - prod W(x, falsifying)."""
+    rng = np.random.default_rng(3)
+    k = 200
+    w = rng.uniform(0.1, 0.9, size=k)
+    Wt = np.stack([1 - w, w], axis=1)
+    signs = rng.choice([-1, 1], size=k)
+    f = Formula(k, [[int(signs[i] * (i + 1)) for i in range(k)]], Wt)
+    tot, fals = Fraction(1), Fraction(1)
+    for i in range(k):
+        tot *= Fraction(Wt[i, 0]) + Fraction(Wt[i, 1])
+        fals *= Fraction(Wt[i, 0] if signs[i] > 0 else Wt[i, 1])
+    ref = tot - fals
+    for precision, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        v, p = run(f, seed=0, precision=precision)
+        assert p.stats()["n_aux_vars"] == k - 2
+        assert rel(value_fraction(v), ref) <= tol

@@ -144,3 +144,23 @@ def test_serve_trace_replay(structures):
         f = structures[int(st_[r.request_id])].with_weights(w[r.request_id])
         m, e = oracle.bucket(f)
         assert rel(frac(r.value), Fraction(m) * Fraction(2) ** e) <= 1e-12
+
+
+def test_serve_long_clause_structures():
+    """Structures with factored long clauses: each request's 2n weights are
+    expanded with the auxiliary variables' (1, 1)."""
+    fs = [wl.random_long(s) for s in range(4)]
+    srv = W.Server(precision="fp64", max_slots=8, buffer_bytes=1 << 27)
+    ids = [srv.register(W.Plan(W.Network.from_formula(f), seed=0)) for f in fs]
+    rng = np.random.default_rng(4)
+    reqs = []
+    for q in range(16):
+        s = q % len(fs)
+        w = rng.uniform(0.1, 0.9, size=fs[s].n)
+        Wt = np.stack([1 - w, w], axis=1)
+        reqs.append((s, Wt))
+        srv.submit(ids[s], Wt, q)
+    got = {r.request_id: r for r in srv.drain()}
+    for q, (s, Wt) in enumerate(reqs):
+        ref = Fraction(oracle.brute(fs[s].with_weights(Wt)))
+        assert rel(frac(got[q].value), ref) <= 1e-12, q

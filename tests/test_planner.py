@@ -63,7 +63,6 @@ def test_network_info_counts_distinct_incidences():
     ([[0, 1]], 3, None, 1),               # zero literal
     ([[1]], 1, [[np.nan, 1.0]], 1),       # NaN weight
     ([[1]], 1, [[np.inf, 1.0]], 1),       # Inf weight
-    ([list(range(1, 27))], 26, None, 6),  # clause longer than WMC_MAX_CLAUSE
 ])
 def test_build_network_errors(clauses, n, weights, status):
     w = np.ones((n, 2)) if weights is None else np.array(weights)
@@ -311,3 +310,84 @@ def test_batch_rejects_sliced_and_mixed():
     with pytest.raises(W.WmcError) as e:
         W.Batch([W.Plan(net, seed=0), W.Plan(net, seed=0, precision="fp32")])
     assert e.value.status == 1
+
+
+# ------------------------------------------------------------------ long clauses
+def _long_clause_formula(k, extra, seed):
+    rng = np.random.default_rng(seed)
+    n = k + extra
+    sign = rng.choice([-1, 1], size=k)
+    clause = [int(sign[i] * (i + 1)) for i in range(k)]
+    w = rng.uniform(0.1, 0.9, size=n)
+    weights = np.stack([1 - w, w], axis=1) * rng.uniform(0.5, 2.0, size=(n, 1))
+    return Formula(n, [clause], weights), clause
+
+
+@pytest.mark.parametrize("k", [9, 12, 26, 40, 64])
+def test_long_clause_closed_form(k):
+    """One clause l_1 v ... v l_k: W = prod_x (W0+W1) - prod_{x in C} W(x, falsifying)
+    * prod_{x not in C} (W0+W1).  Clauses longer than WMC_FACTOR_ABOVE are
+    factored into k-2 auxiliary variables; the replayed descriptors must give
+    the closed form."""
+    f, clause = _long_clause_formula(k, 3, seed=k)
+    tot = Fraction(1)
+    for x in range(f.n):
+        tot *= Fraction(f.weights[x, 0]) + Fraction(f.weights[x, 1])
+    fals = Fraction(1)
+    for l in clause:
+        x = abs(l) - 1
+        fals *= Fraction(f.weights[x, 0] if l > 0 else f.weights[x, 1])
+    for x in range(k, f.n):
+        fals *= Fraction(f.weights[x, 0]) + Fraction(f.weights[x, 1])
+    ref = tot - fals
+    p = W.Plan(W.Network.from_formula(f), seed=0)
+    assert p.stats()["n_aux_vars"] == k - 2
+    assert p.stats()["n_vars"] == f.n
+    got, _ = emulate(p, f.weights)
+    assert rel_err(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_long_clauses_vs_brute(seed):
+    """Random formulas over 13 variables with two long clauses (9-11 literals,
+    one with a repeated literal) among 3-clauses, on min-fill trees and the
+    oracle's elimination order (auxiliary variables placed by the planner),
+    against brute force."""
+    rng = np.random.default_rng(100 + seed)
+    n = 13
+    clauses = []
+    for _ in range(2):
+        k = int(rng.integers(9, 12))
+        vs = rng.choice(n, size=k, replace=False) + 1
+        clauses.append([int(v) * int(s) for v, s in zip(vs, rng.choice([-1, 1], size=k))])
+    clauses[0].append(clauses[0][0])
+    for _ in range(16):
+        vs = rng.choice(n, size=3, replace=False) + 1
+        clauses.append([int(v) * int(s) for v, s in zip(vs, rng.choice([-1, 1], size=3))])
+    w = rng.uniform(0.1, 0.9, size=n)
+    f = Formula(n, clauses, np.stack([1 - w, w], axis=1))
+    ref = oracle.brute(f)
+    order = [int(x) for x in oracle.minfill_order(f)]
+    for kw in (dict(seed=seed), dict(kind="order", order=order), dict(kind="order", order=order, block=3)):
+        p = W.Plan(W.Network.from_formula(f), **kw)
+        assert p.stats()["n_aux_vars"] > 0
+        got, _ = emulate(p, f.weights)
+        assert rel_err(got, Fraction(ref)) <= 1e-11, kw
+
+
+def test_long_tautology_is_dropped():
+    """x v ... v not-x with more than WMC_FACTOR_ABOVE literals weighs 1."""
+    f = Formula(10, [list(range(1, 11)) + [-3]], np.full((10, 2), 0.5))
+    p = W.Plan(W.Network.from_formula(f), seed=0)
+    assert p.stats()["n_aux_vars"] == 0
+    got, _ = emulate(p, f.weights)
+    assert got == 1
+
+
+def test_long_clause_rejects_supplied_tree():
+    f, _ = _long_clause_formula(10, 0, seed=1)
+    net = W.Network.from_formula(f)
+    parent = [-1] * (2 * (f.n + 1) - 1)
+    with pytest.raises(W.WmcError) as e:
+        W.Plan(net, kind="explicit", parent=parent)
+    assert e.value.status == 6

@@ -287,3 +287,21 @@ def random_mixed(seed: int, n_max: int = 14, m_max: int = 30, k_max: int = 5,
     else:
         w = rng.uniform(0.05, 1.0, size=(n, 2))
     return Formula(n, clauses, w, f"mixed-{seed}")
+
+
+def random_long(seed: int, n: int = 13, n_long: int = 2, k_lo: int = 9, k_hi: int = 12,
+                n_short: int = 16) -> Formula:
+    """Formulas with long clauses (k_lo..k_hi-1 distinct literals, the first
+    with a repeated literal) among random 3-clauses, w ~ U(0.1, 0.9).  Long
+    clauses are the ones the network builder factors into chains."""
+    rng = np.random.default_rng(20_000 + seed)
+    clauses: List[List[int]] = []
+    for _ in range(n_long):
+        k = int(rng.integers(k_lo, k_hi))
+        clauses.append(_signed(rng, rng.choice(n, size=k, replace=False) + 1))
+    if clauses:
+        clauses[0].append(clauses[0][0])
+    for _ in range(n_short):
+        clauses.append(_signed(rng, rng.choice(n, size=3, replace=False) + 1))
+    w = rng.uniform(0.1, 0.9, size=n)
+    return Formula(n, clauses, np.stack([1 - w, w], axis=1), f"long-{seed}")
