@@ -185,6 +185,28 @@ wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t dst_bytes,
 wmc_status wmc_contract(const wmc_plan_t *plan, const double *weights, void *workspace,
                         uint64_t workspace_bytes, void *stream, wmc_value *out);
 
+/* Checkpoint of the slice loop (Algorithm 3): the running Neumaier sum
+ * (s + c) * 2^e of the slices already run, the next slice to run and the
+ * plan's slice count.  Zero-initialise to start; the struct is plain data and
+ * can be saved to a file and restored in another process. */
+typedef struct {
+    double s, c;
+    int64_t e;
+    int64_t next_slice;
+    int64_t n_slices;
+    int64_t reserved;
+} wmc_slice_state;
+
+/* Run the next `count` slices after state->next_slice (fewer at the end),
+ * continuing the running sum in *state, and update *state; *out receives the
+ * sum so far (W itself once state->next_slice == n_slices).  Splitting the
+ * slice loop across any number of calls gives the bits of one wmc_contract.
+ * Errors: INVALID_ARGUMENT (state of another plan, non-finite weights),
+ * OUT_OF_MEMORY (workspace), DEVICE. */
+wmc_status wmc_contract_resume(const wmc_plan_t *plan, const double *weights, void *workspace,
+                               uint64_t workspace_bytes, void *stream, int64_t count,
+                               wmc_slice_state *state, wmc_value *out);
+
 /* As wmc_contract, restricted to the slices eta in [slice_begin, slice_end)
  * (the slicing theorem: their sum is a partial sum of W).  If per_slice is
  * not NULL it receives one value per slice in that range. */

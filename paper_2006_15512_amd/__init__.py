@@ -55,6 +55,11 @@ class wmc_plan_options(ctypes.Structure):
                 ("rank_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
+class wmc_slice_state(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_double), ("c", ctypes.c_double), ("e", ctypes.c_int64),
+                ("next_slice", ctypes.c_int64), ("n_slices", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+
+
 class wmc_plan_info(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_clauses", ctypes.c_int64),
                 ("n_tensors", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("max_rank", ctypes.c_int32),
@@ -93,6 +98,7 @@ def lib():
             "wmc_plan_image": [P, P, u64, P, P],
             "wmc_contract": [P, P, P, u64, P, ctypes.POINTER(wmc_value)],
             "wmc_contract_slices": [P, P, P, u64, P, i64, i64, ctypes.POINTER(wmc_value), P],
+            "wmc_contract_resume": [P, P, P, u64, P, i64, ctypes.POINTER(wmc_slice_state), ctypes.POINTER(wmc_value)],
             "wmc_plan_launches": [P, P, P, P, i64, P],
             "wmc_batch_create": [P, i64, P],
             "wmc_batch_info": [P, P, P, P],
@@ -326,6 +332,55 @@ def wmc_contract_slices(plan: Plan, begin: int, end: int, weights=None, ws=None,
 
 
 contract = wmc_contract
+
+
+def wmc_contract_resume(plan: Plan, state: wmc_slice_state, count: int, weights=None, ws=None, stream=None) -> Value:
+    """Run the next ``count`` slices after ``state.next_slice``, continuing
+    the running sum in ``state`` (updated in place); returns the sum so far."""
+    if ws is None:
+        ws = workspace(plan)
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    out = wmc_value()
+    _check(lib().wmc_contract_resume(plan._h, _p(w), ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                     _stream_ptr(stream), int(count), ctypes.byref(state), ctypes.byref(out)))
+    return Value.of(out)
+
+
+def contract_checkpointed(plan: Plan, path: str, chunk: int = 1, weights=None, ws=None, stream=None,
+                          stop_after: Optional[int] = None) -> Optional[Value]:
+    """The slice loop in chunks of ``chunk`` slices with its running sum saved
+    to ``path`` (JSON, written atomically) after every chunk; an existing file
+    resumes the loop where it stopped.  ``stop_after`` ends the call after
+    that many chunks (returns None if slices remain).  The file records the
+    plan's slice count and sliced variables and is refused for another plan."""
+    import json
+    st = plan.stats()
+    ident = {"n_slices": int(st["n_slices"]), "sliced_vars": [int(x) for x in st["sliced_vars"]],
+             "n_vars": int(st["n_vars"]), "n_clauses": int(st["n_clauses"])}
+    state = wmc_slice_state()
+    if os.path.exists(path):
+        with open(path) as fh:
+            saved = json.load(fh)
+        if saved["plan"] != ident:
+            raise ValueError(f"{path} holds a checkpoint of another plan")
+        state.s, state.c = float.fromhex(saved["s"]), float.fromhex(saved["c"])
+        state.e, state.next_slice, state.n_slices = int(saved["e"]), int(saved["next_slice"]), int(saved["n_slices"])
+    done = 0
+    v = None
+    while True:
+        v = wmc_contract_resume(plan, state, chunk, weights, ws, stream)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump({"plan": ident, "s": state.s.hex(), "c": state.c.hex(), "e": int(state.e),
+                       "next_slice": int(state.next_slice), "n_slices": int(state.n_slices)}, fh)
+        os.replace(tmp, path)
+        done += 1
+        if state.next_slice >= state.n_slices:
+            return v
+        if stop_after is not None and done >= stop_after:
+            return None
 
 
 def plan_launches(plan: Plan):

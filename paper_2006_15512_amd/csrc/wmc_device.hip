@@ -32,7 +32,7 @@ static hipError_t upload_weights(const wmc_plan_t &P, const double *weights, cha
 
 template <typename T>
 static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long long b, long long e,
-                             wmc_value *per_slice, LaunchTimer *tm = nullptr) {
+                             wmc_value *per_slice, LaunchTimer *tm = nullptr, bool keep_sum = false) {
     wmc_meta *meta = (wmc_meta *)(ws + P.off_meta);
     wmc_acc *acc = (wmc_acc *)(ws + P.off_acc);
     const double *w = (const double *)(ws + P.off_w);
@@ -47,7 +47,7 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
             tm->mark();
         }
         hipLaunchKernelGGL(k_begin, dim3((nt + WMC_BLOCK - 1) / WMC_BLOCK), dim3(WMC_BLOCK), 0, st, meta, nt, acc,
-                           eta == b ? 1 : 0);
+                           eta == b && !keep_sum ? 1 : 0);
         if (tm) tm->mark();
         if (!P.leaves.empty())
             hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(P.leaf_work)), dim3(WMC_BLOCK), 0, st, L,
@@ -142,6 +142,68 @@ extern "C" wmc_status wmc_contract_slices(const wmc_plan_t *plan, const double *
         *out = make_value(0.0, 0);
     } else {
         *out = make_value(h.s + h.c, h.e);
+    }
+    return WMC_OK;
+}
+
+// Continue the running slice sum held in *state over the next `count`
+// slices (Algorithm 3's loop over eta, split across calls).  The Neumaier
+// pair and its exponent are restored into the device accumulator before the
+// first slice and read back after the last, so a run split at any slice
+// boundary gives the bits of one uninterrupted run.
+extern "C" wmc_status wmc_contract_resume(const wmc_plan_t *plan, const double *weights, void *workspace,
+                                          uint64_t workspace_bytes, void *stream, int64_t count,
+                                          wmc_slice_state *state, wmc_value *out) {
+    if (!plan || !state || !out) {
+        wmc_set_error("wmc_contract_resume: NULL argument");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    const wmc_plan_t &P = *plan;
+    const int64_t ns = (int64_t)1 << P.sliced.size();
+    if (state->next_slice == 0 && state->n_slices == 0) state->n_slices = ns;  // fresh state
+    if (state->n_slices != ns || state->next_slice < 0 || state->next_slice > ns || count < 0 ||
+        !std::isfinite(state->s) || !std::isfinite(state->c)) {
+        wmc_set_error("wmc_contract_resume: state does not belong to this plan (next %lld of %lld slices, plan has %lld)",
+                      (long long)state->next_slice, (long long)state->n_slices, (long long)ns);
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (weights)
+        for (int64_t i = 0; i < 2 * (int64_t)P.n_user; ++i)
+            if (!std::isfinite(weights[i])) {
+                wmc_set_error("wmc_contract_resume: weight %lld is not finite", (long long)i);
+                return WMC_ERR_INVALID_ARGUMENT;
+            }
+    if (!workspace || ((uintptr_t)workspace & 255u) || workspace_bytes < P.workspace_bytes) {
+        wmc_set_error("wmc_contract_resume: workspace NULL, misaligned or below %llu bytes",
+                      (unsigned long long)P.workspace_bytes);
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    const int64_t b = state->next_slice, e = std::min<int64_t>(ns, b + count);
+    if (P.root >= 0 && e > b) {
+        hipStream_t st = (hipStream_t)stream;
+        char *ws = (char *)workspace;
+        wmc_acc h;
+        std::memset(&h, 0, sizeof h);
+        h.s = state->s;
+        h.c = state->c;
+        h.e = state->e;
+        HIP_TRY(upload_weights(P, weights, ws, st));
+        HIP_TRY(hipMemcpyAsync(ws + P.off_leaf, P.desc_image.data(), P.desc_bytes, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(ws + P.off_acc, &h, sizeof h, hipMemcpyHostToDevice, st));
+        wmc_status s = P.precision == WMC_FP64 ? run_slices<double>(P, ws, st, b, e, nullptr, nullptr, true)
+                                               : run_slices<float>(P, ws, st, b, e, nullptr, nullptr, true);
+        if (s != WMC_OK) return s;
+        HIP_TRY(hipMemcpyAsync(&h, ws + P.off_acc, sizeof h, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        state->s = h.s;
+        state->c = h.c;
+        state->e = h.e;
+    }
+    state->next_slice = e;
+    if (P.root < 0) {
+        *out = make_value(1.0, 0);  // no variables and no clauses
+    } else {
+        *out = (state->s == 0.0 && state->c == 0.0) ? make_value(0.0, 0) : make_value(state->s + state->c, state->e);
     }
     return WMC_OK;
 }

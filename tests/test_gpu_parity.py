@@ -343,3 +343,44 @@ def test_one_clause_of_200_literals_closed_form():
         v, p = run(f, seed=0, precision=precision)
         assert p.stats()["n_aux_vars"] == k - 2
         assert rel(value_fraction(v), ref) <= tol
+
+
+# ------------------------------------------------------------------ checkpoint / resume
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_slice_loop_checkpoint_resume_is_bit_exact(tmp_path, precision):
+    """The slice loop stopped after some chunks, its state saved to a file,
+    and resumed with a fresh plan object gives the bits of one wmc_contract."""
+    f = wl.banded_3cnf(120, 400, 24, seed=1)
+    kw = dict(seed=1, rank_cap=16, precision=precision)
+    p = W.Plan(W.Network.from_formula(f), **kw)
+    ns = p.stats()["n_slices"]
+    assert ns >= 16
+    full = W.wmc_contract(p)
+    path = str(tmp_path / "slices.json")
+    assert W.contract_checkpointed(p, path, chunk=3, stop_after=2) is None
+    p2 = W.Plan(W.Network.from_formula(f), **kw)   # as after a restart
+    v = W.contract_checkpointed(p2, path, chunk=5)
+    assert (v.mantissa, v.exp2) == (full.mantissa, full.exp2)
+    m, e = oracle.bucket(f)
+    assert rel(value_fraction(v), Fraction(m) * Fraction(2) ** e) <= (1e-12 if precision == "fp64" else 1e-5)
+    other = W.Plan(W.Network.from_formula(f), seed=1, rank_cap=15, precision=precision)
+    with pytest.raises(ValueError):
+        W.contract_checkpointed(other, path)
+
+
+# ------------------------------------------------------------------ autotuned plan shape
+def test_autotune_plan_picks_fastest_and_caches(tmp_path):
+    """The autotuner times every candidate block size, returns the fastest
+    (whose result matches the oracle) and answers from its cache next time."""
+    from paper_2006_15512_amd.autotune import autotune_plan
+    f = wl.grid_cnf(10, 20, 0.1, seed=3)
+    order = wl.row_major_order(10, 20)
+    cache = str(tmp_path / "tune.json")
+    p, rep = autotune_plan(f, blocks=(1, 3, 5), order=order, reps=2, cache=cache)
+    assert not rep["cached"] and len(rep["results"]) == 3
+    assert rep["ms"] == min(r["ms"] for r in rep["results"] if "ms" in r)
+    m, e = oracle.bucket(f, order=order)
+    assert rel(value_fraction(W.wmc_contract(p)), Fraction(m) * Fraction(2) ** e) <= 1e-12
+    p2, rep2 = autotune_plan(f, blocks=(1, 3, 5), order=order, reps=2, cache=cache)
+    assert rep2["cached"] and rep2["best_candidate"] == rep["best_candidate"]
+    assert p2.stats()["n_launches"] == p.stats()["n_launches"]
