@@ -284,7 +284,7 @@ typedef struct {
     int32_t max_queue;          /* waiting requests; WMC_ERR_BUSY beyond */
     int32_t reserved0;
     uint64_t hbm_budget_bytes;  /* request regions; 0 = all of the buffer left */
-    uint64_t step_bytes;        /* staging per step; 0 = 16 MiB */
+    uint64_t step_bytes;        /* staging per step (two are kept); 0 = min(64 MiB, bytes / 8) */
 } wmc_serve_options;
 
 typedef struct {

@@ -62,6 +62,11 @@ struct wmc_batch {
     std::vector<int> task_first;         // per launch
     std::vector<std::array<int, 5>> task_nk;  // per launch, relative to task_first
     uint64_t off_tasks = 0;
+    // lookup tables replacing the kernels' searches (int32): per launch, the
+    // offset of its wave -> node table and of its workgroup -> task table
+    std::vector<int> tables;
+    std::vector<int64_t> wave_off, btask_off;
+    uint64_t off_tables = 0;
     std::vector<int32_t> roots;
     std::vector<long long> root_off;
     int64_t meta_total = 0;
@@ -147,6 +152,9 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         // node launches, merged by index; big streaming nodes become tasks
         B->task_first.push_back(0);
         B->task_nk.push_back({0, 0, 0, 0, 0});
+        B->wave_off.push_back(0);
+        B->btask_off.push_back(0);
+        std::vector<int> tab;
         for (size_t k = 1; k < kmax; ++k) {
             Launch merged{LAUNCH_NODES, (int32_t)B->nodes.size(), 0, 0, 0};
             std::vector<Launch> gemm_launches;
@@ -190,11 +198,19 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
                 B->task_first.push_back((int)B->tasks.size());
                 B->task_nk.push_back({nkf[0], nkf[1], nkf[2], nkf[3], nkf[4]});
                 B->tasks.insert(B->tasks.end(), tasks.begin(), tasks.end());
+                B->wave_off.push_back((int64_t)B->tables.size());
+                wave_node_table(step_nodes, work, tab);
+                B->tables.insert(B->tables.end(), tab.begin(), tab.end());
+                B->btask_off.push_back((int64_t)B->tables.size());
+                block_task_table(tasks, nkf, tab);
+                B->tables.insert(B->tables.end(), tab.begin(), tab.end());
             }
             for (const Launch &g : gemm_launches) {
                 B->launches.push_back(g);
                 B->task_first.push_back((int)B->tasks.size());
                 B->task_nk.push_back({0, 0, 0, 0, 0});
+                B->wave_off.push_back(0);
+                B->btask_off.push_back(0);
             }
         }
         for (int64_t i = 0; i < n; ++i) {
@@ -222,6 +238,8 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         off += bal(sizeof(int) * (uint64_t)n, 256);
         B->off_rootoff = off;
         off += bal(sizeof(long long) * (uint64_t)n, 256);
+        B->off_tables = off;
+        off += bal(sizeof(int) * std::max<size_t>(B->tables.size(), 1), 256);
         B->off_arena = off;
         B->arena_bytes = (uint64_t)arena_elems * (uint64_t)B->elem;
         B->workspace_bytes = off + bal(B->arena_bytes, 256);
@@ -237,6 +255,7 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         put(B->off_tasks, B->tasks.data(), sizeof(StreamTask) * B->tasks.size());
         put(B->off_roots, B->roots.data(), sizeof(int) * B->roots.size());
         put(B->off_rootoff, B->root_off.data(), sizeof(long long) * B->root_off.size());
+        put(B->off_tables, B->tables.data(), sizeof(int) * B->tables.size());
         *out = B;
     } catch (std::bad_alloc &) {
         wmc_set_error("wmc_batch_create: host allocation failed");
@@ -279,13 +298,14 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
             launch_gemm<T>(B.gemms[(size_t)Ln.pad], G + Ln.pad, arena, meta, st);
             continue;
         }
+        const int *tabs = (const int *)(ws + B.off_tables);
         if (Ln.count)
             hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first, Ln.count,
-                               (long long)Ln.work, arena, meta);
+                               (long long)Ln.work, arena, meta, tabs + B.wave_off[k]);
         const int tf = B.task_first[k];
         if (B.task_nk[k][4] > 0)
             launch_stream_multi<T>((const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf,
-                                   B.task_nk[k].data(), arena, meta, st);
+                                   B.task_nk[k].data(), arena, meta, st, tabs + B.btask_off[k]);
     }
     hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n + 255) / 256)), dim3(256), 0, st, arena,
                        (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n,

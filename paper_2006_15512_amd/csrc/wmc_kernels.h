@@ -158,17 +158,23 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict
 // multiple so that a wave never straddles two nodes.
 template <typename T>
 __global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict__ D, int nd, long long work,
-                                                     T *__restrict__ arena, wmc_meta *meta) {
+                                                     T *__restrict__ arena, wmc_meta *meta,
+                                                     const int *__restrict__ wave_node = nullptr) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
         // a wave's 64 items belong to one node (outputs are padded to waves):
         // search with the wave's first item so the node index, and every
         // descriptor read, is wave-uniform (scalar loads)
         const long long g0 = ((long long)__builtin_amdgcn_readfirstlane((int)(g >> 6))) << 6;
-        int lo = 0, hi = nd - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (D[mid].work_begin <= g0) lo = mid; else hi = mid - 1;
+        int lo = 0;
+        if (wave_node) {
+            lo = wave_node[g0 >> 6];  // one load instead of a dependent search
+        } else {
+            int hi = nd - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (D[mid].work_begin <= g0) lo = mid; else hi = mid - 1;
+            }
         }
         lo = __builtin_amdgcn_readfirstlane(lo);
         const NodeDesc &d = D[lo];
@@ -1057,13 +1063,19 @@ static_assert(sizeof(StreamTask) == 144, "StreamTask layout");
 
 template <typename T, int NK>
 __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restrict__ tasks, int ntasks,
-                                                      T *__restrict__ arena, wmc_meta *meta) {
+                                                      T *__restrict__ arena, wmc_meta *meta,
+                                                      const int *__restrict__ block_task = nullptr) {
     __shared__ double Bs[STREAM_MULTI_B];
     constexpr int K = 1 << NK;
-    int lo = 0, hi = ntasks - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (tasks[mid].block_begin <= (long long)blockIdx.x) lo = mid; else hi = mid - 1;
+    int lo = 0;
+    if (block_task) {
+        lo = block_task[blockIdx.x];  // one load instead of a dependent search
+    } else {
+        int hi = ntasks - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].block_begin <= (long long)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const StreamArgs &args = tasks[lo].a;
@@ -1117,22 +1129,55 @@ static inline bool stream_task(const NodeDesc &d, StreamTask *t) {
     return stream_args(d, &t->a) && d.nk <= 3;
 }
 
+// Workgroups of the task group [f, l): the group's grid size.
+static inline unsigned long long stream_multi_blocks(const StreamTask *host_tasks, int f, int l) {
+    if (f == l) return 0;
+    const StreamTask &last = host_tasks[l - 1];
+    return (unsigned long long)last.block_begin +
+           ((((1ull << last.a.rc) >> 2) + STREAM_MULTI_QUADS - 1) / STREAM_MULTI_QUADS);
+}
+
+// Lookup tables that replace the kernels' searches: the node of every wave
+// of a small-node launch, and the task (relative to its nk group) of every
+// workgroup of the streaming groups, groups concatenated in nk order.
+static inline void wave_node_table(const std::vector<NodeDesc> &nodes, int64_t work, std::vector<int> &out) {
+    out.assign((size_t)(work / WMC_WAVE), 0);
+    for (size_t q = 0; q < nodes.size(); ++q) {
+        const int64_t b = nodes[q].work_begin / WMC_WAVE;
+        const int64_t e = b + (int64_t)(((1ull << nodes[q].rc) + WMC_WAVE - 1) / WMC_WAVE);
+        for (int64_t w = b; w < e; ++w) out[(size_t)w] = (int)q;
+    }
+}
+
+static inline void block_task_table(const std::vector<StreamTask> &tasks, const std::vector<int> &nk_first,
+                                    std::vector<int> &out) {
+    out.clear();
+    for (int k = 0; k < 4; ++k) {
+        const int f = nk_first[(size_t)k], l = nk_first[(size_t)k + 1];
+        for (int t = f; t < l; ++t) {
+            const unsigned long long e = stream_multi_blocks(tasks.data(), f, t + 1);  // end of task t
+            const unsigned long long b = (unsigned long long)tasks[(size_t)t].block_begin;
+            for (unsigned long long x = b; x < e; ++x) out.push_back(t - f);
+        }
+    }
+}
+
 template <typename T>
 static void launch_stream_multi(const StreamTask *dev_tasks, const StreamTask *host_tasks, const int *nk_first,
-                                T *arena, wmc_meta *meta, hipStream_t st) {
+                                T *arena, wmc_meta *meta, hipStream_t st, const int *dev_block_task = nullptr) {
     // nk_first[k] .. nk_first[k+1] is the group of tasks with nk == k
+    unsigned long long toff = 0;  // offset of the group's entries in the block table
     for (int k = 0; k < 4; ++k) {
         const int f = nk_first[k], l = nk_first[k + 1];
         if (f == l) continue;
-        const StreamTask &last = host_tasks[l - 1];
-        const unsigned g = (unsigned)(last.block_begin +
-                                      (long long)((((1ull << last.a.rc) >> 2) + STREAM_MULTI_QUADS - 1) /
-                                                  STREAM_MULTI_QUADS));
+        const unsigned g = (unsigned)stream_multi_blocks(host_tasks, f, l);
+        const int *bt = dev_block_task ? dev_block_task + toff : nullptr;
+        toff += g;
         switch (k) {
-        case 0: hipLaunchKernelGGL((k_stream_multi<T, 0>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
-        case 1: hipLaunchKernelGGL((k_stream_multi<T, 1>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
-        case 2: hipLaunchKernelGGL((k_stream_multi<T, 2>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
-        default: hipLaunchKernelGGL((k_stream_multi<T, 3>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta); break;
+        case 0: hipLaunchKernelGGL((k_stream_multi<T, 0>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
+        case 1: hipLaunchKernelGGL((k_stream_multi<T, 1>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
+        case 2: hipLaunchKernelGGL((k_stream_multi<T, 2>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
+        default: hipLaunchKernelGGL((k_stream_multi<T, 3>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
         }
     }
 }

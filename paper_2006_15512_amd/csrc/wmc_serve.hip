@@ -149,7 +149,9 @@ extern "C" wmc_status wmc_serve_create(const wmc_serve_options *opts, void *devi
         wmc_set_error("wmc_serve_create: invalid options");
         return WMC_ERR_INVALID_ARGUMENT;
     }
-    const uint64_t step_cap = sal(opts->step_bytes ? opts->step_bytes : (16ull << 20), 256);
+    // default staging per step: 64 MiB, or an eighth of a smaller buffer
+    const uint64_t dflt = std::min<uint64_t>(64ull << 20, std::max<uint64_t>(1ull << 20, bytes / 8));
+    const uint64_t step_cap = sal(opts->step_bytes ? opts->step_bytes : dflt, 256);
     const uint64_t res_bytes = sal(sizeof(ServeRes) * (uint64_t)opts->max_slots, 256);
     if (bytes < 2 * step_cap + res_bytes + 4096) {
         wmc_set_error("wmc_serve_create: device buffer too small (%llu bytes)", (unsigned long long)bytes);
@@ -222,10 +224,16 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
                       sizeof(LeafDesc) * s.leaves.size() + sizeof(FinishEntry);
         for (size_t k = 1; k < s.launches.size(); ++k) {
             const Launch &L = s.launches[k];
-            uint64_t b = L.type == LAUNCH_GEMM ? sizeof(GemmDesc) : sizeof(NodeDesc) * (uint64_t)L.count;
+            // descriptors, plus the lookup tables of the merged kernels (one
+            // int per wave of small nodes and per streaming workgroup)
+            uint64_t b = L.type == LAUNCH_GEMM
+                             ? sizeof(GemmDesc)
+                             : sizeof(NodeDesc) * (uint64_t)L.count +
+                                   sizeof(int) * ((uint64_t)L.work / WMC_WAVE + (uint64_t)L.work / 4096 +
+                                                  (uint64_t)L.count + 2);
             mx = std::max(mx, b + sizeof(FinishEntry));
         }
-        s.max_step_bytes = mx + 6 * 256;
+        s.max_step_bytes = mx + 8 * 256;
         if (s.footprint > v->regions_bytes || s.max_step_bytes > v->step_cap) {
             wmc_set_error("wmc_serve_register: structure needs %llu bytes of region and %llu of staging",
                           (unsigned long long)s.footprint, (unsigned long long)s.max_step_bytes);
@@ -431,7 +439,10 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     std::vector<StreamTask> tasks;
     std::vector<int> nkf;
     split_stream(nodes, tasks, nkf, node_work, WMC_STREAM_MIN_RANK);
-    // staging image: [weights][clears][leaves][nodes][gemms][finish][tasks]
+    std::vector<int> wtab, btab;
+    wave_node_table(nodes, node_work, wtab);
+    block_task_table(tasks, nkf, btab);
+    // staging image: [weights][clears][leaves][nodes][gemms][finish][tasks][tables]
     uint64_t o = 0;
     auto place = [&](size_t bytes) {
         uint64_t at = o;
@@ -445,6 +456,8 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     const uint64_t o_g = place(sizeof(GemmDesc) * gemms.size());
     const uint64_t o_f = place(sizeof(FinishEntry) * fin.size());
     const uint64_t o_t = place(sizeof(StreamTask) * tasks.size());
+    const uint64_t o_wt = place(sizeof(int) * wtab.size());
+    const uint64_t o_bt = place(sizeof(int) * btab.size());
     if (o > v->step_cap) {
         wmc_set_error("wmc_serve: step staging overflow (%llu > %llu)", (unsigned long long)o,
                       (unsigned long long)v->step_cap);
@@ -461,6 +474,8 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     cp(o_g, gemms.data(), sizeof(GemmDesc) * gemms.size());
     cp(o_f, fin.data(), sizeof(FinishEntry) * fin.size());
     cp(o_t, tasks.data(), sizeof(StreamTask) * tasks.size());
+    cp(o_wt, wtab.data(), sizeof(int) * wtab.size());
+    cp(o_bt, btab.data(), sizeof(int) * btab.size());
     hipStream_t st = v->st;
     char *stp = v->dev + v->off_step + (uint64_t)h * v->step_cap;
     HIP_TRY(hipMemcpyAsync(stp, stage, o, hipMemcpyHostToDevice, st));
@@ -475,9 +490,11 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
                            (const double *)(stp + o_w), arena, meta, 0ull);
     if (!nodes.empty())
         hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(node_work)), dim3(WMC_BLOCK), 0, st,
-                           (const NodeDesc *)(stp + o_n), (int)nodes.size(), (long long)node_work, arena, meta);
+                           (const NodeDesc *)(stp + o_n), (int)nodes.size(), (long long)node_work, arena, meta,
+                           (const int *)(stp + o_wt));
     if (!tasks.empty())
-        launch_stream_multi<T>((const StreamTask *)(stp + o_t), tasks.data(), nkf.data(), arena, meta, st);
+        launch_stream_multi<T>((const StreamTask *)(stp + o_t), tasks.data(), nkf.data(), arena, meta, st,
+                               (const int *)(stp + o_bt));
     for (size_t q = 0; q < gemms.size(); ++q)
         launch_gemm<T>(gemms[q], (const GemmDesc *)(stp + o_g) + q, arena, meta, st);
     ServeRes *res = (ServeRes *)(v->dev + v->off_res);
