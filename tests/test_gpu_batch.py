@@ -146,3 +146,18 @@ def test_batch_long_clauses_with_new_weights():
         for q, (f, Wt, v) in enumerate(zip(fs, news, vals)):
             m, e = oracle.bucket(f.with_weights(Wt))
             assert rel(frac(v), Fraction(m) * Fraction(2) ** e) <= 1e-12, q
+
+
+def test_batch_with_big_nodes_vs_oracle():
+    """Instances whose merged steps hold nodes of 2^20+ outputs next to small
+    ones, against the oracle; batch equals solo bit for bit."""
+    fs = [wl.banded_3cnf(120, 400, 24, seed=s) for s in range(3)] + [wl.batch_instance(i) for i in range(5)]
+    plans = [W.Plan(W.Network.from_formula(f), seed=s) for s, f in enumerate(fs)]
+    b = W.Batch(plans)
+    for flags in (0, W.BATCH_GRAPH):
+        vals = b.contract(flags=flags)
+        for q, (f, p, v) in enumerate(zip(fs, plans, vals)):
+            m, e = oracle.bucket(f)
+            assert rel(frac(v), Fraction(m) * Fraction(2) ** e) <= 1e-12, q
+            solo = W.wmc_contract(p)
+            assert (solo.mantissa, solo.exp2) == (v.mantissa, v.exp2), q

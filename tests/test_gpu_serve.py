@@ -164,3 +164,27 @@ def test_serve_long_clause_structures():
     for q, (s, Wt) in enumerate(reqs):
         ref = Fraction(oracle.brute(fs[s].with_weights(Wt)))
         assert rel(frac(got[q].value), ref) <= 1e-12, q
+
+
+def test_serve_big_structures_vs_oracle():
+    """Serving structures 6 and 7 (storage rank 23-24) mixed with small ones,
+    against the oracle, and each equal to wmc_contract bit for bit."""
+    fs = [wl.serve_structure(s) for s in (6, 7, 0)]
+    plans = [W.Plan(W.Network.from_formula(f), seed=0) for f in fs]
+    srv = W.Server(precision="fp64", max_slots=8, buffer_bytes=1 << 31)
+    ids = [srv.register(p) for p in plans]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for q in range(6):
+        s = q % 3
+        w = rng.uniform(0.1, 0.9, size=fs[s].n)
+        Wt = np.stack([1 - w, w], axis=1)
+        reqs.append((s, Wt))
+        srv.submit(ids[s], Wt, q)
+    got = {r.request_id: r for r in srv.drain()}
+    for q, (s, Wt) in enumerate(reqs):
+        solo = W.wmc_contract(plans[s], Wt)
+        assert (solo.mantissa, solo.exp2) == (got[q].value.mantissa, got[q].value.exp2), q
+        if q < 3:
+            m, e = oracle.bucket(fs[s].with_weights(Wt))
+            assert rel(frac(got[q].value), Fraction(m) * Fraction(2) ** e) <= 1e-12, q

@@ -391,3 +391,15 @@ def test_long_clause_rejects_supplied_tree():
     with pytest.raises(W.WmcError) as e:
         W.Plan(net, kind="explicit", parent=parent)
     assert e.value.status == 6
+
+
+def test_batch_with_big_nodes_replays():
+    """Batches whose merged steps hold nodes of 2^20+ outputs (streaming
+    tasks) next to small ones: the replayed batch image equals the oracle."""
+    from plan_emulator import emulate_batch
+    fs = [wl.banded_3cnf(120, 400, 24, seed=s) for s in range(2)] + [wl.random_long(0)]
+    b = W.Batch([W.Plan(W.Network.from_formula(f), seed=s) for s, f in enumerate(fs)])
+    vals = emulate_batch(b, np.concatenate([f.weights.reshape(-1) for f in fs]))
+    for f, v in zip(fs, vals):
+        m, e = oracle.bucket(f)
+        assert rel_err(v, Fraction(m) * Fraction(2) ** e) <= 1e-12
