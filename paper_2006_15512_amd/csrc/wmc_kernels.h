@@ -590,19 +590,13 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
 }
 
 // ---------------------------------------------------------------------------
-// Streaming contraction for one big node with a small summed dimension
-// (K = 2^nk <= 8): Hadamard scaling, a single summed variable, outer
-// products.  HBM-bound.  The operands' storage orders follow C's, so the
-// address of A for output r is r with the bits A lacks (C's "holes" for A)
-// removed, times K; B's is the few bits of r that B owns, gathered, times K.
-// Both bit lists arrive by value in the kernel arguments (scalar registers).
-// Every thread produces 4 consecutive outputs (one 32-byte FP64 / 16-byte
-// FP32 store); when C's two lowest bits belong to A the 4 rows of A are one
-// contiguous run of 4K elements, loaded with 16-byte vector loads.  B is
-// staged in LDS (scaled by its power of two) when it has at most 2^12
-// entries.
+// Streaming arguments of the merged-step kernel (many big nodes of a batch
+// or serving step in one launch, K = 2^nk <= 8).  The operands' storage
+// orders follow C's, so the address of A (the larger operand) for output r
+// is r with the bits A lacks (C's "holes" for A) removed, times K; B's is the
+// bits of r that B owns, gathered along runs, times K.  Every thread produces
+// 4 consecutive outputs (one 32-byte FP64 / 16-byte FP32 store).
 // ---------------------------------------------------------------------------
-#define STREAM_B_LDS 4096
 #define STREAM_MAX_HOLES 8
 #define STREAM_MAX_BRUNS 10
 
@@ -615,8 +609,8 @@ struct StreamArgs {
     int nbrun;                      // B's bits of C as runs (src | len << 8 | dst << 16)
     unsigned brun[STREAM_MAX_BRUNS];
     int rb;                         // storage rank of B
-    int b_lds;
-    int low_contig;                 // C bits 0 and 1 both belong to A
+    int b_lds;                      // B has at most 2^12 entries (informational)
+    int low_contig;                 // C bits 0 and 1 both belong to A (informational)
 };
 
 template <typename T> struct Vec4;
@@ -653,73 +647,6 @@ __device__ __forceinline__ unsigned long long gather_bits(unsigned long long r, 
             out |= ((r >> (w & 255u)) & ((1ull << ((w >> 8) & 255u)) - 1ull)) << (w >> 16);
         }
     return out;
-}
-
-template <typename T, int NK>
-__global__ void __launch_bounds__(256) k_stream(const StreamArgs args, T *__restrict__ arena, wmc_meta *meta) {
-    __shared__ double Bs[STREAM_B_LDS];
-    constexpr int K = 1 << NK;
-    const int sA = scale_exp(meta[args.ta].maxbits);
-    const int sB = scale_exp(meta[args.tb].maxbits);
-    const double scaleB = ldexp(1.0, -sB), scaleA = ldexp(1.0, -sA);
-    const T *__restrict__ A = arena + args.a;
-    const T *__restrict__ B = arena + args.b;
-    T *__restrict__ C = arena + args.c;
-    if (args.b_lds) {
-        for (int i = threadIdx.x; i < (1 << args.rb); i += 256) Bs[i] = (double)B[i] * scaleB;
-        __syncthreads();
-    }
-    const unsigned long long quads = (1ull << args.rc) >> 2;
-    double vmax = 0.0;
-    for (unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; q < quads;
-         q += (unsigned long long)gridDim.x * blockDim.x) {
-        double av[4][K];
-        if (args.low_contig) {
-            const unsigned long long pa = drop_holes(q << 2, args) << NK;
-            const T *p = A + pa;
-            if (sizeof(T) == 8) {
-#pragma unroll
-                for (int i = 0; i < 2 * K; ++i) {
-                    double2 v = ((const double2 *)p)[i];
-                    av[(2 * i) / K][(2 * i) % K] = v.x;
-                    av[(2 * i + 1) / K][(2 * i + 1) % K] = v.y;
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    float4 v = ((const float4 *)p)[i];
-                    av[(4 * i) / K][(4 * i) % K] = v.x;
-                    av[(4 * i + 1) / K][(4 * i + 1) % K] = v.y;
-                    av[(4 * i + 2) / K][(4 * i + 2) % K] = v.z;
-                    av[(4 * i + 3) / K][(4 * i + 3) % K] = v.w;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const unsigned long long pa = drop_holes((q << 2) | (unsigned long long)e, args) << NK;
-#pragma unroll
-                for (int j = 0; j < K; ++j) av[e][j] = (double)A[pa + j];
-            }
-        }
-        double o[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const unsigned long long pb = gather_bits((q << 2) | (unsigned long long)e, args) << NK;
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const double bv = args.b_lds ? Bs[pb + j] : (double)B[pb + j] * scaleB;
-                acc = fma(av[e][j], bv, acc);
-            }
-            o[e] = acc * scaleA;
-        }
-        Vec4<T>::store(C + (q << 2), o[0], o[1], o[2], o[3]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs((double)(T)o[e]));
-    }
-    publish_max_block(meta, args.tc, vmax);
-    if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
 }
 
 // Streaming arguments for a single-node launch, if the node fits the kernel.
@@ -765,27 +692,6 @@ static inline bool stream_args(const NodeDesc &d0, StreamArgs *a) {
     a->b_lds = a->rb <= 12;
     a->low_contig = inA[0] && inA[1];
     return true;
-}
-
-template <typename T>
-static void launch_stream(const StreamArgs &sa, T *arena, wmc_meta *meta, hipStream_t st, int nk) {
-    const unsigned long long quads = (1ull << sa.rc) >> 2;
-    unsigned long long blocks = (quads + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    // every workgroup stages B in LDS: keep that below a quarter of the
-    // outputs, but keep at least four workgroups per CU when there is work
-    if (sa.b_lds && sa.rc - sa.rb >= 2) {
-        unsigned long long cap = 1ull << (sa.rc - sa.rb - 2);
-        if (cap < 1024) cap = 1024;
-        if (blocks > cap) blocks = cap;
-    }
-    if (blocks < 1) blocks = 1;
-    switch (nk) {
-    case 0: hipLaunchKernelGGL((k_stream<T, 0>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    case 1: hipLaunchKernelGGL((k_stream<T, 1>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    case 2: hipLaunchKernelGGL((k_stream<T, 2>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    default: hipLaunchKernelGGL((k_stream<T, 3>), dim3((unsigned)blocks), dim3(256), 0, st, sa, arena, meta); break;
-    }
 }
 
 // Register-tiled streaming contraction for one big node,
