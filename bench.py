@@ -330,7 +330,7 @@ def main():
 
     # per-launch timing with HIP events on the launch stream (outside the timed region)
     bytes_l, flops_l, cls_l = W.plan_launches(plan)
-    reps = 3
+    reps = max(3, args.steps)  # as many profiled solves as timed ones
     ms = np.zeros(len(bytes_l))
     for _ in range(reps):
         _, m = W.wmc_contract_profile(plan, None, ws, stream)
