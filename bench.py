@@ -185,6 +185,12 @@ def bench_batch(args, W, torch):
         "contraction_tflops": round(total_flops / (ms_step * 1e-3) / 1e12, 3),
         "zero_fraction": sum(1 for v in vals if v.mantissa == 0.0) / n_inst,
     }
+    if args.precision == "fp32":
+        # the scaled-FP32 results against the FP64 path on the same instances
+        ref = W.Batch([W.Plan(W.Network.from_formula(f), seed=i) for i, f in enumerate(fs)]).contract()
+        errs = [abs(b.mantissa * 2.0 ** (b.exp2 - a.exp2) - a.mantissa) / abs(a.mantissa)
+                for a, b in zip(ref, vals) if a.mantissa != 0.0]
+        out["fp32_max_rel_err_vs_fp64"] = float(max(errs)) if errs else 0.0
     print(json.dumps(out), flush=True)
 
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <utility>
 #include <vector>
@@ -590,110 +591,6 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
 }
 
 // ---------------------------------------------------------------------------
-// Streaming arguments of the merged-step kernel (many big nodes of a batch
-// or serving step in one launch, K = 2^nk <= 8).  The operands' storage
-// orders follow C's, so the address of A (the larger operand) for output r
-// is r with the bits A lacks (C's "holes" for A) removed, times K; B's is the
-// bits of r that B owns, gathered along runs, times K.  Every thread produces
-// 4 consecutive outputs (one 32-byte FP64 / 16-byte FP32 store).
-// ---------------------------------------------------------------------------
-#define STREAM_MAX_HOLES 8
-#define STREAM_MAX_BRUNS 10
-
-struct StreamArgs {
-    long long a, b, c;
-    int ta, tb, tc;
-    int rc;
-    int nhole;                      // C bit positions not in A, ascending
-    int hole[STREAM_MAX_HOLES];
-    int nbrun;                      // B's bits of C as runs (src | len << 8 | dst << 16)
-    unsigned brun[STREAM_MAX_BRUNS];
-    int rb;                         // storage rank of B
-    int b_lds;                      // B has at most 2^12 entries (informational)
-    int low_contig;                 // C bits 0 and 1 both belong to A (informational)
-};
-
-template <typename T> struct Vec4;
-template <> struct Vec4<double> {
-    static __device__ __forceinline__ void store(double *p, double a, double b, double c, double d) {
-        double2 *q = (double2 *)p;
-        q[0] = make_double2(a, b);
-        q[1] = make_double2(c, d);
-    }
-};
-template <> struct Vec4<float> {
-    static __device__ __forceinline__ void store(float *p, double a, double b, double c, double d) {
-        *(float4 *)p = make_float4((float)a, (float)b, (float)c, (float)d);
-    }
-};
-
-__device__ __forceinline__ unsigned long long drop_holes(unsigned long long r, const StreamArgs &s) {
-#pragma unroll
-    for (int i = STREAM_MAX_HOLES - 1; i >= 0; --i) {
-        if (i < s.nhole) {
-            const int h = s.hole[i];
-            r = ((r >> (h + 1)) << h) | (r & ((1ull << h) - 1ull));
-        }
-    }
-    return r;
-}
-
-__device__ __forceinline__ unsigned long long gather_bits(unsigned long long r, const StreamArgs &s) {
-    unsigned long long out = 0;
-#pragma unroll
-    for (int i = 0; i < STREAM_MAX_BRUNS; ++i)
-        if (i < s.nbrun) {
-            const unsigned w = s.brun[i];
-            out |= ((r >> (w & 255u)) & ((1ull << ((w >> 8) & 255u)) - 1ull)) << (w >> 16);
-        }
-    return out;
-}
-
-// Streaming arguments for a single-node launch, if the node fits the kernel.
-static inline bool stream_args(const NodeDesc &d0, StreamArgs *a) {
-    if (d0.rc < 2 || d0.nk > 3) return false;
-    // the contraction is symmetric: stream the larger operand as A
-    auto rank_of = [](const unsigned *runs, int nr, int nk) {
-        int r = nk;
-        for (int q = 0; q < nr; ++q) r += (int)((runs[q] >> 8) & 255u);
-        return r;
-    };
-    NodeDesc d = d0;
-    if (rank_of(d0.ra, d0.nra, d0.nk) < rank_of(d0.rb, d0.nrb, d0.nk)) {
-        std::swap(d.a, d.b);
-        std::swap(d.ta, d.tb);
-        std::swap(d.nra, d.nrb);
-        for (int q = 0; q < WMC_MAX_RUNS; ++q) std::swap(d.ra[q], d.rb[q]);
-    }
-    std::memset(a, 0, sizeof *a);
-    a->a = d.a;
-    a->b = d.b;
-    a->c = d.c;
-    a->ta = d.ta;
-    a->tb = d.tb;
-    a->tc = d.tc;
-    a->rc = d.rc;
-    std::vector<int> inA((size_t)d.rc, 0);
-    for (int q = 0; q < d.nra; ++q)
-        for (unsigned j = 0; j < ((d.ra[q] >> 8) & 255u); ++j) inA[(size_t)((d.ra[q] & 255u) + j)] = 1;
-    for (int p = 0; p < d.rc; ++p)
-        if (!inA[(size_t)p]) {
-            if (a->nhole >= STREAM_MAX_HOLES) return false;
-            a->hole[a->nhole++] = p;
-        }
-    if (d.nrb > STREAM_MAX_BRUNS) return false;
-    int nbbit = 0;
-    for (int q = 0; q < d.nrb; ++q) {
-        a->brun[q] = d.rb[q];
-        nbbit += (int)((d.rb[q] >> 8) & 255u);
-    }
-    a->nbrun = d.nrb;
-    a->rb = d.nk + nbbit;
-    a->b_lds = a->rb <= 12;
-    a->low_contig = inA[0] && inA[1];
-    return true;
-}
-
 // Register-tiled streaming contraction for one big node,
 //
 //   C[beta, sigma, omega] = sum_kappa S[beta, sigma, kappa] * O[beta, omega, kappa]
@@ -857,7 +754,7 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
 
 // Arguments of the register-tiled streaming kernel for a single-node launch,
 // if the node fits it (at most 2^5 summed entries, run lists that fit).
-static inline bool stream2_args(const NodeDesc &d, Stream2Args *a) {
+static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each = 2, int min_thread_bits = 14) {
     if (d.rc < 2 || d.nk > 5) return false;
     auto bits_of = [&](const unsigned *runs, int nr, std::vector<int> &in) {
         int n = 0;
@@ -890,13 +787,13 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a) {
     // bits looped inside a thread: the highest S-only and O-only bits at or
     // above bit 4 (lower ones are reused from cache between neighbouring
     // lanes), while keeping at least 2^14 threads
-    const int budget = std::max(0, std::min(4, d.rc - 14));
+    const int budget = std::max(0, std::min(2 * max_each, d.rc - min_thread_bits));
     int taken = 0;
     for (int p = d.rc - 1; p >= 4 && taken < budget; --p) {
-        if (inS[(size_t)p] && !inO[(size_t)p] && a->np < 2) {
+        if (inS[(size_t)p] && !inO[(size_t)p] && a->np < max_each) {
             a->pbit[a->np++] = p;
             ++taken;
-        } else if (inO[(size_t)p] && !inS[(size_t)p] && a->nq < 2) {
+        } else if (inO[(size_t)p] && !inS[(size_t)p] && a->nq < max_each) {
             a->qbit[a->nq++] = p;
             ++taken;
         }
@@ -956,27 +853,37 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
 }
 
 // Many streaming nodes in one launch (the merged steps of batches and
-// serving).  Task t owns workgroups [block_begin_t, block_begin_{t+1}); each
-// workgroup produces STREAM_MULTI_QUADS consecutive quads of its node.  Tasks
-// share NK; B is staged in LDS only when it is small (at most 2^9 entries),
-// since every workgroup stages it.
-#define STREAM_MULTI_QUADS 1024
-#define STREAM_MULTI_B 512
+// serving), on the register-tiled scheme of k_stream2 with a fixed 2 x 2
+// tile: each thread loads two rows of S and two of O and writes the four
+// outputs.  A node without an S-only (or O-only) looped bit repeats its one
+// row, so the duplicate outputs are the same value stored at the same
+// address.  Task t owns workgroups [block_begin_t, block_begin_{t+1}); each
+// workgroup covers STREAM2_MULTI_THREADS consecutive threads of its node.
+// Tasks of one launch share NK.
+#define STREAM2_MULTI_THREADS 1024
 #define WMC_STREAM_MIN_RANK 12  // merged-step nodes with at least 2^12 outputs stream
 
 struct StreamTask {
-    StreamArgs a;
+    Stream2Args a;
     long long block_begin;
 };
-static_assert(sizeof(StreamArgs) == 136, "StreamArgs layout");
-static_assert(sizeof(StreamTask) == 144, "StreamTask layout");
+static_assert(sizeof(Stream2Args) == 240, "Stream2Args layout");
+static_assert(offsetof(Stream2Args, srun) == 100 && offsetof(Stream2Args, orun) == 164 &&
+                  offsetof(Stream2Args, ro) == 228, "Stream2Args layout");
+static_assert(sizeof(StreamTask) == 248, "StreamTask layout");
+
+// Workgroups of one task.
+static inline unsigned long long stream_task_blocks(const Stream2Args &a) {
+    const unsigned long long threads = 1ull << (a.rc - a.np - a.nq);
+    return (threads + STREAM2_MULTI_THREADS - 1) / STREAM2_MULTI_THREADS;
+}
 
 template <typename T, int NK>
 __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restrict__ tasks, int ntasks,
                                                       T *__restrict__ arena, wmc_meta *meta,
                                                       const int *__restrict__ block_task = nullptr) {
-    __shared__ double Bs[STREAM_MULTI_B];
     constexpr int K = 1 << NK;
+    constexpr int KC = K < 4 ? K : 4;
     int lo = 0;
     if (block_task) {
         lo = block_task[blockIdx.x];  // one load instead of a dependent search
@@ -988,63 +895,71 @@ __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restri
         }
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
-    const StreamArgs &args = tasks[lo].a;
+    const Stream2Args &args = tasks[lo].a;
     const unsigned long long lb = (unsigned long long)((long long)blockIdx.x - tasks[lo].block_begin);
-    const int sA = scale_exp(meta[args.ta].maxbits);
-    const int sB = scale_exp(meta[args.tb].maxbits);
-    const double scaleB = ldexp(1.0, -sB), scaleA = ldexp(1.0, -sA);
-    const T *__restrict__ A = arena + args.a;
-    const T *__restrict__ B = arena + args.b;
+    const int sS = scale_exp(meta[args.ts].maxbits);
+    const int sO = scale_exp(meta[args.to].maxbits);
+    const int se = -(sS + sO);
+    const T *__restrict__ S = arena + args.s;
+    const T *__restrict__ O = arena + args.o;
     T *__restrict__ C = arena + args.c;
-    const bool b_lds = args.rb <= 9;
-    if (b_lds) {
-        for (int i = threadIdx.x; i < (1 << args.rb); i += 256) Bs[i] = (double)B[i] * scaleB;
-        __syncthreads();
+    unsigned long long cP[2] = {0, 0}, sP[2] = {0, 0}, cQ[2] = {0, 0}, oQ[2] = {0, 0};
+    if (args.np) {
+        cP[1] = uniform64(1ull << args.pbit[0]);
+        sP[1] = uniform64(apply_runs<STREAM2_RUNS>(cP[1], args.srun, args.nsrun));
     }
-    const unsigned long long quads = (1ull << args.rc) >> 2;
-    const unsigned long long q0 = lb * STREAM_MULTI_QUADS;
+    if (args.nq) {
+        cQ[1] = uniform64(1ull << args.qbit[0]);
+        oQ[1] = uniform64(apply_runs<STREAM2_RUNS>(cQ[1], args.orun, args.norun));
+    }
+    const unsigned long long threads = 1ull << (args.rc - args.np - args.nq);
+    const unsigned long long u0 = lb * STREAM2_MULTI_THREADS;
+    const unsigned long long u1 = u0 + STREAM2_MULTI_THREADS < threads ? u0 + STREAM2_MULTI_THREADS : threads;
     double vmax = 0.0;
-    for (unsigned long long q = q0 + threadIdx.x; q < quads && q < q0 + STREAM_MULTI_QUADS; q += 256) {
-        double av[4][K];
+    for (unsigned long long u = u0 + threadIdx.x; u < u1; u += 256) {
+        const unsigned long long r0 = apply_runs<6>(u, args.lrun, args.nlrun);
+        const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
+        const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
+        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const unsigned long long pa = drop_holes((q << 2) | (unsigned long long)e, args) << NK;
+        for (int kc = 0; kc < K; kc += KC) {
+            double sv[2][KC], ov[2][KC];
 #pragma unroll
-            for (int j = 0; j < K; ++j) av[e][j] = (double)A[pa + j];
+            for (int i = 0; i < 2; ++i) load_chunk<T, KC>(S + (((s0 | sP[i]) << NK) + kc), sv[i]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) load_chunk<T, KC>(O + (((o0 | oQ[j]) << NK) + kc), ov[j]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) acc[i][j] = fma(sv[i][k], ov[j][k], acc[i][j]);
         }
-        double o[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const unsigned long long pb = gather_bits((q << 2) | (unsigned long long)e, args) << NK;
-            double acc = 0.0;
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const double bv = b_lds ? Bs[pb + j] : (double)B[pb + j] * scaleB;
-                acc = fma(av[e][j], bv, acc);
+            for (int j = 0; j < 2; ++j) {
+                const T v = (T)ldexp(acc[i][j], se);
+                C[r0 | cP[i] | cQ[j]] = v;
+                vmax = fmax(vmax, fabs((double)v));
             }
-            o[e] = acc * scaleA;
-        }
-        Vec4<T>::store(C + (q << 2), o[0], o[1], o[2], o[3]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) vmax = fmax(vmax, fabs((double)(T)o[e]));
     }
     publish_max_block(meta, args.tc, vmax);
-    if (lb == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
+    if (lb == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
 }
 
-// Build the streaming tasks of a node list; returns false for a node the
-// streaming kernel cannot take.  Workgroup ranges are assigned per NK group.
 static inline bool stream_task(const NodeDesc &d, StreamTask *t) {
     std::memset(t, 0, sizeof *t);
-    return stream_args(d, &t->a) && d.nk <= 3;
+    if (d.nk > 3 || !stream2_args(d, &t->a, 1, 10)) return false;
+    t->a.o_lds = 0;
+    return true;
 }
 
 // Workgroups of the task group [f, l): the group's grid size.
 static inline unsigned long long stream_multi_blocks(const StreamTask *host_tasks, int f, int l) {
     if (f == l) return 0;
     const StreamTask &last = host_tasks[l - 1];
-    return (unsigned long long)last.block_begin +
-           ((((1ull << last.a.rc) >> 2) + STREAM_MULTI_QUADS - 1) / STREAM_MULTI_QUADS);
+    return (unsigned long long)last.block_begin + stream_task_blocks(last.a);
 }
 
 // Lookup tables that replace the kernels' searches: the node of every wave
@@ -1119,7 +1034,7 @@ static inline void split_stream(std::vector<NodeDesc> &generic, std::vector<Stre
         long long blocks = 0;
         for (StreamTask &t : by_nk[k]) {
             t.block_begin = blocks;
-            blocks += (long long)((((1ull << t.a.rc) >> 2) + STREAM_MULTI_QUADS - 1) / STREAM_MULTI_QUADS);
+            blocks += (long long)stream_task_blocks(t.a);
             tasks.push_back(t);
         }
     }

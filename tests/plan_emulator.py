@@ -30,12 +30,13 @@ GEMM = np.dtype({"names": ["a", "b", "c", "ta", "tb", "tc", "nk", "nm", "nn", "n
                  "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 48, 52, 80],
                  "itemsize": 336})
 GR_MU_A, GR_BETA_A, GR_NU_B, GR_BETA_B, GR_MU_C, GR_NU_C, GR_BETA_C = range(7)
-STREAM = np.dtype({"names": ["a", "b", "c", "ta", "tb", "tc", "rc", "nhole", "hole", "nbrun", "brun", "rb",
-                             "b_lds", "low_contig", "block_begin"],
-                   "formats": ["<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", ("<i4", (8,)), "<i4",
-                               ("<u4", (10,)), "<i4", "<i4", "<i4", "<i8"],
-                   "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 76, 80, 120, 124, 128, 136],
-                   "itemsize": 144})
+STREAM = np.dtype({"names": ["s", "o", "c", "ts", "to", "tc", "rc", "np", "nq", "pbit", "qbit", "nlrun", "nsrun",
+                             "norun", "lrun", "srun", "orun", "ro", "o_lds", "block_begin"],
+                   "formats": ["<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", ("<i4", (2,)),
+                               ("<i4", (2,)), "<i4", "<i4", "<i4", ("<u4", (6,)), ("<u4", (16,)), ("<u4", (16,)),
+                               "<i4", "<i4", "<i8"],
+                   "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 48, 56, 64, 68, 72, 76, 100, 164, 228, 232, 240],
+                   "itemsize": 248})
 
 
 def parse(plan):
@@ -75,23 +76,12 @@ def _sexp(m: float) -> int:
 
 
 def _stream_task_as_node(t, nk):
-    """A streaming task (A = the operand whose bits are C minus the holes, B
-    via run words) rewritten as (a, b, c, ta, tb, tc, rc, nk, A-runs, B-runs)
-    so the generic replay below can execute it."""
-    rc = int(t["rc"])
-    holes = set(int(h) for h in t["hole"][: int(t["nhole"])])
-    a_bits = [p for p in range(rc) if p not in holes]
-    runs_a = []
-    i = 0
-    while i < len(a_bits):
-        j = i
-        while j + 1 < len(a_bits) and a_bits[j + 1] == a_bits[j] + 1:
-            j += 1
-        runs_a.append(a_bits[i] | ((j - i + 1) << 8) | (i << 16))
-        i = j + 1
-    return dict(a=int(t["a"]), b=int(t["b"]), c=int(t["c"]), ta=int(t["ta"]), tb=int(t["tb"]), tc=int(t["tc"]),
-                rc=rc, nk=nk, ra=np.array(runs_a, dtype=np.uint32), nra=len(runs_a),
-                rb=np.array(t["brun"][: int(t["nbrun"])], dtype=np.uint32), nrb=int(t["nbrun"]))
+    """A streaming task (S, O and their C-bit run lists) rewritten as
+    (a, b, c, ta, tb, tc, rc, nk, A-runs, B-runs) so the generic replay below
+    can execute it (the product is symmetric in its operands)."""
+    return dict(a=int(t["s"]), b=int(t["o"]), c=int(t["c"]), ta=int(t["ts"]), tb=int(t["to"]), tc=int(t["tc"]),
+                rc=int(t["rc"]), nk=nk, ra=np.array(t["srun"][: int(t["nsrun"])], dtype=np.uint32),
+                nra=int(t["nsrun"]), rb=np.array(t["orun"][: int(t["norun"])], dtype=np.uint32), nrb=int(t["norun"]))
 
 
 def _replay(leaves, nodes, launches, gemms, arena_elems, nt, w, store, eta, roots, root_offs, tasks_of=None):
