@@ -66,6 +66,7 @@ struct wmc_batch {
     // offset of its wave -> node table and of its workgroup -> task table
     std::vector<int> tables;
     std::vector<int64_t> wave_off, btask_off;
+    int64_t leaf_tab_off = 0;
     uint64_t off_tables = 0;
     std::vector<int32_t> roots;
     std::vector<long long> root_off;
@@ -149,6 +150,10 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
             }
         }
         B->launches[0].work = B->leaf_work;
+        std::vector<int> ltab;
+        wave_leaf_table(B->leaves, B->leaf_work, ltab);
+        B->leaf_tab_off = (int64_t)B->tables.size();
+        B->tables.insert(B->tables.end(), ltab.begin(), ltab.end());
         // node launches, merged by index; big streaming nodes become tasks
         B->task_first.push_back(0);
         B->task_nk.push_back({0, 0, 0, 0, 0});
@@ -291,7 +296,8 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
                        (wmc_acc *)nullptr, 0);
     if (!B.leaves.empty())
         hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(B.leaf_work)), dim3(WMC_BLOCK), 0, st, L, (int)B.leaves.size(),
-                           (long long)B.leaf_work, w, arena, meta, 0ull);
+                           (long long)B.leaf_work, w, arena, meta, 0ull,
+                           (const int *)(ws + B.off_tables) + B.leaf_tab_off);
     for (size_t k = 1; k < B.launches.size(); ++k) {
         const Launch &Ln = B.launches[k];
         if (Ln.type == LAUNCH_GEMM) {

@@ -117,13 +117,20 @@ static __global__ __attribute__((unused)) void k_begin(wmc_meta *meta, int nt, w
 template <typename T>
 __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict__ L, int nl, long long work,
                                                       const double *__restrict__ w, T *__restrict__ arena,
-                                                      wmc_meta *meta, unsigned long long eta) {
+                                                      wmc_meta *meta, unsigned long long eta,
+                                                      const int *__restrict__ wave_leaf = nullptr) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
-        int lo = 0, hi = nl - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (L[mid].work_begin <= g) lo = mid; else hi = mid - 1;
+        // leaves start on wave boundaries: a wave's items belong to one leaf
+        int lo = 0;
+        if (wave_leaf) {
+            lo = wave_leaf[g / WMC_WAVE];  // one load instead of a dependent search
+        } else {
+            int hi = nl - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (L[mid].work_begin <= g) lo = mid; else hi = mid - 1;
+            }
         }
         const LeafDesc &d = L[lo];
         const long long e = g - d.work_begin;
@@ -971,6 +978,15 @@ static inline void wave_node_table(const std::vector<NodeDesc> &nodes, int64_t w
         const int64_t b = nodes[q].work_begin / WMC_WAVE;
         const int64_t e = b + (int64_t)(((1ull << nodes[q].rc) + WMC_WAVE - 1) / WMC_WAVE);
         for (int64_t w = b; w < e; ++w) out[(size_t)w] = (int)q;
+    }
+}
+
+static inline void wave_leaf_table(const std::vector<LeafDesc> &leaves, int64_t work, std::vector<int> &out) {
+    out.assign((size_t)(work / WMC_WAVE), 0);
+    for (size_t q = 0; q < leaves.size(); ++q) {
+        const int64_t b = leaves[q].work_begin / WMC_WAVE;
+        const int64_t e = b + (int64_t)(((1ull << leaves[q].rank) + WMC_WAVE - 1) / WMC_WAVE);
+        for (int64_t x = b; x < e; ++x) out[(size_t)x] = (int)q;
     }
 }
 

@@ -221,7 +221,8 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
         s.footprint = s.meta_bytes + s.arena_bytes;
         s.leaf_work = plan->leaf_work;
         uint64_t mx = sal(sizeof(double) * 2 * (uint64_t)s.n, 8) + sizeof(ClearRange) +
-                      sizeof(LeafDesc) * s.leaves.size() + sizeof(FinishEntry);
+                      sizeof(LeafDesc) * s.leaves.size() + sizeof(int) * ((uint64_t)s.leaf_work / WMC_WAVE + 1) +
+                      sizeof(FinishEntry);
         for (size_t k = 1; k < s.launches.size(); ++k) {
             const Launch &L = s.launches[k];
             // descriptors, plus the lookup tables of the merged kernels (one
@@ -439,7 +440,8 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     std::vector<StreamTask> tasks;
     std::vector<int> nkf;
     split_stream(nodes, tasks, nkf, node_work, WMC_STREAM_MIN_RANK);
-    std::vector<int> wtab, btab;
+    std::vector<int> wtab, btab, ltab;
+    wave_leaf_table(leaves, leaf_work, ltab);
     wave_node_table(nodes, node_work, wtab);
     block_task_table(tasks, nkf, btab);
     // staging image: [weights][clears][leaves][nodes][gemms][finish][tasks][tables]
@@ -456,6 +458,7 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     const uint64_t o_g = place(sizeof(GemmDesc) * gemms.size());
     const uint64_t o_f = place(sizeof(FinishEntry) * fin.size());
     const uint64_t o_t = place(sizeof(StreamTask) * tasks.size());
+    const uint64_t o_lt = place(sizeof(int) * ltab.size());
     const uint64_t o_wt = place(sizeof(int) * wtab.size());
     const uint64_t o_bt = place(sizeof(int) * btab.size());
     if (o > v->step_cap) {
@@ -474,6 +477,7 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     cp(o_g, gemms.data(), sizeof(GemmDesc) * gemms.size());
     cp(o_f, fin.data(), sizeof(FinishEntry) * fin.size());
     cp(o_t, tasks.data(), sizeof(StreamTask) * tasks.size());
+    cp(o_lt, ltab.data(), sizeof(int) * ltab.size());
     cp(o_wt, wtab.data(), sizeof(int) * wtab.size());
     cp(o_bt, btab.data(), sizeof(int) * btab.size());
     hipStream_t st = v->st;
@@ -487,7 +491,7 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     if (!leaves.empty())
         hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(leaf_work)), dim3(WMC_BLOCK), 0, st,
                            (const LeafDesc *)(stp + o_l), (int)leaves.size(), (long long)leaf_work,
-                           (const double *)(stp + o_w), arena, meta, 0ull);
+                           (const double *)(stp + o_w), arena, meta, 0ull, (const int *)(stp + o_lt));
     if (!nodes.empty())
         hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(node_work)), dim3(WMC_BLOCK), 0, st,
                            (const NodeDesc *)(stp + o_n), (int)nodes.size(), (long long)node_work, arena, meta,
