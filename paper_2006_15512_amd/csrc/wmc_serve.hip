@@ -24,6 +24,8 @@ struct SStruct {
     int32_t n = 0;                // variables, auxiliary ones included
     int32_t n_user = 0;           // a request brings 2 * n_user weights
     std::vector<double> w_aux;    // (1, 1) per auxiliary variable
+    std::vector<int> task_of;     // per node: index into tasks if it streams in merged steps, else -1
+    std::vector<StreamTask> tasks;  // streaming arguments of those nodes (region offsets not yet added)
     std::vector<LeafDesc> leaves;
     std::vector<NodeDesc> nodes;
     std::vector<GemmDesc> gemms;
@@ -210,6 +212,15 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
         s.n_user = plan->n_user;
         s.w_aux.assign(plan->w.begin() + 2 * (size_t)plan->n_user, plan->w.end());
         s.leaves = plan->leaves;
+        s.task_of.assign(plan->nodes.size(), -1);
+        for (size_t q = 0; q < plan->nodes.size(); ++q) {
+            const NodeDesc &d = plan->nodes[q];
+            StreamTask t;
+            if (d.rc >= WMC_STREAM_MIN_RANK && d.cls != WMC_CLASS_GEMM && stream_task(d, &t)) {
+                s.task_of[q] = (int)s.tasks.size();
+                s.tasks.push_back(t);
+            }
+        }
         s.nodes = plan->nodes;
         s.gemms = plan->gemms;
         s.launches = plan->launches;
@@ -383,6 +394,7 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     std::vector<NodeDesc> nodes;
     std::vector<GemmDesc> gemms;
     std::vector<FinishEntry> fin;
+    std::vector<StreamTask> by_nk[4];
     int64_t leaf_work = 0, node_work = 0;
     std::vector<SReq> keep;
     keep.reserve(v->active.size());
@@ -416,6 +428,18 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
                 gemms.push_back(g);
             } else {
                 for (int32_t q = 0; q < L.count; ++q) {
+                    const int ti = s.task_of[(size_t)(L.first + q)];
+                    if (ti >= 0) {  // streams: arguments precomputed at registration
+                        StreamTask t = s.tasks[(size_t)ti];
+                        t.a.s += abase;
+                        t.a.o += abase;
+                        t.a.c += abase;
+                        t.a.ts += (int)mbase;
+                        t.a.to += (int)mbase;
+                        t.a.tc += (int)mbase;
+                        by_nk[s.nodes[(size_t)(L.first + q)].nk].push_back(t);
+                        continue;
+                    }
                     NodeDesc d = s.nodes[(size_t)(L.first + q)];
                     d.a += abase;
                     d.b += abase;
@@ -423,6 +447,8 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
                     d.ta += (int)mbase;
                     d.tb += (int)mbase;
                     d.tc += (int)mbase;
+                    d.work_begin = node_work;
+                    node_work += (int64_t)sal((uint64_t)1 << d.rc, WMC_WAVE);
                     nodes.push_back(d);
                 }
             }
@@ -436,10 +462,20 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
         }
     }
     v->active.swap(keep);
-    // big streaming nodes of the merged step run in the multi-node streaming kernel
+    // big streaming nodes of the merged step run in the multi-node streaming
+    // kernel, one launch per summed-index size
     std::vector<StreamTask> tasks;
-    std::vector<int> nkf;
-    split_stream(nodes, tasks, nkf, node_work, WMC_STREAM_MIN_RANK);
+    std::vector<int> nkf(5, 0);
+    for (int k = 0; k < 4; ++k) {
+        nkf[(size_t)k] = (int)tasks.size();
+        long long blocks = 0;
+        for (StreamTask &t : by_nk[k]) {
+            t.block_begin = blocks;
+            blocks += (long long)stream_task_blocks(t.a);
+            tasks.push_back(t);
+        }
+    }
+    nkf[4] = (int)tasks.size();
     std::vector<int> wtab, btab, ltab;
     wave_leaf_table(leaves, leaf_work, ltab);
     wave_node_table(nodes, node_work, wtab);
