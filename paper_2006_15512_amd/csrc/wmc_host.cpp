@@ -652,9 +652,12 @@ static int32_t node_class(int32_t ra, int32_t rb, int32_t rc, int32_t nk) {
     int32_t nb = ra + rb - rc - 2 * nk;
     int32_t nn = std::min(ra, rb) - nk - nb;  // columns: variables of the smaller operand only
     int32_t nm = std::max(ra, rb) - nk - nb;
-    // matrix cores pay only with at least 16 summed entries; below that the
-    // node is HBM-bound and streams
-    if (nk >= 4 && nn >= 2 && nk + nn >= 6 && nn <= 7 && nm + nb >= 4) return WMC_CLASS_GEMM;
+    // matrix cores pay only with at least 16 summed entries (below that the
+    // node is HBM-bound and streams) and for few batch bits: with many, each
+    // workgroup owns a short matrix per batch index and the batch bits land
+    // in the low address bits of the output, where the streaming kernel's
+    // C-ordered stores do better (measured on banded formulas)
+    if (nk >= 4 && nn >= 2 && nk + nn >= 6 && nn <= 7 && nm + nb >= 4 && nb <= 6) return WMC_CLASS_GEMM;
     return WMC_CLASS_STREAM;
 }
 
