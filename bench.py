@@ -49,9 +49,9 @@ def workload(name: str):
         return f, dict(kind="order", order=wl.row_major_order(12, 24)), "grid CNF 12x24, seed 1, row-major sweep"
     if name == "banded300":
         f = wl.banded_3cnf(300, 1050, 37, seed=0)
-        return f, dict(kind="minfill", seed=0, rank_cap=27, block=3), \
+        return f, dict(kind="minfill", seed=0, rank_cap=27, block=4), \
             "banded random 3-CNF, 300 vars, 1050 clauses (ratio 3.5), window 37, w~U(0.05,0.95), seed 0; " \
-            "seeded min-fill tree (max rank 30) sliced to rank 27"
+            "seeded min-fill order (max rank 30; 29 once blocked by 4) sliced to rank 27, 8 slices"
     if name == "config1":
         f = wl.random_kcnf(20, 85, seed=2)
         return f, dict(kind="minfill", seed=0), "random 3-CNF 20 vars 85 clauses, seed 2, min-fill tree"
