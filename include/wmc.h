@@ -44,7 +44,8 @@ typedef enum {
     WMC_ERR_CAP_UNREACHABLE = 3,  /* slicing cannot meet the memory / rank cap */
     WMC_ERR_DEVICE = 4,           /* a HIP call failed; message in wmc_last_error() */
     WMC_ERR_BUSY = 5,             /* server queue full */
-    WMC_ERR_UNSUPPORTED = 6       /* clause longer than WMC_MAX_CLAUSE, rank too large */
+    WMC_ERR_UNSUPPORTED = 6       /* rank too large, supplied tree over factored clauses,
+                                     sliced plan in a batch or server */
 } wmc_status;
 
 typedef enum { WMC_FP64 = 0, WMC_FP32_SCALED = 1 } wmc_precision;
@@ -93,7 +94,8 @@ typedef struct wmc_plan_t wmc_plan_t;
 wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
                              const int32_t *lits, const double *weights, wmc_network **out);
 
-/* Size of the Theorem-2 network: n_tensors = n_vars + n_clauses tensors,
+/* Size of the Theorem-2 network: n_tensors = n_vars + n_clauses tensors
+ * (auxiliary variables and chain clauses of factored long clauses included),
  * n_indices = number of (variable, clause) incidences (distinct per clause). */
 wmc_status wmc_network_info(const wmc_network *net, int64_t *n_tensors, int64_t *n_indices);
 
@@ -220,9 +222,9 @@ wmc_status wmc_contract_slices(const wmc_plan_t *plan, const double *weights, vo
  * launch's algorithmic bytes (elem_size * (|A|+|B|+|C|) summed over its
  * nodes), flops (2*b*m*n*k) and node class (-1 for non-node launches); with
  * all arrays NULL it only reports *n_out.  wmc_contract_profile is
- * wmc_contract with a HIP event recorded on `stream` after every launch;
- * ms[k] (k < n_out - 1... one entry per launch) receives the duration of
- * launch k summed over the slices. */
+ * wmc_contract with a HIP event recorded on `stream` around every launch;
+ * ms (cap >= n_out entries) receives in ms[k] the duration of launch k in
+ * that same order, summed over the slices. */
 wmc_status wmc_plan_launches(const wmc_plan_t *plan, double *bytes, double *flops, int32_t *cls,
                              int64_t cap, int64_t *n_out);
 wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double *weights, void *workspace,
@@ -232,7 +234,9 @@ wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double *weights, v
 /* ------------------------------------------------------------------ */
 /* Batches: many planned networks contracted in shared launches         */
 /* ------------------------------------------------------------------ */
-/* The plans' launch lists are merged by index (launch k of one plan depends
+/* Each instance is the paper's execution stage (Algorithm 2 over its plan's
+ * tree); the paper runs formulas one at a time, this runs many together.
+ * The plans' launch lists are merged by index (launch k of one plan depends
  * only on its own launches < k), their descriptors concatenated into one
  * arena, meta table and weight vector, and every root finished by one kernel.
  * Plans must share a precision and be unsliced (WMC_ERR_UNSUPPORTED
@@ -266,7 +270,9 @@ wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, ui
 /* ------------------------------------------------------------------ */
 /* Serving: weight queries on registered structures, continuous batching */
 /* ------------------------------------------------------------------ */
-/* A server owns a caller-supplied device buffer: two staging areas for step
+/* Each request is the paper's execution stage (Algorithm 2) on a registered
+ * plan with the request's weights W (Definition 1); requests share launches.
+ * A server owns a caller-supplied device buffer: two staging areas for step
  * descriptors (2 * step_bytes), a result table, and the request regions (at
  * most hbm_budget_bytes).  Registered structures are unsliced plans of the
  * server's precision.  A request (structure, weight vector) waits in a FIFO
