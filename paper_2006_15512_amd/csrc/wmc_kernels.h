@@ -465,6 +465,11 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
     __syncthreads();
     double vmax = 0.0;
     for (unsigned long long grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        // B is the same in every group; keep the compiler from hoisting all
+        // its LDS reads out of the loop when they would not fit beside the
+        // accumulators (NT * S values per lane: 128 registers at K = N = 64,
+        // which left one wave per SIMD)
+        if constexpr (NT * S > 16) asm volatile("" ::: "memory");
         T a[TPW][S];
         bool ok[TPW];
 #pragma unroll
