@@ -730,7 +730,10 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
         for (int i = 0; i < P; ++i)
 #pragma unroll
             for (int j = 0; j < Q; ++j) acc[i][j] = 0.0;
-#pragma unroll
+        // K >= 16: the chunk loop stays rolled, so only one chunk's rows
+        // are in registers (fully unrolled, the loads of every chunk were
+        // hoisted: 256+ registers, one wave per SIMD)
+#pragma unroll (NK >= 4 ? 1 : 8)
         for (int kc = 0; kc < K; kc += KC) {
             double sv[P][KC], ov[Q][KC];
 #pragma unroll
