@@ -109,7 +109,14 @@ def cpu_baseline(name: str):
         per_solve = dt / k
         sample = f"oracle bucket elimination, {k} full solves in {dt:.1f}s"
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample}
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample,
+            "cpu_model": model}
 
 
 def achievable(torch, precision: str):
