@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="with --profile-only: also run a plain device-to-device copy of MIB MiB "
                          "(reference for the HBM byte counters)")
+    ap.add_argument("--gemm-calibration", type=int, default=0, metavar="N",
+                    help="with --profile-only: end with one library N^3 matrix product (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the slice loop would be split across "
@@ -328,6 +330,14 @@ def main():
             dst.copy_(src)
             torch.cuda.synchronize()
             print(f"copy calibration: {n * 8} bytes read and written", flush=True)
+        if args.gemm_calibration:
+            m = args.gemm_calibration
+            dt = torch.float64 if args.precision == "fp64" else torch.float32
+            a = torch.rand(m, m, dtype=dt, device="cuda")
+            b = torch.rand(m, m, dtype=dt, device="cuda")
+            c = a @ b
+            torch.cuda.synchronize()
+            print(f"gemm calibration: {2 * m ** 3} flops ({dt})", flush=True)
         print(f"profile-only: {args.steps} solves, W = {v.mantissa} * 2^{v.exp2}", flush=True)
         return
 
