@@ -1,4 +1,4 @@
-"""Plan shape chosen by measurement.
+"""Plan shape chosen by measurement, and Algorithm 1's anytime planning loop.
 
 The block size of the elimination steps sets the matrix nodes' shapes (a
 step over k variables sums K = 2^k entries), and the tree seed changes the
@@ -90,3 +90,72 @@ def autotune_plan(f, precision: str = "fp64", blocks: Sequence[int] = (1, 2, 3, 
             json.dump(table, fh, indent=1)
         os.replace(tmp, cache)
     return best_plan, rep
+
+
+# ---------------------------------------------------------------------------
+# Anytime planning (Algorithm 1): generate contraction trees until the chosen
+# one's predicted execution time, scaled by the performance factor alpha,
+# falls below the time already spent planning.
+# ---------------------------------------------------------------------------
+
+# Execution-time model per launch: max(bytes / bandwidth, flops / rate) for
+# the launch's node class, plus a fixed launch cost; class rates are the
+# achieved figures measured on MI355X (FP64; FP32 moves half the bytes).
+DEFAULT_RATES = {
+    "launch_s": 5e-6,
+    0: (0.05e12, 1e12),    # small nodes: launch/latency-bound
+    1: (2.5e12, 30e12),    # streaming nodes
+    2: (4.4e12, 30e12),    # matrix nodes
+}
+
+
+def time_cost(plan, rates: Optional[Dict] = None) -> float:
+    """Predicted seconds for one wmc_contract of ``plan`` (all slices)."""
+    from . import plan_launches
+    r = dict(DEFAULT_RATES)
+    if rates:
+        r.update(rates)
+    b, fl, cls = plan_launches(plan)
+    t = 0.0
+    for k in range(len(b)):
+        c = int(cls[k])
+        bw, fr = r.get(c, r[0]) if c >= 0 else (r[0][0], r[0][1])
+        t += max(float(b[k]) / bw, float(fl[k]) / fr) + r["launch_s"]
+    return t * plan.stats()["n_slices"]
+
+
+def anytime_plan(f, alpha: float, precision: str = "fp64", blocks: Sequence[int] = (1, 2, 3, 4, 5, 6),
+                 rank_cap: int = 0, mem_cap_bytes: int = 0, max_candidates: int = 64,
+                 rates: Optional[Dict] = None) -> Tuple[Plan, Dict]:
+    """Algorithm 1's planning loop: candidate trees (seeded min-fill orders
+    with seeds 0, 1, 2, ... at each block size) are generated one after
+    another; the best by ``time_cost`` is kept, and planning stops once
+    alpha * time_cost(best) < planning time so far (or after
+    ``max_candidates``).  Returns (best plan, report)."""
+    net = Network.from_formula(f)
+    t0 = time.perf_counter()
+    best, best_cost, tried, history = None, float("inf"), 0, []
+    seed = 0
+    while tried < max_candidates:
+        for b in blocks:
+            if tried >= max_candidates:
+                break
+            try:
+                p = Plan(net, kind="minfill", seed=seed, block=int(b), precision=precision, rank_cap=rank_cap,
+                         mem_cap_bytes=mem_cap_bytes)
+            except WmcError:
+                tried += 1
+                continue
+            tried += 1
+            c = time_cost(p, rates)
+            history.append({"seed": seed, "block": int(b), "cost_s": c})
+            if c < best_cost:
+                best, best_cost = p, c
+            if best is not None and alpha * best_cost < time.perf_counter() - t0:
+                return best, {"candidates": tried, "plan_seconds": time.perf_counter() - t0,
+                              "predicted_seconds": best_cost, "history": history, "stopped": "alpha"}
+        seed += 1
+    if best is None:
+        raise WmcError(3, "anytime_plan: no candidate plan could be built")
+    return best, {"candidates": tried, "plan_seconds": time.perf_counter() - t0, "predicted_seconds": best_cost,
+                  "history": history, "stopped": "max_candidates"}

@@ -403,3 +403,33 @@ def test_batch_with_big_nodes_replays():
     for f, v in zip(fs, vals):
         m, e = oracle.bucket(f)
         assert rel_err(v, Fraction(m) * Fraction(2) ** e) <= 1e-12
+
+
+# ------------------------------------------------------------------ anytime planning (Algorithm 1)
+def test_anytime_plan_stops_by_alpha_and_keeps_the_best():
+    """alpha = 0 stops after the first candidate; a large alpha keeps
+    planning up to the candidate limit and returns the cheapest predicted
+    plan; the plan still computes W (replayed on the CPU)."""
+    from paper_2006_15512_amd.autotune import anytime_plan, time_cost
+    from plan_emulator import emulate
+    f = wl.banded_3cnf(60, 200, 14, seed=3)
+    p0, r0 = anytime_plan(f, alpha=0.0)
+    assert r0["candidates"] == 1 and r0["stopped"] == "alpha"
+    p1, r1 = anytime_plan(f, alpha=1e9, blocks=(1, 2, 3), max_candidates=9)
+    assert r1["candidates"] == 9 and r1["stopped"] == "max_candidates"
+    assert r1["predicted_seconds"] == min(h["cost_s"] for h in r1["history"])
+    assert abs(time_cost(p1) - r1["predicted_seconds"]) <= 1e-12 * r1["predicted_seconds"]
+    got, _ = emulate(p1, f.weights)
+    m, e = oracle.bucket(f)
+    assert rel_err(got, Fraction(m) * Fraction(2) ** e) <= 1e-12
+
+
+def test_time_cost_grows_with_slices():
+    """Slicing to a lower rank multiplies the predicted time by the slices."""
+    from paper_2006_15512_amd.autotune import time_cost
+    f = wl.banded_3cnf(120, 400, 24, seed=1)
+    net = W.Network.from_formula(f)
+    a = W.Plan(net, seed=1)
+    b = W.Plan(net, seed=1, rank_cap=a.stats()["max_rank"] - 3)
+    assert b.stats()["n_slices"] >= 8
+    assert time_cost(b) > time_cost(a)
