@@ -60,8 +60,9 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
             if (Ln.type == LAUNCH_GEMM)
                 launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st);
             else if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM &&
-                     stream2_args(P.nodes[(size_t)Ln.first], &sa) &&
-                     launch_stream2<T>(sa, P.nodes[(size_t)Ln.first].nk, arena, meta, st)) {
+                     stream2_args(P.nodes[(size_t)Ln.first], &sa, 2, 14, 6) &&
+                     launch_stream2<T>(sa, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
+                                      stream2_split_lanes<T>(P.nodes[(size_t)Ln.first].nk))) {
             } else
                 hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first,
                                    Ln.count, (long long)Ln.work, arena, meta);

@@ -611,14 +611,16 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
 // output bits only O has.  Each thread owns P = 2^np values of (up to two,
 // high) sigma bits and Q = 2^nq values of (up to two, high) omega bits: it
 // loads P rows of S and Q rows of O (2^nk contiguous summed entries each, in
-// chunks of up to 4) and produces the P x Q outputs, so each S row is read
+// chunks of up to 8) and produces the P x Q outputs, so each S row is read
 // once per Q outputs and each O row once per P.  The remaining output bits
-// enumerate threads in C order, so for a fixed (p, q) the lanes of a wave
-// store consecutive outputs.  The bits chosen for P and Q are the ones whose
-// reuse distance in C order is largest.  O is staged in LDS when it has at
+// enumerate threads: the lowest ones in C order, so for a fixed (p, q) the
+// lanes of a wave store consecutive outputs, then the other one-operand
+// bits, so that threads sharing a row run at the same time.  The bits
+// chosen for P and Q are the highest one-operand bits.  O is staged in LDS when it has at
 // most 2^12 entries.  Every product is summed in the order of the summed
 // index and scaled once at the end, exactly as the generic node kernel does.
 #define STREAM2_RUNS 16
+#define STREAM2_LRUNS 16
 #define STREAM2_O_LDS 4096
 
 struct Stream2Args {
@@ -628,7 +630,7 @@ struct Stream2Args {
     int np, nq;                        // sigma bits and omega bits handled inside a thread
     int pbit[2], qbit[2];              // their positions in C
     int nlrun, nsrun, norun;
-    unsigned lrun[6];                  // thread index -> C address (runs src | len << 8 | dst << 16)
+    unsigned lrun[STREAM2_LRUNS];      // thread index -> C address (runs src | len << 8 | dst << 16)
     unsigned srun[STREAM2_RUNS];       // C address -> S row
     unsigned orun[STREAM2_RUNS];       // C address -> O row
     int ro;                            // storage rank of O, summed bits included
@@ -722,7 +724,7 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
     double vmax = 0.0;
     for (unsigned long long u = (unsigned long long)lb * blockDim.x + threadIdx.x; u < threads;
          u += (unsigned long long)G * blockDim.x) {
-        const unsigned long long r0 = apply_runs<6>(u, args.lrun, args.nlrun);
+        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);
         const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
         const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
         double acc[P][Q];
@@ -769,9 +771,124 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
     if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
 }
 
+// Long summed index (K >= 8): the same register tile, but the K summed
+// entries of every output are split over a group of LG lanes, lane p of a
+// group holding entries [p K/LG, (p+1) K/LG) of each of its P + Q rows.  A
+// load instruction then reads whole rows (LG lanes side by side in one
+// row) instead of one 16-byte piece of 64 different rows, which is what
+// bounds the unsplit kernel at K = 16.  After the partial products, a
+// butterfly over the group (lane p and p ^ b, b = LG/2 ... 1) halves the
+// P x Q partial sums per step: the lane with bit b set keeps the upper half
+// and receives the partner's, the other the lower half, so each lane ends
+// with PQ / LG complete outputs (or, when PQ < LG, the group's lanes agree
+// on the single output and the lowest stores it).  The sum over the
+// summed index is therefore a fixed tree over the lanes' sequential partial
+// sums.
+template <int V, int B>
+__device__ __forceinline__ void group_reduce_scatter(double *v, int lane, int &fbase, int &dup) {
+    if constexpr (B >= 1) {
+        if constexpr (V > 1) {
+            const bool up = (lane & B) != 0;
+#pragma unroll
+            for (int t = 0; t < V / 2; ++t) {
+                const double send = up ? v[t] : v[t + V / 2];
+                const double keep = up ? v[t + V / 2] : v[t];
+                v[t] = keep + __shfl_xor(send, B, WMC_WAVE);
+            }
+            if (up) fbase += V / 2;
+            group_reduce_scatter<V / 2, B / 2>(v, lane, fbase, dup);
+        } else {
+            v[0] += __shfl_xor(v[0], B, WMC_WAVE);
+            dup |= B;
+            group_reduce_scatter<1, B / 2>(v, lane, fbase, dup);
+        }
+    }
+}
+
+template <typename T, int NK, int NP, int NQ, int LG>
+__global__ void __launch_bounds__(256) k_stream2_split(const Stream2Args args, T *__restrict__ arena,
+                                                       wmc_meta *meta) {
+    constexpr int K = 1 << NK;
+    constexpr int KL = K / LG;  // summed entries per lane and row
+    constexpr int P = 1 << NP, Q = 1 << NQ, PQ = P * Q;
+    constexpr int GPB = 256 / LG;  // groups per workgroup
+    constexpr int VF = PQ >= LG ? PQ / LG : 1;
+    static_assert(KL >= 2 && LG <= 8, "split layout");
+    const int sS = scale_exp(meta[args.ts].maxbits);
+    const int sO = scale_exp(meta[args.to].maxbits);
+    const T *__restrict__ S = arena + args.s;
+    const T *__restrict__ O = arena + args.o;
+    T *__restrict__ C = arena + args.c;
+    const int lane = (int)(threadIdx.x & (LG - 1));
+    unsigned long long sP[P], oQ[Q];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) c |= (unsigned long long)((i >> t) & 1) << args.pbit[t];
+        sP[i] = uniform64(apply_runs<STREAM2_RUNS>(c, args.srun, args.nsrun));
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) c |= (unsigned long long)((j >> t) & 1) << args.qbit[t];
+        oQ[j] = uniform64(apply_runs<STREAM2_RUNS>(c, args.orun, args.norun));
+    }
+    const int se = -(sS + sO);
+    const unsigned long long groups = 1ull << (args.rc - NP - NQ);
+    const unsigned G = gridDim.x;
+    const unsigned lb = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
+    double vmax = 0.0;
+    // a group's lanes share u, so every lane of a group runs the same
+    // iterations and the exchanges below stay inside active groups
+    for (unsigned long long u = (unsigned long long)lb * GPB + threadIdx.x / LG; u < groups;
+         u += (unsigned long long)G * GPB) {
+        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);
+        const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
+        const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
+        double sv[P][KL], ov[Q][KL];
+#pragma unroll
+        for (int i = 0; i < P; ++i) load_chunk<T, KL>(S + (((s0 | sP[i]) << NK) + lane * KL), sv[i]);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) load_chunk<T, KL>(O + (((o0 | oQ[j]) << NK) + lane * KL), ov[j]);
+        double acc[PQ];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                double a = 0.0;
+#pragma unroll
+                for (int k = 0; k < KL; ++k) a = fma(sv[i][k], ov[j][k], a);
+                acc[i * Q + j] = a;
+            }
+        int fbase = 0, dup = 0;
+        group_reduce_scatter<PQ, LG / 2>(acc, lane, fbase, dup);
+        if ((lane & dup) == 0) {
+#pragma unroll
+            for (int t = 0; t < VF; ++t) {
+                const int f = fbase + t;  // output index i * Q + j
+                unsigned long long c = r0;
+#pragma unroll
+                for (int b = 0; b < NQ; ++b)
+                    if ((f >> b) & 1) c |= 1ull << args.qbit[b];
+#pragma unroll
+                for (int b = 0; b < NP; ++b)
+                    if ((f >> (NQ + b)) & 1) c |= 1ull << args.pbit[b];
+                const T v = (T)ldexp(acc[t], se);
+                C[c] = v;
+                vmax = fmax(vmax, fabs((double)v));
+            }
+        }
+    }
+    publish_max_block(meta, args.tc, vmax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
+}
+
 // Arguments of the register-tiled streaming kernel for a single-node launch,
 // if the node fits it (at most 2^5 summed entries, run lists that fit).
-static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each = 2, int min_thread_bits = 14) {
+static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each = 2, int min_thread_bits = 14,
+                                int low = -1) {
     if (d.rc < 2 || d.nk > 5) return false;
     auto bits_of = [&](const unsigned *runs, int nr, std::vector<int> &in) {
         int n = 0;
@@ -815,7 +932,11 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each 
             ++taken;
         }
     }
-    // remaining C bits, ascending, numbered by the thread index
+    // remaining C bits, numbered by the thread index: the lowest `low` of
+    // them in C order (a wave's lanes store consecutive outputs), then the
+    // bits that only one operand has, then the rest.  Threads that share an
+    // operand row then run close together in time, so the row comes from
+    // HBM once and from the L2 cache for its other readers.
     std::vector<int> rest;
     for (int p = 0; p < d.rc; ++p) {
         bool used = false;
@@ -823,23 +944,47 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each 
         for (int t = 0; t < a->nq; ++t) used |= a->qbit[t] == p;
         if (!used) rest.push_back(p);
     }
-    int nl = 0;
-    for (size_t t = 0; t < rest.size();) {
-        size_t e = t + 1;
-        while (e < rest.size() && rest[e] == rest[e - 1] + 1) ++e;
-        if (nl >= 6) return false;
-        a->lrun[nl++] = WMC_RUN(t, e - t, rest[t]);
-        t = e;
+    auto make_runs = [&](const std::vector<int> &order) {
+        int nl = 0;
+        for (size_t t = 0; t < order.size();) {
+            size_t e = t + 1;
+            while (e < order.size() && order[e] == order[e - 1] + 1) ++e;
+            if (nl >= STREAM2_LRUNS) return -1;
+            a->lrun[nl++] = WMC_RUN(t, e - t, order[t]);
+            t = e;
+        }
+        return nl;
+    };
+    int nl = -1;
+    if (low >= 0 && (int)rest.size() > low) {
+        std::vector<int> order(rest.begin(), rest.begin() + low);
+        for (size_t t = (size_t)low; t < rest.size(); ++t)
+            if (inS[(size_t)rest[t]] != inO[(size_t)rest[t]]) order.push_back(rest[t]);
+        for (size_t t = (size_t)low; t < rest.size(); ++t)
+            if (inS[(size_t)rest[t]] == inO[(size_t)rest[t]]) order.push_back(rest[t]);
+        nl = make_runs(order);
     }
+    if (nl < 0) nl = make_runs(rest);
+    if (nl < 0) return false;
     a->nlrun = nl;
     a->o_lds = (1 << a->ro) <= STREAM2_O_LDS && d.rc >= 16;
     return true;
 }
 
+// Lanes per summed-index group for a single-node streaming launch (0: one
+// lane per output tile).  Measured on the sliced banded formula: FP64
+// nodes with K >= 16 gain from groups of 4 (7.04 -> 7.82 solves/s; groups
+// of 8: 7.26); FP32 (rows of 64 bytes) and K = 8 lose (FP32 13.3 -> 11.7,
+// K = 8 with groups of 4: 2.93 -> 2.70).
+template <typename T>
+static inline int stream2_split_lanes(int nk) {
+    return sizeof(T) == 8 && nk >= 4 ? 4 : 0;
+}
+
 // Returns false (nothing launched) if no instance covers the arguments.
 template <typename T>
-static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st) {
-    const unsigned long long threads = 1ull << (sa.rc - sa.np - sa.nq);
+static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st, int lg = 0) {
+    const unsigned long long threads = (1ull << (sa.rc - sa.np - sa.nq)) * (unsigned long long)(lg > 0 ? lg : 1);
     unsigned long long blocks = (threads + 255) / 256;
     // grid cap (measured on the sliced banded formula): FP32 runs fastest
     // with about one resident round of workgroups looping over the outputs,
@@ -855,6 +1000,23 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
     if (a.o_lds && outs_per_wg < (16ull << sa.ro)) a.o_lds = 0;
     const size_t lds = a.o_lds ? sizeof(double) << a.ro : 0;
     const dim3 g((unsigned)blocks), b(256);
+    if constexpr (sizeof(T) == 8) {
+        if (lg > 0) {
+#define WMC_S2X(NKV, LGV, NPV, NQV)                                                                    \
+    if (nk == NKV && lg == LGV && a.np == NPV && a.nq == NQV) {                                        \
+        hipLaunchKernelGGL((k_stream2_split<T, NKV, NPV, NQV, LGV>), g, b, 0, st, a, arena, meta);      \
+        return true;                                                                                   \
+    }
+#define WMC_S2X_PQ(NKV, LGV)                                                                          \
+    WMC_S2X(NKV, LGV, 0, 0) WMC_S2X(NKV, LGV, 0, 1) WMC_S2X(NKV, LGV, 0, 2) WMC_S2X(NKV, LGV, 1, 0)   \
+    WMC_S2X(NKV, LGV, 1, 1) WMC_S2X(NKV, LGV, 1, 2) WMC_S2X(NKV, LGV, 2, 0) WMC_S2X(NKV, LGV, 2, 1)   \
+    WMC_S2X(NKV, LGV, 2, 2)
+            WMC_S2X_PQ(4, 4) WMC_S2X_PQ(5, 4)
+#undef WMC_S2X_PQ
+#undef WMC_S2X
+            return false;
+        }
+    }
 #define WMC_S2(NKV, NPV, NQV)                                                                  \
     if (nk == NKV && a.np == NPV && a.nq == NQV) {                                             \
         hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, lds, st, a, arena, meta);      \
@@ -884,10 +1046,10 @@ struct StreamTask {
     Stream2Args a;
     long long block_begin;
 };
-static_assert(sizeof(Stream2Args) == 240, "Stream2Args layout");
-static_assert(offsetof(Stream2Args, srun) == 100 && offsetof(Stream2Args, orun) == 164 &&
-                  offsetof(Stream2Args, ro) == 228, "Stream2Args layout");
-static_assert(sizeof(StreamTask) == 248, "StreamTask layout");
+static_assert(sizeof(Stream2Args) == 280, "Stream2Args layout");
+static_assert(offsetof(Stream2Args, lrun) == 76 && offsetof(Stream2Args, srun) == 140 &&
+                  offsetof(Stream2Args, orun) == 204 && offsetof(Stream2Args, ro) == 268, "Stream2Args layout");
+static_assert(sizeof(StreamTask) == 288, "StreamTask layout");
 
 // Workgroups of one task.
 static inline unsigned long long stream_task_blocks(const Stream2Args &a) {
@@ -934,7 +1096,7 @@ __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restri
     const unsigned long long u1 = u0 + STREAM2_MULTI_THREADS < threads ? u0 + STREAM2_MULTI_THREADS : threads;
     double vmax = 0.0;
     for (unsigned long long u = u0 + threadIdx.x; u < u1; u += 256) {
-        const unsigned long long r0 = apply_runs<6>(u, args.lrun, args.nlrun);
+        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);
         const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
         const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
         double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};

@@ -33,10 +33,10 @@ GR_MU_A, GR_BETA_A, GR_NU_B, GR_BETA_B, GR_MU_C, GR_NU_C, GR_BETA_C = range(7)
 STREAM = np.dtype({"names": ["s", "o", "c", "ts", "to", "tc", "rc", "np", "nq", "pbit", "qbit", "nlrun", "nsrun",
                              "norun", "lrun", "srun", "orun", "ro", "o_lds", "block_begin"],
                    "formats": ["<i8", "<i8", "<i8", "<i4", "<i4", "<i4", "<i4", "<i4", "<i4", ("<i4", (2,)),
-                               ("<i4", (2,)), "<i4", "<i4", "<i4", ("<u4", (6,)), ("<u4", (16,)), ("<u4", (16,)),
+                               ("<i4", (2,)), "<i4", "<i4", "<i4", ("<u4", (16,)), ("<u4", (16,)), ("<u4", (16,)),
                                "<i4", "<i4", "<i8"],
-                   "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 48, 56, 64, 68, 72, 76, 100, 164, 228, 232, 240],
-                   "itemsize": 248})
+                   "offsets": [0, 8, 16, 24, 28, 32, 36, 40, 44, 48, 56, 64, 68, 72, 76, 140, 204, 268, 272, 280],
+                   "itemsize": 288})
 
 
 def parse(plan):
