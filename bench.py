@@ -27,7 +27,7 @@ import wmc_workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 # kernel that runs the launches of each node class in a single solve
-KERNEL_OF_CLASS = {0: "k_nodes (small nodes)", 1: "k_stream2 (streaming nodes)",
+KERNEL_OF_CLASS = {0: "k_nodes (small nodes)", 1: "k_stream_mfma + k_stream2 (streaming nodes)",
                    2: "k_gemm_p (MFMA GEMM nodes)", 3: "k_nodes"}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3

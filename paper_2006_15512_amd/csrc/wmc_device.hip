@@ -57,8 +57,12 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
         for (size_t k = 1; k < P.launches.size(); ++k) {
             const Launch &Ln = P.launches[k];
             Stream2Args sa;
+            StreamMfmaArgs ma;
             if (Ln.type == LAUNCH_GEMM)
                 launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st);
+            else if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM &&
+                     stream_mfma_args(P.nodes[(size_t)Ln.first], &ma))
+                launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st);
             else if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM &&
                      stream2_args(P.nodes[(size_t)Ln.first], &sa, 2, 14, 6) &&
                      launch_stream2<T>(sa, P.nodes[(size_t)Ln.first].nk, arena, meta, st,

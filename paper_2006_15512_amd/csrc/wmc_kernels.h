@@ -971,10 +971,298 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each 
     return true;
 }
 
+// Long summed index on the matrix cores.  For a node with K >= 16 the
+// outputs sharing a batch value form a small matrix product
+//   C[beta, mu, nu] = sum_k A[beta, mu, k] B[beta, nu, k],
+// so a wave computes a 16 x 16 block of it (4 mu bits as rows, 4 nu bits
+// as columns, fewer when the node has fewer: rows then repeat) with K/4
+// MFMA steps, loading 16 rows of A and 16 of B once for 256 outputs, where
+// the register-tiled kernels load P + Q rows for P x Q outputs.  Lane l
+// holds summed entries [g K/4, (g+1) K/4) of its row and column (g = l/16)
+// and step s multiplies entry g K/4 + s, so the steps together cover every
+// k once.  A workgroup covers every combination of a set T of output bits:
+// the row and column bits, and batch bits so that T holds C's four lowest
+// bits (up to 16 blocks, one or more per wave).  The blocks go to LDS and
+// are written out in C order, so every store covers whole 128-byte
+// segments.  The remaining output bits number the workgroup tiles,
+// one-operand bits first, so tiles sharing operand rows run together.
+#define SMFMA_MAX_T 12
+
+struct StreamMfmaArgs {
+    long long a, b, c;                 // element offsets: row operand, column operand, C
+    int ta, tb, tc;                    // meta entries
+    int rc;                            // output rank
+    int nt;                            // |T|
+    int nrb, ncb, nbt;                 // row, column and block (batch) bits in T
+    int rbit[4], cbit[4], tbit[4];     // their C positions
+    int tpos[SMFMA_MAX_T];             // T ascending by C position
+    int tdst[SMFMA_MAX_T];             // bit of the LDS index (block << 8 | row << 4 | column) it feeds
+    int nwrun, nwarun, nwbrun, nar, nbr;
+    unsigned wrun[STREAM2_LRUNS];      // tile index -> C bits outside T
+    unsigned warun[STREAM2_LRUNS];     // tile index -> A row bits
+    unsigned wbrun[STREAM2_LRUNS];     // tile index -> B row bits
+    unsigned arun[STREAM2_RUNS];       // C address -> A row
+    unsigned brun[STREAM2_RUNS];       // C address -> B row
+};
+
+// N consecutive entries of a row in the storage type (N a multiple of 4).
+template <typename T, int N>
+__device__ __forceinline__ void load_row(const T *__restrict__ p, T *v) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int h = 0; h < N / 2; ++h) {
+            const double2 x = ((const double2 *)p)[h];
+            v[2 * h] = x.x;
+            v[2 * h + 1] = x.y;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < N / 4; ++h) {
+            const float4 x = ((const float4 *)p)[h];
+            v[4 * h] = x.x;
+            v[4 * h + 1] = x.y;
+            v[4 * h + 2] = x.z;
+            v[4 * h + 3] = x.w;
+        }
+    }
+}
+
+template <typename T, int NK>
+__global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, T *__restrict__ arena,
+                                                     wmc_meta *meta) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    constexpr int K = 1 << NK, KG = K / 4;
+    constexpr int NBW = NK == 4 ? 4 : 2;  // blocks per wave (at most 16 / 8 per tile)
+    __shared__ T tile[16 * 256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int sA = scale_exp(meta[args.ta].maxbits);
+    const int sB = scale_exp(meta[args.tb].maxbits);
+    const int se = -(sA + sB);
+    const T *__restrict__ A = arena + args.a;
+    const T *__restrict__ B = arena + args.b;
+    T *__restrict__ C = arena + args.c;
+    // this lane's row and column inside a block, as operand row offsets
+    unsigned long long rowc = 0, colc = 0;
+    for (int t = 0; t < args.nrb; ++t)
+        if ((l16 >> t) & 1) rowc |= 1ull << args.rbit[t];
+    for (int t = 0; t < args.ncb; ++t)
+        if ((l16 >> t) & 1) colc |= 1ull << args.cbit[t];
+    const unsigned long long aR = apply_runs<STREAM2_RUNS>(rowc, args.arun, args.nar);
+    const unsigned long long bC = apply_runs<STREAM2_RUNS>(colc, args.brun, args.nbr);
+    // write-out: element e of the tile (T bits ascending) sits at LDS index
+    // lds(e) and C offset off(e); the low 8 bits of e are this thread's
+    unsigned lds_lo = 0;
+    unsigned long long off_lo = 0;
+    for (int q = 0; q < args.nt && q < 8; ++q)
+        if ((threadIdx.x >> q) & 1) {
+            lds_lo |= 1u << args.tdst[q];
+            off_lo |= 1ull << args.tpos[q];
+        }
+    const int nblk = 1 << args.nbt;
+    const int mine = nblk > wave ? (nblk - wave + 3) / 4 : 0;  // blocks wave, wave + 4, ...
+    // this wave's blocks: their C bits and operand row bits (uniform)
+    unsigned long long ablk[NBW], bblk[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+        const int bt = wave + 4 * i;
+        unsigned long long cb = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (t < args.nbt && ((bt >> t) & 1)) cb |= 1ull << args.tbit[t];
+        ablk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.arun, args.nar));
+        bblk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.brun, args.nbr));
+    }
+    // T bits 8..11 of the write-out index (uniform per iteration)
+    unsigned hdst[4];
+    unsigned long long hoff[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        hdst[q] = 8 + q < args.nt ? 1u << args.tdst[8 + q] : 0u;
+        hoff[q] = 8 + q < args.nt ? 1ull << args.tpos[8 + q] : 0ull;
+    }
+    const unsigned ne = 1u << args.nt;
+    const unsigned nit = ne > 256u ? ne >> 8 : 1u;
+    const unsigned long long tiles = 1ull << (args.rc - args.nt);
+    const unsigned G = gridDim.x;
+    const unsigned lb = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
+    T av[NBW][KG], bv[NBW][KG];
+    // operands of tile wt, issued one tile ahead so that their latency
+    // overlaps the previous tile's write-out
+    auto load_tile = [&](unsigned long long wt) {
+        const unsigned long long ab = apply_runs<STREAM2_LRUNS>(wt, args.warun, args.nwarun);
+        const unsigned long long bb = apply_runs<STREAM2_LRUNS>(wt, args.wbrun, args.nwbrun);
+#pragma unroll
+        for (int i = 0; i < NBW; ++i)
+            if (i < mine) {
+                load_row<T, KG>(A + ((((ab | ablk[i]) | aR) << NK) + g * KG), av[i]);
+                load_row<T, KG>(B + ((((bb | bblk[i]) | bC) << NK) + g * KG), bv[i]);
+            }
+    };
+    double vmax = 0.0;
+    if (lb < tiles) load_tile(lb);
+    for (unsigned long long wt = lb; wt < tiles; wt += G) {
+        const unsigned long long base = apply_runs<STREAM2_LRUNS>(wt, args.wrun, args.nwrun);
+#pragma unroll
+        for (int i = 0; i < NBW; ++i)
+            if (i < mine) {
+                const int bt = wave + 4 * i;
+                acc_t acc = {};
+#pragma unroll
+                for (int st = 0; st < KG; ++st) acc = Mfma<T>::step(av[i][st], bv[i][st], acc);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = Mfma<T>::out_row(g, v);
+                    tile[(bt << 8) | (m << 4) | (l16 ^ m ^ bt)] = acc[v];
+                }
+            }
+        if (wt + G < tiles) load_tile(wt + G);
+        __syncthreads();
+        for (unsigned it = 0; it < nit; ++it) {
+            unsigned li = lds_lo;
+            unsigned long long off = base | off_lo;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if ((it >> q) & 1u) {
+                    li |= hdst[q];
+                    off |= hoff[q];
+                }
+            if (threadIdx.x < ne) {
+                // columns are stored XOR-ed with row and block (fewer bank
+                // conflicts whichever of them the lanes walk)
+                li ^= ((li >> 4) ^ (li >> 8)) & 15u;
+                const T v = (T)ldexp((double)tile[li], se);
+                C[off] = v;
+                vmax = fmax(vmax, fabs((double)v));
+            }
+        }
+        __syncthreads();
+    }
+    publish_max_block(meta, args.tc, vmax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ta].exp + meta[args.tb].exp + sA + sB;
+}
+
+// Arguments of k_stream_mfma for a node, if it fits (K of 16 or 32, at
+// least min_bits row and column bits, run lists that fit).  Measured on the
+// sliced banded formula (FP64 / FP32 solves/s): min_bits 2: 9.27 / 14.0,
+// 3: 9.41 / 14.2, 4: 9.25 / 14.1; the register-tiled kernels alone: 7.83 /
+// 13.4.  Nodes with fewer row or column bits keep the register-tiled path.
+static inline bool stream_mfma_args(const NodeDesc &d, StreamMfmaArgs *a, int min_bits = 3) {
+    if (d.nk < 4 || d.nk > 5 || d.rc < 8 || d.rc > 62) return false;
+    if (d.nra > STREAM2_RUNS || d.nrb > STREAM2_RUNS) return false;
+    std::vector<int> inA((size_t)d.rc, 0), inB((size_t)d.rc, 0);
+    for (int q = 0; q < d.nra; ++q)
+        for (unsigned j = 0; j < ((d.ra[q] >> 8) & 255u); ++j) inA[(size_t)((d.ra[q] & 255u) + j)] = 1;
+    for (int q = 0; q < d.nrb; ++q)
+        for (unsigned j = 0; j < ((d.rb[q] >> 8) & 255u); ++j) inB[(size_t)((d.rb[q] & 255u) + j)] = 1;
+    int nmu = 0, nnu = 0;
+    for (int p = 0; p < d.rc; ++p) {
+        nmu += inA[(size_t)p] && !inB[(size_t)p];
+        nnu += inB[(size_t)p] && !inA[(size_t)p];
+    }
+    if (nmu < min_bits || nnu < min_bits) return false;
+    std::memset(a, 0, sizeof *a);
+    std::vector<int> inT((size_t)d.rc, 0);
+    // rows and columns: the one-operand bits among C's four lowest first,
+    // then the lowest others; block bits: the lowest batch bits, up to 16
+    // blocks (8 for K = 32), so that a tile's fixed costs spread over up to
+    // 4096 outputs
+    for (int pass = 0; pass < 2; ++pass)
+        for (int p = 0; p < d.rc; ++p) {
+            if (inT[(size_t)p] || (pass == 0) != (p < 4)) continue;
+            if (inA[(size_t)p] && !inB[(size_t)p] && a->nrb < 4) {
+                a->rbit[a->nrb++] = p;
+                inT[(size_t)p] = 1;
+            } else if (inB[(size_t)p] && !inA[(size_t)p] && a->ncb < 4) {
+                a->cbit[a->ncb++] = p;
+                inT[(size_t)p] = 1;
+            } else if (inA[(size_t)p] && inB[(size_t)p] && a->nbt < (d.nk == 4 ? 4 : 3)) {
+                a->tbit[a->nbt++] = p;
+                inT[(size_t)p] = 1;
+            }
+        }
+    for (int p = 0; p < 4 && p < d.rc; ++p)
+        if (!inT[(size_t)p]) return false;
+    for (int p = 0; p < d.rc; ++p)
+        if (inT[(size_t)p]) {
+            int dst = -1;
+            for (int t = 0; t < a->nrb; ++t) if (a->rbit[t] == p) dst = 4 + t;
+            for (int t = 0; t < a->ncb; ++t) if (a->cbit[t] == p) dst = t;
+            for (int t = 0; t < a->nbt; ++t) if (a->tbit[t] == p) dst = 8 + t;
+            a->tpos[a->nt] = p;
+            a->tdst[a->nt] = dst;
+            ++a->nt;
+        }
+    // tile index -> the other C bits: one-operand bits first, then batch
+    std::vector<int> order;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int p = 0; p < d.rc; ++p)
+            if (!inT[(size_t)p] && ((inA[(size_t)p] != inB[(size_t)p]) == (pass == 0))) order.push_back(p);
+    int nw = 0;
+    for (size_t t = 0; t < order.size();) {
+        size_t e = t + 1;
+        while (e < order.size() && order[e] == order[e - 1] + 1) ++e;
+        if (nw >= STREAM2_LRUNS) return false;
+        a->wrun[nw++] = WMC_RUN(t, e - t, order[t]);
+        t = e;
+    }
+    a->nwrun = nw;
+    // the same tile bits as operand row bits, through the operands' run lists
+    auto compose = [&](const unsigned *oruns, int nor, unsigned *runs, int *nruns) {
+        auto row_bit = [&](int p) {
+            for (int q = 0; q < nor; ++q) {
+                const int src = (int)(oruns[q] & 255u), len = (int)((oruns[q] >> 8) & 255u);
+                if (p >= src && p < src + len) return (int)(oruns[q] >> 16) + (p - src);
+            }
+            return -1;
+        };
+        int n = 0;
+        for (size_t t = 0; t < order.size();) {
+            const int r0 = row_bit(order[t]);
+            if (r0 < 0) {
+                ++t;
+                continue;
+            }
+            size_t e = t + 1;
+            while (e < order.size() && row_bit(order[e]) == r0 + (int)(e - t)) ++e;
+            if (n >= STREAM2_LRUNS) return false;
+            runs[n++] = WMC_RUN(t, e - t, r0);
+            t = e;
+        }
+        *nruns = n;
+        return true;
+    };
+    if (!compose(d.ra, d.nra, a->warun, &a->nwarun) || !compose(d.rb, d.nrb, a->wbrun, &a->nwbrun)) return false;
+    a->a = d.a;
+    a->b = d.b;
+    a->c = d.c;
+    a->ta = d.ta;
+    a->tb = d.tb;
+    a->tc = d.tc;
+    a->rc = d.rc;
+    a->nar = d.nra;
+    a->nbr = d.nrb;
+    for (int q = 0; q < d.nra; ++q) a->arun[q] = d.ra[q];
+    for (int q = 0; q < d.nrb; ++q) a->brun[q] = d.rb[q];
+    return true;
+}
+
+template <typename T>
+static void launch_stream_mfma(const StreamMfmaArgs &a, int nk, T *arena, wmc_meta *meta, hipStream_t st,
+                               unsigned cap = 2048) {
+    const unsigned long long tiles = 1ull << (a.rc - a.nt);
+    unsigned long long blocks = tiles < cap ? tiles : cap;
+    if (blocks >= 64) blocks &= ~7ull;  // whole XCD rounds
+    const dim3 g((unsigned)blocks), b(256);
+    if (nk == 4) hipLaunchKernelGGL((k_stream_mfma<T, 4>), g, b, 0, st, a, arena, meta);
+    else hipLaunchKernelGGL((k_stream_mfma<T, 5>), g, b, 0, st, a, arena, meta);
+}
+
 // Lanes per summed-index group for a single-node streaming launch (0: one
-// lane per output tile).  Measured on the sliced banded formula: FP64
-// nodes with K >= 16 gain from groups of 4 (7.04 -> 7.82 solves/s; groups
-// of 8: 7.26); FP32 (rows of 64 bytes) and K = 8 lose (FP32 13.3 -> 11.7,
+// lane per output tile), for nodes the matrix-core streaming kernel does not
+// take.  Measured on the sliced banded formula with every K >= 16 node on
+// this path: FP64 gains from groups of 4 (7.04 -> 7.82 solves/s; groups of
+// 8: 7.26); FP32 (rows of 64 bytes) and K = 8 lose (FP32 13.3 -> 11.7,
 // K = 8 with groups of 4: 2.93 -> 2.70).
 template <typename T>
 static inline int stream2_split_lanes(int nk) {
