@@ -1328,6 +1328,7 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
 // workgroup covers STREAM2_MULTI_THREADS consecutive threads of its node.
 // Tasks of one launch share NK.
 #define STREAM2_MULTI_THREADS 1024
+#define STREAM2_MULTI_LRUNS 4  // thread-index runs a merged-step task may use
 #define WMC_STREAM_MIN_RANK 12  // merged-step nodes with at least 2^12 outputs stream
 
 struct StreamTask {
@@ -1384,7 +1385,7 @@ __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restri
     const unsigned long long u1 = u0 + STREAM2_MULTI_THREADS < threads ? u0 + STREAM2_MULTI_THREADS : threads;
     double vmax = 0.0;
     for (unsigned long long u = u0 + threadIdx.x; u < u1; u += 256) {
-        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);
+        const unsigned long long r0 = apply_runs<STREAM2_MULTI_LRUNS>(u, args.lrun, args.nlrun);
         const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
         const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
         double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
@@ -1417,7 +1418,8 @@ __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restri
 
 static inline bool stream_task(const NodeDesc &d, StreamTask *t) {
     std::memset(t, 0, sizeof *t);
-    if (d.nk > 3 || !stream2_args(d, &t->a, 1, 10)) return false;
+    // threads in C order: at most three runs around the two looped bits
+    if (d.nk > 3 || !stream2_args(d, &t->a, 1, 10) || t->a.nlrun > STREAM2_MULTI_LRUNS) return false;
     t->a.o_lds = 0;
     return true;
 }
