@@ -149,6 +149,28 @@ typedef struct {
 } wmc_plan_info;
 
 wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *opts, wmc_plan_t **out);
+
+/* Elimination order from a tree decomposition of the formula's primal graph
+ * (tree decompositions and their width as defined in Section 2; used the way
+ * variable elimination uses them, which Section 3 sets beside FactorTree).
+ *   td:       NUL-terminated text in the PACE ".td" format, host memory:
+ *             "s td <bags> <max bag size> <vertices>", then "b <id> <v...>"
+ *             lines (bag ids 1..bags, vertices = the caller's variables
+ *             1..n_vars) and "<id> <id>" tree edges; lines starting with 'c'
+ *             are comments.
+ *   root_bag: bag to root the tree at (1-based; 0 = bag 1).
+ *   order:    n_vars entries out (host), a permutation of 1..n_vars to pass
+ *             as WMC_TREE_ORDER: variables in no bag first, then each
+ *             variable at its bag nearest the root, bags children first.
+ *   width:    out (may be NULL): the decomposition's width, max |bag| - 1.
+ * With this order no bucket spans more variables than one bag holds, so a
+ * plan built from it (block 1) has storage rank at most width + 1.
+ * WMC_ERR_INVALID_ARGUMENT if the text is malformed, the vertex count is not
+ * n_vars, the bags do not form a tree, a variable's bags are not connected,
+ * or no bag holds all caller variables of some clause (message in
+ * wmc_last_error()); nothing is written to order then. */
+wmc_status wmc_order_from_td(const wmc_network *net, const char *td, int64_t root_bag, int32_t *order,
+                             int32_t *width);
 wmc_status wmc_plan_stats(const wmc_plan_t *plan, wmc_plan_info *out);
 void wmc_plan_destroy(wmc_plan_t *plan);
 

@@ -93,6 +93,7 @@ def lib():
             "wmc_network_info": [P, P, P],
             "wmc_plan": [P, ctypes.POINTER(wmc_plan_options), P],
             "wmc_plan_stats": [P, ctypes.POINTER(wmc_plan_info)],
+            "wmc_order_from_td": [P, ctypes.c_char_p, i64, P, P],
             "wmc_plan_tensor": [P, i64, P, P, P, P],
             "wmc_plan_node": [P, i64, P, P, P, P],
             "wmc_plan_image": [P, P, u64, P, P],
@@ -185,6 +186,16 @@ class Network:
 
 def wmc_build_network(n, clauses, weights) -> Network:
     return Network(n, clauses, weights)
+
+
+def order_from_td(net: Network, td: str, root_bag: int = 0):
+    """wmc_order_from_td: (elimination order over 1..n, width) from a tree
+    decomposition of the primal graph given as PACE .td text; pass the order
+    to Plan(net, kind="order", order=...)."""
+    order = np.zeros(max(net.n, 1), dtype=np.int32)
+    width = ctypes.c_int32()
+    _check(lib().wmc_order_from_td(net._h, td.encode(), int(root_bag), _p(order), ctypes.byref(width)))
+    return order[: net.n], width.value
 
 
 # ---------------------------------------------------------------------------

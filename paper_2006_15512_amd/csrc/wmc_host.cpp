@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <new>
 #include <numeric>
 #include <string>
@@ -1352,5 +1354,147 @@ extern "C" wmc_status wmc_plan_launches(const wmc_plan_t *plan, double *bytes, d
         if (flops) flops[k] = F[(size_t)k];
         if (cls) cls[k] = C[(size_t)k];
     }
+    return WMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Elimination order from a tree decomposition of the primal graph (the
+// decompositions of Section 2; the variable-elimination use of them that
+// Section 3 contrasts with FactorTree).  Rooted at root_bag, every variable
+// is eliminated at its top bag (the bag of least depth holding it), bags
+// taken children first.  When x is eliminated, every variable that shares
+// an original or fill edge with x and is still open lies in x's top bag:
+// such a variable shares a bag with x, and its bags form a connected
+// subtree that is not entirely below the top bag (else it would be gone
+// already), so the subtree passes through the top bag.  The bucket of x
+// therefore spans at most the top bag's size.
+extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, int64_t root_bag,
+                                        int32_t *order, int32_t *width) {
+    if (!net || !td || !order) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: NULL argument");
+    const int32_t n = net->n_user;
+    long long nb = -1, nv = -1;
+    std::vector<std::vector<int32_t>> bags;
+    std::vector<std::pair<long long, long long>> edges;
+    const char *p = td;
+    long long line = 0;
+    while (*p) {
+        const char *e = p;
+        while (*e && *e != '\n') ++e;
+        std::string s(p, (size_t)(e - p));
+        p = *e ? e + 1 : e;
+        ++line;
+        size_t i = s.find_first_not_of(" \t\r");
+        if (i == std::string::npos || s[i] == 'c') continue;
+        if (s[i] == 's') {
+            long long w = 0;
+            if (nb >= 0 || std::sscanf(s.c_str() + i, "s td %lld %lld %lld", &nb, &w, &nv) != 3 || nb < 0 || nv < 0)
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad solution line %lld", line);
+            if (nv != n)
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: %lld vertices, the formula has %d variables",
+                         nv, (int)n);
+            bags.assign((size_t)nb, {});
+            continue;
+        }
+        if (nb < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: line %lld before the 's td' line", line);
+        const char *q = s.c_str() + i;
+        char *end = nullptr;
+        if (s[i] == 'b') {
+            ++q;
+            const long long id = std::strtoll(q, &end, 10);
+            if (end == q || id < 1 || id > nb)
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad bag id on line %lld", line);
+            std::vector<int32_t> &B = bags[(size_t)(id - 1)];
+            for (q = end;;) {
+                const long long v = std::strtoll(q, &end, 10);
+                if (end == q) break;
+                if (v < 1 || v > n)
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: vertex %lld out of range on line %lld", v,
+                             line);
+                B.push_back((int32_t)v);
+                q = end;
+            }
+            std::sort(B.begin(), B.end());
+            B.erase(std::unique(B.begin(), B.end()), B.end());
+        } else {
+            const long long a = std::strtoll(q, &end, 10);
+            const char *q2 = end;
+            const long long b = std::strtoll(q2, &end, 10);
+            if (end == q2 || a < 1 || a > nb || b < 1 || b > nb || a == b)
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad edge on line %lld", line);
+            edges.push_back({a - 1, b - 1});
+        }
+    }
+    if (nb < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: no 's td' line");
+    if (nb == 0 && n > 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: no bags");
+    if ((long long)edges.size() != (nb > 0 ? nb - 1 : 0))
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: %zu edges for %lld bags (not a tree)", edges.size(), nb);
+    // breadth-first order from the root: parents before children
+    std::vector<std::vector<int64_t>> adj((size_t)nb);
+    for (auto &e : edges) {
+        adj[(size_t)e.first].push_back(e.second);
+        adj[(size_t)e.second].push_back(e.first);
+    }
+    const int64_t root = root_bag > 0 ? root_bag - 1 : 0;
+    if (nb > 0 && (root < 0 || root >= nb)) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad root bag");
+    std::vector<int64_t> bfs, par((size_t)nb, -2);
+    if (nb > 0) {
+        bfs.push_back(root);
+        par[(size_t)root] = -1;
+    }
+    for (size_t h = 0; h < bfs.size(); ++h)
+        for (int64_t c : adj[(size_t)bfs[h]])
+            if (par[(size_t)c] == -2) {
+                par[(size_t)c] = bfs[h];
+                bfs.push_back(c);
+            }
+    if ((long long)bfs.size() != nb) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bags not connected");
+    // each variable's bags must form a subtree (bags holding it minus tree
+    // edges joining two of them = 1)
+    std::vector<int64_t> top((size_t)n + 1, -1), nbags((size_t)n + 1, 0), nedges((size_t)n + 1, 0);
+    std::vector<std::vector<int64_t>> bags_of((size_t)n + 1);
+    for (int64_t b : bfs)
+        for (int32_t v : bags[(size_t)b]) {
+            if (top[(size_t)v] < 0) top[(size_t)v] = b;
+            ++nbags[(size_t)v];
+            bags_of[(size_t)v].push_back(b);
+        }
+    for (auto &e : edges) {
+        const std::vector<int32_t> &A = bags[(size_t)e.first], &B = bags[(size_t)e.second];
+        std::vector<int32_t> both;
+        std::set_intersection(A.begin(), A.end(), B.begin(), B.end(), std::back_inserter(both));
+        for (int32_t v : both) ++nedges[(size_t)v];
+    }
+    for (int32_t v = 1; v <= n; ++v)
+        if (nbags[(size_t)v] > 0 && nedges[(size_t)v] != nbags[(size_t)v] - 1)
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bags of variable %d are not connected", (int)v);
+    // every clause (its caller variables) inside one bag
+    for (size_t c = 0; c < net->clauses.size(); ++c) {
+        std::vector<int32_t> vs;
+        for (int32_t v : net->clauses[c].vars)
+            if (v <= n) vs.push_back(v);
+        if (vs.empty()) continue;
+        int32_t lead = vs[0];
+        for (int32_t v : vs)
+            if (nbags[(size_t)v] < nbags[(size_t)lead]) lead = v;
+        bool ok = false;
+        for (int64_t b : bags_of[(size_t)lead]) {
+            const std::vector<int32_t> &B = bags[(size_t)b];
+            ok = std::includes(B.begin(), B.end(), vs.begin(), vs.end());
+            if (ok) break;
+        }
+        if (!ok) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: no bag holds the variables of clause %zu", c);
+    }
+    // variables in no bag (in no clause) first, then bags children first
+    size_t k = 0;
+    for (int32_t v = 1; v <= n; ++v)
+        if (top[(size_t)v] < 0) order[k++] = v;
+    int32_t wmax = 0;
+    for (size_t h = bfs.size(); h-- > 0;) {
+        const int64_t b = bfs[h];
+        wmax = std::max(wmax, (int32_t)bags[(size_t)b].size() - 1);
+        for (int32_t v : bags[(size_t)b])
+            if (top[(size_t)v] == b) order[k++] = v;
+    }
+    if (width) *width = wmax;
     return WMC_OK;
 }
