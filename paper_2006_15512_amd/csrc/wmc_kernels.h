@@ -687,6 +687,7 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
     // summed entries per register chunk: 8 for K >= 16 (fewer dependent
     // load rounds; measured 11-15% faster than 4 on the banded formula)
     constexpr int KC = K < 4 ? K : (NK >= 4 ? 8 : 4);
+    constexpr int CHUNK_UNROLL = NK >= 4 ? 1 : 8;
     constexpr int P = 1 << NP, Q = 1 << NQ;
     const int sS = scale_exp(meta[args.ts].maxbits);
     const int sO = scale_exp(meta[args.to].maxbits);
@@ -735,7 +736,7 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
         // K >= 16: the chunk loop stays rolled, so only one chunk's rows
         // are in registers (fully unrolled, the loads of every chunk were
         // hoisted: 256+ registers, one wave per SIMD)
-#pragma unroll (NK >= 4 ? 1 : 8)
+#pragma unroll CHUNK_UNROLL
         for (int kc = 0; kc < K; kc += KC) {
             double sv[P][KC], ov[Q][KC];
 #pragma unroll
