@@ -1028,6 +1028,10 @@ __device__ __forceinline__ void load_row(const T *__restrict__ p, T *v) {
     }
 }
 
+// Two neighbouring outputs with one store (p is 2-element aligned).
+__device__ __forceinline__ void store_pair(double *p, double a, double b) { *(double2 *)p = make_double2(a, b); }
+__device__ __forceinline__ void store_pair(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
+
 template <typename T, int NK>
 __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, T *__restrict__ arena,
                                                      wmc_meta *meta) {
@@ -1052,14 +1056,17 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
     const unsigned long long aR = apply_runs<STREAM2_RUNS>(rowc, args.arun, args.nar);
     const unsigned long long bC = apply_runs<STREAM2_RUNS>(colc, args.brun, args.nbr);
     // write-out: element e of the tile (T bits ascending) sits at LDS index
-    // lds(e) and C offset off(e); the low 8 bits of e are this thread's
+    // lds(e) and C offset off(e).  T's lowest bit is C bit 0, so elements
+    // 2p and 2p + 1 are neighbours in C: a thread stores such a pair with
+    // one instruction; bits 1..8 of e are this thread's
     unsigned lds_lo = 0;
     unsigned long long off_lo = 0;
-    for (int q = 0; q < args.nt && q < 8; ++q)
-        if ((threadIdx.x >> q) & 1) {
+    for (int q = 1; q < args.nt && q < 9; ++q)
+        if ((threadIdx.x >> (q - 1)) & 1) {
             lds_lo |= 1u << args.tdst[q];
             off_lo |= 1ull << args.tpos[q];
         }
+    const unsigned lds_pair = 1u << args.tdst[0];
     const int nblk = 1 << args.nbt;
     const int mine = nblk > wave ? (nblk - wave + 3) / 4 : 0;  // blocks wave, wave + 4, ...
     // this wave's blocks: their C bits and operand row bits (uniform)
@@ -1074,16 +1081,16 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
         ablk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.arun, args.nar));
         bblk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.brun, args.nbr));
     }
-    // T bits 8..11 of the write-out index (uniform per iteration)
-    unsigned hdst[4];
-    unsigned long long hoff[4];
+    // T bits 9..11 of the write-out index (uniform per iteration)
+    unsigned hdst[3];
+    unsigned long long hoff[3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        hdst[q] = 8 + q < args.nt ? 1u << args.tdst[8 + q] : 0u;
-        hoff[q] = 8 + q < args.nt ? 1ull << args.tpos[8 + q] : 0ull;
+    for (int q = 0; q < 3; ++q) {
+        hdst[q] = 9 + q < args.nt ? 1u << args.tdst[9 + q] : 0u;
+        hoff[q] = 9 + q < args.nt ? 1ull << args.tpos[9 + q] : 0ull;
     }
-    const unsigned ne = 1u << args.nt;
-    const unsigned nit = ne > 256u ? ne >> 8 : 1u;
+    const unsigned npair = 1u << (args.nt - 1);
+    const unsigned nit = npair > 256u ? npair >> 8 : 1u;
     const unsigned long long tiles = 1ull << (args.rc - args.nt);
     const unsigned G = gridDim.x;
     const unsigned lb = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
@@ -1123,18 +1130,21 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
             unsigned li = lds_lo;
             unsigned long long off = base | off_lo;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 3; ++q)
                 if ((it >> q) & 1u) {
                     li |= hdst[q];
                     off |= hoff[q];
                 }
-            if (threadIdx.x < ne) {
+            if (threadIdx.x < npair) {
                 // columns are stored XOR-ed with row and block (fewer bank
                 // conflicts whichever of them the lanes walk)
+                unsigned l1 = li | lds_pair;
                 li ^= ((li >> 4) ^ (li >> 8)) & 15u;
-                const T v = (T)ldexp((double)tile[li], se);
-                C[off] = v;
-                vmax = fmax(vmax, fabs((double)v));
+                l1 ^= ((l1 >> 4) ^ (l1 >> 8)) & 15u;
+                const T v0 = (T)ldexp((double)tile[li], se);
+                const T v1 = (T)ldexp((double)tile[l1], se);
+                store_pair(C + off, v0, v1);
+                vmax = fmax(vmax, fmax(fabs((double)v0), fabs((double)v1)));
             }
         }
         __syncthreads();
