@@ -39,6 +39,7 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
     const LeafDesc *L = (const LeafDesc *)(ws + P.off_leaf);
     const NodeDesc *D = (const NodeDesc *)(ws + P.off_node);
     const GemmDesc *Gd = (const GemmDesc *)(ws + P.off_gemm);
+    const int *TB = (const int *)(ws + P.off_tab);
     T *arena = (T *)(ws + P.off_arena);
     const int nt = (int)P.T.size();
     for (long long eta = b; eta < e; ++eta) {
@@ -52,7 +53,7 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
         if (!P.leaves.empty())
             hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(P.leaf_work)), dim3(WMC_BLOCK), 0, st, L,
                                (int)P.leaves.size(), (long long)P.leaf_work, w, arena, meta,
-                               (unsigned long long)eta);
+                               (unsigned long long)eta, P.leaf_tab >= 0 ? TB + P.leaf_tab : nullptr);
         if (tm) tm->mark();
         for (size_t k = 1; k < P.launches.size(); ++k) {
             const Launch &Ln = P.launches[k];
@@ -69,7 +70,8 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
                                       stream2_split_lanes<T>(P.nodes[(size_t)Ln.first].nk))) {
             } else
                 hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first,
-                                   Ln.count, (long long)Ln.work, arena, meta);
+                                   Ln.count, (long long)Ln.work, arena, meta,
+                                   P.tab_off[k] >= 0 ? TB + P.tab_off[k] : nullptr);
             if (tm) tm->mark();
         }
         hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(1), 0, st, arena, (long long)P.T[(size_t)P.root].off, meta,

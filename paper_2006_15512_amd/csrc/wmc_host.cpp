@@ -1129,6 +1129,34 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     off += align_up(sizeof(NodeDesc) * (uint64_t)std::max<size_t>(P.nodes.size(), 1), 256);
     P.off_gemm = off;
     off += align_up(sizeof(GemmDesc) * (uint64_t)std::max<size_t>(P.gemms.size(), 1), 256);
+    // wave -> leaf and wave -> node tables, so the batched leaf and
+    // small-node kernels find their item with one load instead of a
+    // dependent binary search; only launches of several nodes need one
+    std::vector<int32_t> tabs;
+    if (P.leaves.size() > 1) {
+        P.leaf_tab = 0;
+        tabs.assign((size_t)(P.leaf_work / WMC_WAVE), 0);
+        for (size_t q = 0; q < P.leaves.size(); ++q) {
+            const int64_t b = P.leaves[q].work_begin / WMC_WAVE;
+            const int64_t e = b + (int64_t)(((1ull << P.leaves[q].rank) + WMC_WAVE - 1) / WMC_WAVE);
+            for (int64_t x = b; x < e; ++x) tabs[(size_t)x] = (int32_t)q;
+        }
+    }
+    P.tab_off.assign(P.launches.size(), -1);
+    for (size_t k = 1; k < P.launches.size(); ++k) {
+        const Launch &Ln = P.launches[k];
+        if (Ln.type == LAUNCH_GEMM || Ln.count < 2) continue;
+        P.tab_off[k] = (int64_t)tabs.size();
+        tabs.resize(tabs.size() + (size_t)(Ln.work / WMC_WAVE), 0);
+        for (int32_t q = 0; q < Ln.count; ++q) {
+            const NodeDesc &d = P.nodes[(size_t)(Ln.first + q)];
+            const int64_t b = d.work_begin / WMC_WAVE;
+            const int64_t e = b + (int64_t)(((1ull << d.rc) + WMC_WAVE - 1) / WMC_WAVE);
+            for (int64_t x = b; x < e; ++x) tabs[(size_t)(P.tab_off[k] + x)] = q;
+        }
+    }
+    P.off_tab = off;
+    off += align_up(sizeof(int32_t) * (uint64_t)std::max<size_t>(tabs.size(), 1), 256);
     P.off_arena = off;
     P.desc_bytes = P.off_arena - P.off_leaf;
     P.desc_image.assign(P.desc_bytes, 0);
@@ -1137,6 +1165,8 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
         std::memcpy(P.desc_image.data() + (P.off_node - P.off_leaf), P.nodes.data(), sizeof(NodeDesc) * P.nodes.size());
     if (!P.gemms.empty())
         std::memcpy(P.desc_image.data() + (P.off_gemm - P.off_leaf), P.gemms.data(), sizeof(GemmDesc) * P.gemms.size());
+    if (!tabs.empty())
+        std::memcpy(P.desc_image.data() + (P.off_tab - P.off_leaf), tabs.data(), sizeof(int32_t) * tabs.size());
     P.workspace_bytes = P.off_arena + align_up(P.arena_bytes, 256);
 
     // ---- statistics

@@ -74,7 +74,12 @@ struct wmc_plan_t {
     std::vector<GemmDesc> gemms;
     int64_t leaf_work = 0;
     // workspace layout (bytes)
-    uint64_t off_acc = 0, off_w = 0, off_meta = 0, off_leaf = 0, off_node = 0, off_gemm = 0, off_arena = 0;
+    uint64_t off_acc = 0, off_w = 0, off_meta = 0, off_leaf = 0, off_node = 0, off_gemm = 0, off_tab = 0,
+             off_arena = 0;
+    // wave -> leaf / node lookup tables (ints at off_tab): entry offset of
+    // the leaf table and of each launch's table, -1 where the kernel searches
+    int64_t leaf_tab = -1;
+    std::vector<int64_t> tab_off;
     uint64_t desc_bytes = 0;          // contiguous [off_leaf, off_arena) image
     std::vector<uint8_t> desc_image;
     uint64_t arena_bytes = 0, workspace_bytes = 0;
