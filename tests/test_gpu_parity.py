@@ -305,6 +305,21 @@ def test_banded_medium_stream_shapes(seed):
         assert rel(value_fraction(v), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("seed", [2, 3, 4, 5])
+def test_banded_medium_k32_blocks_fp32(seed):
+    """Scaled FP32 on min-fill orders in blocks of 5: streaming nodes with 32
+    summed entries and short matrices per batch value (the matrix-core
+    streaming kernel at K = 32, rows or columns repeated where a side has
+    only 3 bits) against the oracle."""
+    f = wl.banded_3cnf(120, 400, 24, seed=seed)
+    m, e = oracle.bucket(f)
+    ref = Fraction(m) * Fraction(2) ** e
+    assert ref > 0
+    say(f"banded120 fp32 k32 seed={seed}")
+    v, _ = run(f, kind="order", order=oracle.minfill_order(f), block=5, precision="fp32")
+    assert rel(value_fraction(v), ref) <= 1e-5
+
+
 # ------------------------------------------------------------------ long clauses
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_long_clauses_vs_brute(precision, tol):
