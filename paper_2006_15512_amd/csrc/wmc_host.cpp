@@ -1422,6 +1422,12 @@ extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, 
             if (nv != n)
                 WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: %lld vertices, the formula has %d variables",
                          nv, (int)n);
+            // a tree of nb bags needs nb - 1 edge lines: more bags than
+            // characters cannot be a well-formed file (and would only
+            // allocate)
+            if (nb > (long long)std::strlen(td))
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: %lld bags in a text of %zu bytes", nb,
+                         std::strlen(td));
             bags.assign((size_t)nb, {});
             continue;
         }

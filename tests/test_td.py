@@ -99,6 +99,7 @@ def test_isolated_variables_come_first():
     ("s td 2 2 3\nb 1 1 2\nb 2 3\n1 2\n", "clause"),
     ("s td 2 2 3\nb 1 1 2 7\nb 2 2 3\n1 2\n", "out of range"),
     ("s td 2 2 3\nb 1 1 2\nb 2 2 3\n1 1\n", "bad edge"),
+    ("s td 1000000000000 2 3\nb 1 1 2\n", "bags in a text"),
 ])
 def test_malformed_decompositions_rejected(td, what):
     f = wl.Formula(3, [[1, 2], [2, 3]], np.full((3, 2), 0.5))
