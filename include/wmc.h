@@ -116,10 +116,24 @@ typedef struct {
                                 i-n), n+m..2(n+m)-2 are internal; every internal vertex has
                                 exactly two children. */
     int64_t n_tree_nodes;    /* = 2(n+m)-1 */
-    uint64_t mem_cap_bytes;  /* Algorithm 3 bound m on the peak live tensor bytes; 0 = none */
+    uint64_t mem_cap_bytes;  /* Algorithm 3 bound m on MemCost, the bytes of the tensor arena
+                                one slice occupies as placed (every tensor 256-byte aligned);
+                                0 = none.  Met exactly: wmc_plan_info.arena_bytes <= m, or
+                                WMC_ERR_CAP_UNREACHABLE. */
     int32_t rank_cap;        /* bound on the largest storage rank; 0 = none */
-    int32_t reserved[7];
+    int32_t slice_objective; /* wmc_slice_objective: how ChooseSliceIndex picks the next variable */
+    int32_t reserved[6];
 } wmc_plan_options;
+
+/* Choice of the next sliced variable (Algorithm 3's ChooseSliceIndex, over
+ * the variables of the tensors within one of the largest rank):
+ *  WMC_SLICE_BY_MEMORY: least MemCost after slicing it, ties by flops (the
+ *    paper's greedy memory criterion);
+ *  WMC_SLICE_BY_FLOPS: among the variables that bring the plan closer to the
+ *    caps, least total flops over all slices (the alternative heuristics the
+ *    slicing section leaves open); afterwards sliced variables the caps no
+ *    longer need are dropped, last added first. */
+typedef enum { WMC_SLICE_BY_MEMORY = 0, WMC_SLICE_BY_FLOPS = 1 } wmc_slice_objective;
 
 /* Node classes of the histogram in wmc_plan_info. */
 enum { WMC_CLASS_SMALL = 0, WMC_CLASS_STREAM = 1, WMC_CLASS_GEMM = 2, WMC_N_CLASSES = 4 };
@@ -138,8 +152,9 @@ typedef struct {
     int32_t sliced_vars[WMC_MAX_SLICED];
     double flops_per_slice;     /* sum over nodes of 2*b*m*n*k */
     double bytes_per_slice;     /* sum over nodes of elem_size*(|A|+|B|+|C|) */
-    double peak_live_bytes;     /* MemCost: peak of live tensor bytes over the schedule */
-    uint64_t arena_bytes;       /* static arena after placement */
+    double peak_live_bytes;     /* peak of live tensor bytes (256-byte aligned) over the executed
+                                   schedule: a lower bound on arena_bytes */
+    uint64_t arena_bytes;       /* static arena after placement (MemCost, what mem_cap bounds) */
     uint64_t workspace_bytes;   /* device workspace wmc_contract needs */
     int64_t class_hist[WMC_N_CLASSES];
     int64_t n_launches;         /* kernel launches per slice */
@@ -252,6 +267,23 @@ wmc_status wmc_plan_launches(const wmc_plan_t *plan, double *bytes, double *flop
 wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double *weights, void *workspace,
                                 uint64_t workspace_bytes, void *stream, float *ms, int64_t cap,
                                 wmc_value *out);
+
+/* Kernel family of each launch of one slice, in the order of
+ * wmc_plan_launches (for attributing measured time to kernels).  Host only;
+ * the matrix-kernel choice reads the current device's LDS size.  With
+ * kernel == NULL it only reports *n_out. */
+enum {
+    WMC_KERNEL_BEGIN = 0,         /* k_begin: meta reset */
+    WMC_KERNEL_LEAVES = 1,        /* k_leaves: clause and weight tables of a slice */
+    WMC_KERNEL_NODES = 2,         /* k_nodes: batched small nodes */
+    WMC_KERNEL_GEMM_P = 3,        /* k_gemm_p: persistent MFMA matrix node */
+    WMC_KERNEL_GEMM = 4,          /* k_gemm: chunked MFMA matrix node */
+    WMC_KERNEL_STREAM_MFMA = 5,   /* k_stream_mfma: streaming node on 16x16 MFMA blocks */
+    WMC_KERNEL_STREAM2 = 6,       /* k_stream2: register-tiled streaming node */
+    WMC_KERNEL_STREAM2_SPLIT = 7, /* k_stream2_split: summed index split over lane groups */
+    WMC_KERNEL_FINISH = 8         /* k_finish: slice accumulation */
+};
+wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, int64_t cap, int64_t *n_out);
 
 /* ------------------------------------------------------------------ */
 /* Batches: many planned networks contracted in shared launches         */

@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAP_UNRE
                 4: "DEVICE", 5: "BUSY", 6: "UNSUPPORTED"}
 FP64, FP32_SCALED = 0, 1
 TREE_MINFILL, TREE_ORDER, TREE_EXPLICIT = 0, 1, 2
+SLICE_BY_MEMORY, SLICE_BY_FLOPS = 0, 1
 MAX_RANK = 34
 MAX_SLICED = 40
 N_CLASSES = 4
@@ -52,7 +53,7 @@ class wmc_plan_options(ctypes.Structure):
                 ("order", ctypes.POINTER(ctypes.c_int32)), ("order_len", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("parent", ctypes.POINTER(ctypes.c_int64)),
                 ("n_tree_nodes", ctypes.c_int64), ("mem_cap_bytes", ctypes.c_uint64),
-                ("rank_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("rank_cap", ctypes.c_int32), ("slice_objective", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class wmc_slice_state(ctypes.Structure):
@@ -113,6 +114,7 @@ def lib():
             "wmc_serve": [P, P, i64, P],
             "wmc_serve_stats": [P, P],
             "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
+            "wmc_plan_kernels": [P, P, i64, P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -206,7 +208,8 @@ class Plan:
 
     def __init__(self, net: Network, kind: str = "minfill", seed: int = 0,
                  order: Optional[Sequence[int]] = None, parent: Optional[Sequence[int]] = None,
-                 mem_cap_bytes: int = 0, rank_cap: int = 0, precision: str = "fp64", block: int = 1):
+                 mem_cap_bytes: int = 0, rank_cap: int = 0, precision: str = "fp64", block: int = 1,
+                 slice_objective: str = "memory"):
         o = wmc_plan_options()
         o.kind = {"minfill": TREE_MINFILL, "order": TREE_ORDER, "explicit": TREE_EXPLICIT}[kind]
         o.precision = {"fp64": FP64, "fp32": FP32_SCALED, "fp32_scaled": FP32_SCALED}[precision]
@@ -223,6 +226,7 @@ class Plan:
             o.n_tree_nodes = int(self._parent.size)
         o.mem_cap_bytes = int(mem_cap_bytes)
         o.rank_cap = int(rank_cap)
+        o.slice_objective = {"memory": SLICE_BY_MEMORY, "flops": SLICE_BY_FLOPS}[slice_objective]
         h = ctypes.c_void_p()
         _check(lib().wmc_plan(net._h, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -404,6 +408,20 @@ def plan_launches(plan: Plan):
     c = np.zeros(k, dtype=np.int32)
     _check(lib().wmc_plan_launches(plan._h, _p(b), _p(f), _p(c), k, ctypes.byref(n)))
     return b, f, c
+
+
+KERNEL_NAMES = ["k_begin", "k_leaves", "k_nodes", "k_gemm_p", "k_gemm", "k_stream_mfma", "k_stream2",
+                "k_stream2_split", "k_finish"]
+
+
+def plan_kernels(plan: Plan) -> np.ndarray:
+    """Kernel family (index into KERNEL_NAMES) of each launch of one slice,
+    in the order of plan_launches."""
+    n = ctypes.c_int64()
+    _check(lib().wmc_plan_kernels(plan._h, None, 0, ctypes.byref(n)))
+    k = np.zeros(int(n.value), dtype=np.int32)
+    _check(lib().wmc_plan_kernels(plan._h, _p(k), int(n.value), ctypes.byref(n)))
+    return k
 
 
 def wmc_contract_profile(plan: Plan, weights=None, ws=None, stream=None):

@@ -30,6 +30,23 @@ static hipError_t upload_weights(const wmc_plan_t &P, const double *weights, cha
     return e;
 }
 
+// Kernel family that runs node launch k (1 <= k < P.launches.size()) of a
+// solo plan, with the streaming kernels' arguments filled in when one of
+// them is chosen.  The executor and wmc_plan_kernels share this choice.
+template <typename T>
+static int solo_kernel(const wmc_plan_t &P, size_t k, Stream2Args *sa, StreamMfmaArgs *ma) {
+    const Launch &Ln = P.launches[k];
+    if (Ln.type == LAUNCH_GEMM)
+        return gemm_persistent<T>(P.gemms[(size_t)Ln.pad]) ? WMC_KERNEL_GEMM_P : WMC_KERNEL_GEMM;
+    if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM) {
+        const NodeDesc &d = P.nodes[(size_t)Ln.first];
+        if (stream_mfma_args(d, ma)) return WMC_KERNEL_STREAM_MFMA;
+        if (stream2_args(d, sa, 2, 14, 6))
+            return stream2_split_lanes<T>(d.nk) > 0 ? WMC_KERNEL_STREAM2_SPLIT : WMC_KERNEL_STREAM2;
+    }
+    return WMC_KERNEL_NODES;
+}
+
 template <typename T>
 static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long long b, long long e,
                              wmc_value *per_slice, LaunchTimer *tm = nullptr, bool keep_sum = false) {
@@ -59,15 +76,14 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
             const Launch &Ln = P.launches[k];
             Stream2Args sa;
             StreamMfmaArgs ma;
-            if (Ln.type == LAUNCH_GEMM)
+            const int kern = solo_kernel<T>(P, k, &sa, &ma);
+            if (kern == WMC_KERNEL_GEMM_P || kern == WMC_KERNEL_GEMM)
                 launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st);
-            else if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM &&
-                     stream_mfma_args(P.nodes[(size_t)Ln.first], &ma))
+            else if (kern == WMC_KERNEL_STREAM_MFMA)
                 launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st);
-            else if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM &&
-                     stream2_args(P.nodes[(size_t)Ln.first], &sa, 2, 14, 6) &&
+            else if ((kern == WMC_KERNEL_STREAM2 || kern == WMC_KERNEL_STREAM2_SPLIT) &&
                      launch_stream2<T>(sa, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
-                                      stream2_split_lanes<T>(P.nodes[(size_t)Ln.first].nk))) {
+                                      kern == WMC_KERNEL_STREAM2_SPLIT ? stream2_split_lanes<T>(P.nodes[(size_t)Ln.first].nk) : 0)) {
             } else
                 hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first,
                                    Ln.count, (long long)Ln.work, arena, meta,
@@ -270,5 +286,32 @@ extern "C" wmc_status wmc_contract_profile(const wmc_plan_t *plan, const double 
         return s;
     }
     *out = (h.s == 0.0 && h.c == 0.0) ? make_value(0.0, 0) : make_value(h.s + h.c, h.e);
+    return WMC_OK;
+}
+
+// Kernel family of every launch wmc_contract issues for one slice, in the
+// order of wmc_plan_launches (host only: the choice depends on the plan and,
+// for the matrix kernel, on the current device's LDS size).
+extern "C" wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, int64_t cap, int64_t *n_out) {
+    if (!plan) {
+        wmc_set_error("wmc_plan_kernels: plan is NULL");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    const wmc_plan_t &P = *plan;
+    const int64_t n = (int64_t)P.launches.size() + 2;
+    if (n_out) *n_out = n;
+    if (!kernel) return WMC_OK;
+    if (cap < n) {
+        wmc_set_error("wmc_plan_kernels: need %lld slots", (long long)n);
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    kernel[0] = WMC_KERNEL_BEGIN;
+    kernel[1] = WMC_KERNEL_LEAVES;
+    for (size_t k = 1; k < P.launches.size(); ++k) {
+        Stream2Args sa;
+        StreamMfmaArgs ma;
+        kernel[k + 1] = P.precision == WMC_FP64 ? solo_kernel<double>(P, k, &sa, &ma) : solo_kernel<float>(P, k, &sa, &ma);
+    }
+    kernel[n - 1] = WMC_KERNEL_FINISH;
     return WMC_OK;
 }

@@ -788,7 +788,7 @@ static Schedule make_schedule(const std::vector<TNode> &T, const std::vector<int
 
 // Peak of live tensor bytes over a schedule (MemCost of Algorithm 3).
 static double peak_live(const std::vector<TNode> &T, const Schedule &S, const std::vector<uint8_t> &sl,
-                        int32_t elem, int32_t root) {
+                        int32_t elem, int32_t root, bool aligned = false) {
     const size_t NL = S.launches.size();
     // launch 0 is the leaf fill; node launch k is index k+1
     std::vector<double> delta(NL + 3, 0.0);
@@ -798,6 +798,7 @@ static double peak_live(const std::vector<TNode> &T, const Schedule &S, const st
             birth[(size_t)S.order[(size_t)(S.launches[k].first + q)]] = (int32_t)k + 1;
     for (size_t i = 0; i < T.size(); ++i) {
         double b = (double)elem * std::ldexp(1.0, srank(T[i], sl));
+        if (aligned) b = std::max(b, 256.0);
         int32_t death = ((int32_t)i == root || T[i].parent < 0) ? (int32_t)NL + 1 : birth[(size_t)T[i].parent];
         delta[(size_t)birth[i]] += b;
         delta[(size_t)death + 1] -= b;
@@ -837,51 +838,189 @@ static std::vector<int32_t> classes_of(const std::vector<TNode> &T, const std::v
 // ---------------------------------------------------------------------------
 static uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Static arena of a schedule: each tensor lives from the launch that writes
+// it (leaves: the leaf fill, launch 0) to the launch that reads it, and is
+// placed first-fit over the tensors whose lifetimes overlap its own, largest
+// first, each 256-byte aligned.  Returns the arena bytes; offs (optional)
+// receives every tensor's element offset.  This is MemCost of Algorithm 3
+// as the device sees it: the memory one slice's tensors occupy.
+static uint64_t place_arena(const std::vector<TNode> &T, const Schedule &S, const std::vector<uint8_t> &sl,
+                            int32_t elem, std::vector<int64_t> *offs) {
+    const size_t NT = T.size();
+    std::vector<int32_t> birth(NT, 0), death(NT, 0);
+    for (size_t k = 0; k < S.launches.size(); ++k)
+        for (int32_t q = 0; q < S.launches[k].second; ++q)
+            birth[(size_t)S.order[(size_t)(S.launches[k].first + q)]] = (int32_t)k + 1;
+    const int32_t NL = (int32_t)S.launches.size() + 1;
+    for (size_t i = 0; i < NT; ++i) death[i] = (T[i].parent < 0) ? NL : birth[(size_t)T[i].parent];
+    const uint64_t align_elems = 256 / (uint64_t)elem;
+    std::vector<int32_t> by_size(NT);
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::vector<uint64_t> elems(NT);
+    for (size_t i = 0; i < NT; ++i) elems[i] = align_up((uint64_t)1 << srank(T[i], sl), align_elems);
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int32_t a, int32_t b) {
+        if (elems[(size_t)a] != elems[(size_t)b]) return elems[(size_t)a] > elems[(size_t)b];
+        return birth[(size_t)a] < birth[(size_t)b];
+    });
+    std::vector<int64_t> off(NT, 0);
+    std::vector<int32_t> placed;
+    uint64_t arena_elems = 0;
+    std::vector<std::pair<uint64_t, uint64_t>> busy;
+    for (int32_t t : by_size) {
+        busy.clear();
+        for (int32_t p : placed) {
+            if (death[(size_t)p] < birth[(size_t)t] || death[(size_t)t] < birth[(size_t)p]) continue;
+            busy.push_back({(uint64_t)off[(size_t)p], (uint64_t)off[(size_t)p] + elems[(size_t)p]});
+        }
+        std::sort(busy.begin(), busy.end());
+        uint64_t o = 0;
+        for (auto &iv : busy) {
+            if (iv.first >= o + elems[(size_t)t]) break;
+            o = std::max(o, iv.second);
+        }
+        off[(size_t)t] = (int64_t)o;
+        arena_elems = std::max(arena_elems, o + elems[(size_t)t]);
+        placed.push_back(t);
+    }
+    if (offs) offs->swap(off);
+    return arena_elems * (uint64_t)elem;
+}
+
+// Peak of live tensor bytes, sizes 256-byte aligned, over the schedule the
+// slice set sl executes (its node classes decide which small nodes share a
+// launch): the lower bound the arena placement reaches at best.
+static double peak_live_aligned(const std::vector<TNode> &T, const std::vector<uint8_t> &sl, int32_t elem,
+                                int32_t root) {
+    const Schedule S = make_schedule(T, classes_of(T, sl));
+    return peak_live(T, S, sl, elem, root, true);
+}
+
+// Excess over the rank cap: sum over tensors above it of 2^(rank - cap).
+static double rank_excess(const std::vector<TNode> &T, const std::vector<uint8_t> &sl, int32_t cap) {
+    double e = 0.0;
+    for (const TNode &t : T) {
+        const int32_t r = srank(t, sl);
+        if (r > cap) e += std::ldexp(1.0, r - cap);
+    }
+    return e;
+}
+
 static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &o, wmc_plan_t &P) {
     std::vector<TNode> &T = P.T;
     const size_t NT = T.size();
     const int32_t n = net.n;
     std::vector<uint8_t> sl((size_t)n + 1, 0);
 
-    // ---- slicing (Algorithm 3): grow I greedily while MemCost exceeds the bound
+    // ---- slicing (Algorithm 3): grow I greedily while the cap is exceeded.
+    // The rank cap bounds the largest storage rank; the memory cap bounds
+    // MemCost, the placed arena of the schedule this slice set executes
+    // (node classes, and with them which small nodes share a launch, depend
+    // on the slice set, so the schedule is rebuilt for every check).
     const int32_t rank0 = max_rank_of(T, sl);
     int32_t idx_rank = 0;
     for (const TNode &t : T) idx_rank = std::max(idx_rank, t.index_rank);
-    auto over = [&](const Schedule &S, const std::vector<uint8_t> &s) {
-        if (o.rank_cap > 0 && max_rank_of(T, s) > o.rank_cap) return true;
-        if (o.mem_cap_bytes > 0 && peak_live(T, S, s, P.elem, P.root) > (double)o.mem_cap_bytes) return true;
-        return false;
+    const int32_t objective = o.slice_objective;  // WMC_SLICE_BY_MEMORY or WMC_SLICE_BY_FLOPS
+    if (objective < 0 || objective > 1)
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: slice objective %d (0 = memory, 1 = flops)", objective);
+    auto rank_over = [&](const std::vector<uint8_t> &s) { return o.rank_cap > 0 && max_rank_of(T, s) > o.rank_cap; };
+    auto mem_over = [&](const std::vector<uint8_t> &s) {
+        if (o.mem_cap_bytes == 0) return false;
+        const Schedule S = make_schedule(T, classes_of(T, s));
+        return place_arena(T, S, s, P.elem, nullptr) > o.mem_cap_bytes;
     };
-    Schedule S0 = make_schedule(T, classes_of(T, sl));
-    while (over(S0, sl)) {
-        if ((int32_t)P.sliced.size() >= WMC_MAX_SLICED)
-            WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: cap not met after slicing %d variables", WMC_MAX_SLICED);
-        // candidates: variables of the tensors at the current maximum rank,
-        // and of the tensors live at the peak
-        int32_t mr = max_rank_of(T, sl);
-        std::vector<uint8_t> cand((size_t)n + 1, 0);
-        for (const TNode &t : T)
-            if (srank(t, sl) >= mr - 1)
-                for (int32_t v : t.vars)
-                    if (!sl[(size_t)v]) cand[(size_t)v] = 1;
-        int32_t best = -1;
-        double best_mem = 0, best_fl = 0;
-        for (int32_t v = 1; v <= n; ++v) {
-            if (!cand[(size_t)v]) continue;
-            sl[(size_t)v] = 1;
-            double mem = peak_live(T, S0, sl, P.elem, P.root);
-            double fl = flops_of(T, sl);
-            if (o.rank_cap > 0) mem += 1e30 * (double)std::max(0, max_rank_of(T, sl) - o.rank_cap);
-            sl[(size_t)v] = 0;
-            if (best < 0 || mem < best_mem || (mem == best_mem && fl < best_fl)) {
-                best = v;
-                best_mem = mem;
-                best_fl = fl;
+    auto over = [&](const std::vector<uint8_t> &s) { return rank_over(s) || mem_over(s); };
+    // how far a slice set is from the caps (0 once both hold): rank excess
+    // first, then the aligned peak of live bytes above the memory cap
+    auto excess = [&](const std::vector<uint8_t> &s) {
+        double e = o.rank_cap > 0 ? 1e30 * rank_excess(T, s, o.rank_cap) : 0.0;
+        if (o.mem_cap_bytes > 0) e += std::max(0.0, peak_live_aligned(T, s, P.elem, P.root) - (double)o.mem_cap_bytes);
+        return e;
+    };
+    if (o.mem_cap_bytes > 0) {
+        // every leaf is live during the leaf fill and takes at least 256
+        // bytes, whatever is sliced: below that no slice set meets the cap
+        uint64_t floor_bytes = 0;
+        for (const TNode &t : T) floor_bytes += t.kind != 2 ? 256 : 0;
+        if (floor_bytes > o.mem_cap_bytes)
+            WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: cap %llu below the %llu bytes the leaves occupy",
+                     (unsigned long long)o.mem_cap_bytes, (unsigned long long)floor_bytes);
+    }
+    // greedy growth of I with one criterion (0: memory, 1: flops), then, for
+    // the flops criterion, dropping the variables the caps no longer need
+    auto grow = [&](int32_t crit, std::vector<int32_t> &I) -> wmc_status {
+        std::vector<uint8_t> s2((size_t)n + 1, 0);
+        for (int32_t v : I) s2[(size_t)v] = 1;
+        while (over(s2)) {
+            if ((int32_t)I.size() >= WMC_MAX_SLICED)
+                WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: cap not met after slicing %d variables", WMC_MAX_SLICED);
+            // candidates: variables of the tensors within one of the maximum rank
+            int32_t mr = max_rank_of(T, s2);
+            if (mr == 0) WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: cap below the arena of rank-0 tensors");
+            std::vector<uint8_t> cand((size_t)n + 1, 0);
+            for (const TNode &t : T)
+                if (srank(t, s2) >= mr - 1)
+                    for (int32_t v : t.vars)
+                        if (!s2[(size_t)v]) cand[(size_t)v] = 1;
+            const double ex0 = crit == 1 ? excess(s2) : 0.0;
+            int32_t best = -1;
+            double best_key = 0, best_tie = 0;
+            for (int32_t v = 1; v <= n; ++v) {
+                if (!cand[(size_t)v]) continue;
+                s2[(size_t)v] = 1;
+                double key, tie;
+                if (crit == 0) {
+                    // Algorithm 3's ChooseSliceIndex: least MemCost (aligned
+                    // peak of live bytes on the executed schedule), ties by flops
+                    key = peak_live_aligned(T, s2, P.elem, P.root);
+                    if (o.rank_cap > 0) key += 1e30 * (double)std::max(0, max_rank_of(T, s2) - o.rank_cap);
+                    tie = flops_of(T, s2);
+                } else {
+                    // least summed flops over all slices among the variables
+                    // that bring the slice set closer to the caps
+                    const double ex = excess(s2);
+                    key = ex < ex0 ? std::ldexp(flops_of(T, s2), (int)I.size() + 1) : HUGE_VAL;
+                    tie = ex;
+                }
+                s2[(size_t)v] = 0;
+                if (best < 0 || key < best_key || (key == best_key && tie < best_tie)) {
+                    best = v;
+                    best_key = key;
+                    best_tie = tie;
+                }
+            }
+            if (best < 0) WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: no variable left to slice");
+            s2[(size_t)best] = 1;
+            I.push_back(best);
+        }
+        if (objective == 1) {
+            for (size_t q = I.size(); q-- > 0;) {
+                const int32_t v = I[q];
+                s2[(size_t)v] = 0;
+                if (over(s2)) s2[(size_t)v] = 1;
+                else I.erase(I.begin() + (long)q);
             }
         }
-        if (best < 0) WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: no variable left to slice");
-        sl[(size_t)best] = 1;
-        P.sliced.push_back(best);
+        return WMC_OK;
+    };
+    {
+        std::vector<int32_t> I0;
+        wmc_status st = grow(0, I0);
+        if (st != WMC_OK) return st;
+        if (objective == 1) {
+            // the flops criterion keeps whichever of the two greedy slice
+            // sets (both pruned) does less work over all its slices
+            std::vector<int32_t> I1;
+            if (grow(1, I1) == WMC_OK) {
+                auto work = [&](const std::vector<int32_t> &I) {
+                    std::vector<uint8_t> s2((size_t)n + 1, 0);
+                    for (int32_t v : I) s2[(size_t)v] = 1;
+                    return std::ldexp(flops_of(T, s2), (int)I.size());
+                };
+                if (work(I1) < work(I0)) I0.swap(I1);
+            }
+        }
+        P.sliced = I0;
+        for (int32_t v : I0) sl[(size_t)v] = 1;
     }
     const int32_t rankS = max_rank_of(T, sl);
     if (rankS > WMC_MAX_RANK)
@@ -979,37 +1118,12 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     }
 
     // ---- static arena: greedy placement by size over lifetime intervals
-    const uint64_t align_elems = 256 / (uint64_t)P.elem;
-    std::vector<int32_t> by_size(NT);
-    std::iota(by_size.begin(), by_size.end(), 0);
-    std::vector<uint64_t> elems(NT);
-    for (size_t i = 0; i < NT; ++i) elems[i] = align_up((uint64_t)1 << srank(T[i], sl), align_elems);
-    std::stable_sort(by_size.begin(), by_size.end(), [&](int32_t a, int32_t b) {
-        if (elems[(size_t)a] != elems[(size_t)b]) return elems[(size_t)a] > elems[(size_t)b];
-        return T[(size_t)a].birth < T[(size_t)b].birth;
-    });
-    std::vector<int32_t> placed;
-    uint64_t arena_elems = 0;
-    std::vector<std::pair<uint64_t, uint64_t>> busy;
-    for (int32_t t : by_size) {
-        busy.clear();
-        const TNode &X = T[(size_t)t];
-        for (int32_t p : placed) {
-            const TNode &Y = T[(size_t)p];
-            if (Y.death < X.birth || X.death < Y.birth) continue;
-            busy.push_back({(uint64_t)Y.off, (uint64_t)Y.off + elems[(size_t)p]});
-        }
-        std::sort(busy.begin(), busy.end());
-        uint64_t off = 0;
-        for (auto &iv : busy) {
-            if (iv.first >= off + elems[(size_t)t]) break;
-            off = std::max(off, iv.second);
-        }
-        T[(size_t)t].off = (int64_t)off;
-        arena_elems = std::max(arena_elems, off + elems[(size_t)t]);
-        placed.push_back(t);
-    }
-    P.arena_bytes = arena_elems * (uint64_t)P.elem;
+    std::vector<int64_t> offs;
+    P.arena_bytes = place_arena(T, S, sl, P.elem, &offs);
+    for (size_t i = 0; i < NT; ++i) T[i].off = offs[i];
+    if (o.mem_cap_bytes > 0 && P.arena_bytes > o.mem_cap_bytes)
+        WMC_FAIL(WMC_ERR_CAP_UNREACHABLE, "wmc_plan: internal arena %llu above the cap %llu",
+                 (unsigned long long)P.arena_bytes, (unsigned long long)o.mem_cap_bytes);
 
     // ---- descriptors
     P.leaves.clear();
@@ -1198,7 +1312,7 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     I.flops_per_slice = fl;
     I.bytes_per_slice = by;
     I.max_node_bytes = mx;
-    I.peak_live_bytes = peak_live(T, S, sl, P.elem, P.root);
+    I.peak_live_bytes = peak_live(T, S, sl, P.elem, P.root, true);
     I.arena_bytes = P.arena_bytes;
     I.workspace_bytes = P.workspace_bytes;
     I.n_launches = (int64_t)P.launches.size() + 2;  // + begin and finish kernels

@@ -551,15 +551,31 @@ static inline int lds_budget() {
     return budget[dev];
 }
 
+// LDS bytes of B[beta] in the persistent matrix kernel (rows padded against
+// bank conflicts).
+template <typename T>
+static inline size_t gemm_p_lds(const GemmDesc &hd) {
+    const int N = 1 << hd.nn, K = 1 << hd.nk;
+    const int NT = (N + 15) / 16;
+    return (size_t)K * (NT * 16 + (sizeof(T) == 8 ? 2 : 4)) * sizeof(T);
+}
+
+// True when a matrix node runs on the persistent kernel k_gemm_p (K of 4 to
+// 64 and B[beta] fits the LDS budget); otherwise the chunked k_gemm runs.
+template <typename T>
+static inline bool gemm_persistent(const GemmDesc &hd) {
+    const int K = 1 << hd.nk;
+    return K >= 4 && K <= 64 && gemm_p_lds<T>(hd) <= (size_t)lds_budget();
+}
+
 template <typename T>
 static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_meta *meta, hipStream_t st) {
     const int N = 1 << hd.nn, K = 1 << hd.nk;
     const int NT = (N + 15) / 16;
     const unsigned long long tiles = 1ull << (hd.nm - 4);
     const unsigned long long groups = (tiles + GEMM_TILES - 1) / GEMM_TILES;  // fallback kernel
-    const size_t full = (size_t)K * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
-    const size_t padded = (size_t)K * (NT * 16 + (sizeof(T) == 8 ? 2 : 4)) * sizeof(T);
-    if (K >= 4 && K <= 64 && padded <= (size_t)lds_budget()) {
+    const size_t padded = gemm_p_lds<T>(hd);
+    if (gemm_persistent<T>(hd)) {
         const int NTp = NT <= 1 ? 1 : NT <= 2 ? 2 : NT <= 4 ? 4 : 8;
         // persistent grid: as many workgroups as fit on the device at once
         auto grid_of = [&](const void *fn) {
@@ -592,7 +608,6 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
 #undef WMC_GP
 #undef WMC_GP1
     }
-    (void)full;
     const int KC = gemm_kc(hd.nk, hd.nn, (int)sizeof(T));
     const size_t smem = (size_t)KC * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
     dim3 grid((unsigned)groups, 1u << hd.nb);

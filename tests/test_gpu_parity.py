@@ -168,6 +168,24 @@ def test_slicing(cap):
     assert rel(a + b, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("objective", ["memory", "flops"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_mem_capped_sliced_plan_vs_oracle(objective, precision, tol):
+    """A plan sliced to meet a memory cap (Algorithm 3's bound m on the
+    arena) runs within the cap it was given and matches the oracle."""
+    f = wl.banded_3cnf(120, 420, 22, seed=3)
+    net = W.Network.from_formula(f)
+    base = W.Plan(net, seed=0, block=2, precision=precision).stats()
+    cap = base["arena_bytes"] // 4
+    say(f"mem cap {cap} {objective} {precision}")
+    p = W.Plan(net, seed=0, block=2, precision=precision, mem_cap_bytes=cap, slice_objective=objective)
+    st = p.stats()
+    assert st["arena_bytes"] <= cap and st["n_sliced"] >= 3
+    v = W.wmc_contract(p)
+    m, e = oracle.bucket(f)
+    assert rel(value_fraction(v), Fraction(m) * Fraction(2) ** e) <= tol
+
+
 def test_weights_override_and_reuse():
     f = wl.grid_cnf(6, 7, 0.2, seed=4)
     net = W.Network.from_formula(f)

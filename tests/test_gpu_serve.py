@@ -62,9 +62,14 @@ def test_serve_results_vs_oracle(structures, precision, tol):
         assert rel(frac(got[q].value), ref) <= tol, q
 
 
-def test_serve_alone_equals_in_mix(structures):
-    """Each result in a mix equals the same request served alone, bit for bit."""
-    srv, plans, ids = make_server(structures, max_slots=32, buffer_bytes=1 << 29)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_serve_alone_equals_in_mix(structures, precision, tol):
+    """Each result in a mix equals the same request served alone, bit for bit
+    (both precisions: a request's arithmetic is its plan's, whatever shares
+    its launches), and wmc_contract on the same plan: bit for bit in FP64;
+    in scaled FP32 within the FP32 tolerance (the solo executor may run a
+    node on another kernel family, which rounds at other points)."""
+    srv, plans, ids = make_server(structures, precision, max_slots=32, buffer_bytes=1 << 29)
     rng = np.random.default_rng(2)
     reqs = []
     for q in range(40):
@@ -88,15 +93,18 @@ def test_serve_alone_equals_in_mix(structures):
             mix[r.request_id] = r.value
     assert len(mix) == len(reqs)
     assert srv.stats()["peak_active"] > 4
-    say("mix done")
+    say(f"mix done ({precision})")
     for q, (s, Wt) in enumerate(reqs):
-        alone = W.Server(precision="fp64", max_slots=1, buffer_bytes=1 << 27)
+        alone = W.Server(precision=precision, max_slots=1, buffer_bytes=1 << 27)
         sid = alone.register(plans[s])
         alone.submit(sid, Wt, 0)
         (r,) = alone.drain()
         assert (r.value.mantissa, r.value.exp2) == (mix[q].mantissa, mix[q].exp2), q
         solo = W.wmc_contract(plans[s], Wt)
-        assert (solo.mantissa, solo.exp2) == (mix[q].mantissa, mix[q].exp2), q
+        if precision == "fp64":
+            assert (solo.mantissa, solo.exp2) == (mix[q].mantissa, mix[q].exp2), q
+        else:
+            assert rel(frac(solo), frac(mix[q])) <= tol, q
 
 
 def test_serve_admission_respects_budget(structures):
@@ -166,12 +174,14 @@ def test_serve_long_clause_structures():
         assert rel(frac(got[q].value), ref) <= 1e-12, q
 
 
-def test_serve_big_structures_vs_oracle():
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_serve_big_structures_vs_oracle(precision, tol):
     """Serving structures 6 and 7 (storage rank 23-24) mixed with small ones,
-    against the oracle, and each equal to wmc_contract bit for bit."""
+    against the oracle, and each equal to wmc_contract (bit for bit in FP64,
+    within the tolerance in scaled FP32)."""
     fs = [wl.serve_structure(s) for s in (6, 7, 0)]
-    plans = [W.Plan(W.Network.from_formula(f), seed=0) for f in fs]
-    srv = W.Server(precision="fp64", max_slots=8, buffer_bytes=1 << 31)
+    plans = [W.Plan(W.Network.from_formula(f), seed=0, precision=precision) for f in fs]
+    srv = W.Server(precision=precision, max_slots=8, buffer_bytes=1 << 31)
     ids = [srv.register(p) for p in plans]
     rng = np.random.default_rng(9)
     reqs = []
@@ -184,7 +194,9 @@ def test_serve_big_structures_vs_oracle():
     got = {r.request_id: r for r in srv.drain()}
     for q, (s, Wt) in enumerate(reqs):
         solo = W.wmc_contract(plans[s], Wt)
-        assert (solo.mantissa, solo.exp2) == (got[q].value.mantissa, got[q].value.exp2), q
-        if q < 3:
-            m, e = oracle.bucket(fs[s].with_weights(Wt))
-            assert rel(frac(got[q].value), Fraction(m) * Fraction(2) ** e) <= 1e-12, q
+        if precision == "fp64":
+            assert (solo.mantissa, solo.exp2) == (got[q].value.mantissa, got[q].value.exp2), q
+        else:
+            assert rel(frac(solo), frac(got[q].value)) <= tol, q
+        m, e = oracle.bucket(fs[s].with_weights(Wt))
+        assert rel(frac(got[q].value), Fraction(m) * Fraction(2) ** e) <= tol, q

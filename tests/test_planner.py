@@ -190,10 +190,73 @@ def test_mem_cap_slicing():
     peak = p0.stats()["peak_live_bytes"]
     p = W.Plan(net, seed=0, mem_cap_bytes=int(peak // 5))
     s = p.stats()
-    assert s["peak_live_bytes"] <= peak // 5
+    assert s["peak_live_bytes"] <= s["arena_bytes"] <= peak // 5
     assert s["n_sliced"] >= 1
     got, _ = emulate(p, f.weights)
     assert rel_err(got, Fraction(oracle.brute(f))) < 1e-12
+
+
+def _cap_sweep_formulas():
+    """Random, banded and grid formulas whose arenas are dominated by their
+    intermediates (not by the 256-byte floor of the leaves)."""
+    fs = []
+    for seed in range(6):
+        fs.append(("random", wl.random_kcnf(26 + seed, 100 + 6 * seed, 100 + seed)))
+    for seed in range(3):
+        fs.append(("banded", wl.banded_3cnf(80 + 10 * seed, 280 + 35 * seed, 16 + seed, seed)))
+    fs.append(("grid", wl.grid_cnf(14, 16, 0.10, seed=14)))
+    return fs
+
+
+@pytest.mark.parametrize("objective,blocks", [("memory", (1, 2, 3, 4, 5)), ("flops", (1, 5))])
+def test_mem_cap_is_met_by_the_placed_arena(objective, blocks):
+    """Algorithm 3's bound m holds for the memory the plan allocates: over
+    random, banded and grid formulas, blocks 1-5 and caps of arena/3 to
+    arena/9, every plan keeps its arena (the bytes its tensors occupy as
+    placed, alignment included), and so its live peak, within the cap, or
+    reports CAP_UNREACHABLE; the replayed descriptors of capped plans of the
+    smaller formulas equal the oracle."""
+    n_plans = n_capped = n_checked = 0
+    for fi, (kind, f) in enumerate(_cap_sweep_formulas()):
+        net = W.Network.from_formula(f)
+        for block in blocks:
+            base = W.Plan(net, seed=fi, block=block).stats()
+            for div in range(3, 10):
+                cap = int(base["arena_bytes"] // div)
+                try:
+                    p = W.Plan(net, seed=fi, block=block, mem_cap_bytes=cap, slice_objective=objective)
+                except W.WmcError as e:
+                    assert e.status == 3, (kind, fi, block, div)
+                    continue
+                s = p.stats()
+                n_plans += 1
+                assert s["arena_bytes"] <= cap, (kind, fi, block, div, s["arena_bytes"], cap)
+                assert s["peak_live_bytes"] <= s["arena_bytes"], (kind, fi, block, div)
+                assert s["workspace_bytes"] >= s["arena_bytes"]
+                n_capped += s["n_sliced"] > 0
+                if kind == "random" and fi < 3 and div in (3, 9) and block == blocks[-1]:
+                    got, _ = emulate(p, f.weights)
+                    assert rel_err(got, Fraction(oracle.bucket_value(f))) < 1e-12
+                    n_checked += 1
+    need = 250 if len(blocks) == 5 else 100
+    assert n_plans >= need and n_capped == n_plans and n_checked >= 6, (n_plans, n_capped, n_checked)
+
+
+def test_flops_objective_never_slices_more_work():
+    """The flops objective (least summed flops, then unneeded slices dropped)
+    never does more total work than the memory greedy on the same cap, and
+    both meet it."""
+    for seed in range(8):
+        f = wl.banded_3cnf(120, 420, 14, seed)
+        net = W.Network.from_formula(f)
+        r0 = W.Plan(net, seed=seed).stats()["max_rank"]
+        cap = r0 - 3
+        a = W.Plan(net, seed=seed, rank_cap=cap).stats()
+        b = W.Plan(net, seed=seed, rank_cap=cap, slice_objective="flops").stats()
+        assert a["max_rank"] <= cap and b["max_rank"] <= cap
+        work_a = a["flops_per_slice"] * a["n_slices"]
+        work_b = b["flops_per_slice"] * b["n_slices"]
+        assert work_b <= work_a * 1.0000001, (seed, work_a, work_b)
 
 
 def test_cap_unreachable():
