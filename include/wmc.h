@@ -224,6 +224,21 @@ wmc_status wmc_plan_image(const wmc_plan_t *plan, void *dst, uint64_t dst_bytes,
 wmc_status wmc_contract(const wmc_plan_t *plan, const double *weights, void *workspace,
                         uint64_t workspace_bytes, void *stream, wmc_value *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * wmc_contract with its workspace taken from a static device array of
+ * WMC_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends.  The call allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library routine).  Every call on a device shares
+ * that device's array, so calls that overlap on one device (other threads,
+ * other streams) race; successive calls on one stream are safe.  Blocks
+ * until the result is on the host, as wmc_contract does.  Errors:
+ * OUT_OF_MEMORY if wmc_plan_info.workspace_bytes exceeds
+ * WMC_NOALLOC_SCRATCH_BYTES, INVALID_ARGUMENT (NULL, non-finite weights),
+ * DEVICE (HIP failure, including the symbol lookup on first use). */
+#define WMC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+wmc_status wmc_contract_noalloc(const wmc_plan_t *plan, const double *weights, void *stream, wmc_value *out);
+
 /* Checkpoint of the slice loop (Algorithm 3): the running Neumaier sum
  * (s + c) * 2^e of the slices already run, the next slice to run and the
  * plan's slice count.  Zero-initialise to start; the struct is plain data and

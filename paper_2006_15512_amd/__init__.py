@@ -115,6 +115,7 @@ def lib():
             "wmc_serve_stats": [P, P],
             "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
             "wmc_plan_kernels": [P, P, i64, P],
+            "wmc_contract_noalloc": [P, P, P, ctypes.POINTER(wmc_value)],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -325,6 +326,22 @@ def wmc_contract(plan: Plan, weights=None, ws=None, stream=None) -> Value:
     out = wmc_value()
     _check(lib().wmc_contract(plan._h, _p(w), ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                               _stream_ptr(stream), ctypes.byref(out)))
+    return Value.of(out)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def wmc_contract_noalloc(plan: Plan, weights=None, stream=None) -> Value:
+    """wmc_contract on the library's static device scratch (no device
+    allocation; plans up to NOALLOC_SCRATCH_BYTES of workspace)."""
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        if w.size != 2 * plan.net.n:
+            raise ValueError("weights must have 2*n entries")
+    out = wmc_value()
+    _check(lib().wmc_contract_noalloc(plan._h, _p(w), _stream_ptr(stream), ctypes.byref(out)))
     return Value.of(out)
 
 

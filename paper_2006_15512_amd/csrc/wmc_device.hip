@@ -1,6 +1,8 @@
 // Execution stage on gfx950 for one plan: the pairwise contractions of
 // Algorithm 2 over the slices of Algorithm 3, all on the device.  Kernels
 // and their numerics are in wmc_kernels.h.
+#include <mutex>
+
 #include "wmc_kernels.h"
 
 // Optional per-launch timing: an event is recorded on the stream after every
@@ -314,4 +316,59 @@ extern "C" wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, 
     }
     kernel[n - 1] = WMC_KERNEL_FINISH;
     return WMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Contraction without any device allocation: the workspace is a static
+// device array of WMC_NOALLOC_SCRATCH_BYTES.  Host code never passes the
+// array's name to a kernel or copy (on the host it is only a stand-in for
+// the symbol); it passes the device address hipGetSymbolAddress returns,
+// looked up once per device with that device current.  Every call on a
+// device shares that device's array, so calls that overlap on one device
+// race; k_begin clears the meta table and the accumulator at the start of
+// every contraction, and nothing else in the workspace is read before it is
+// written.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[WMC_NOALLOC_SCRATCH_BYTES];
+
+#define WMC_NOALLOC_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[WMC_NOALLOC_MAX_DEVICES];
+
+static wmc_status scratch_of_current_device(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= WMC_NOALLOC_MAX_DEVICES) {
+        wmc_set_error("wmc_contract_noalloc: device %d beyond the %d supported", dev, WMC_NOALLOC_MAX_DEVICES);
+        return WMC_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            wmc_set_error("wmc_contract_noalloc: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return WMC_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_contract_noalloc(const wmc_plan_t *plan, const double *weights, void *stream,
+                                           wmc_value *out) {
+    if (!plan || !out) {
+        wmc_set_error("wmc_contract_noalloc: NULL plan or out");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (plan->workspace_bytes > WMC_NOALLOC_SCRATCH_BYTES) {
+        wmc_set_error("wmc_contract_noalloc: plan needs a workspace of %llu bytes, the static scratch holds %llu",
+                      (unsigned long long)plan->workspace_bytes, (unsigned long long)WMC_NOALLOC_SCRATCH_BYTES);
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    void *ws = nullptr;
+    const wmc_status s = scratch_of_current_device(&ws);
+    if (s != WMC_OK) return s;
+    return wmc_contract(plan, weights, ws, WMC_NOALLOC_SCRATCH_BYTES, stream, out);
 }
