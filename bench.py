@@ -49,9 +49,10 @@ def workload(name: str):
     """(formula, plan kwargs, description, golden key) for a named workload."""
     if name == "banded300":
         f = wl.banded_3cnf(300, 1050, 37, seed=0)
-        return f, dict(kind="minfill", seed=0, rank_cap=27, block=4), \
+        return f, dict(kind="minfill", seed=0, rank_cap=27, block=4, slice_group=8), \
             "banded random 3-CNF, 300 vars, 1050 clauses (ratio 3.5), window 37, w~U(0.05,0.95), seed 0; " \
-            "seeded min-fill order (max storage rank 30; 29 once blocked by 4) sliced to rank 27, 8 slices", \
+            "seeded min-fill order (max storage rank 30; 29 once blocked by 4) sliced to rank 27, 8 slices, " \
+            "all 8 side by side in every launch", \
             "banded300_m1050_W37_s0"
     if name == "grid24":
         f = wl.grid_cnf(24, 24, 0.10, seed=0)
@@ -60,8 +61,9 @@ def workload(name: str):
             "w~U(0.1,0.9), seed 0, row-major sweep tree (storage rank 25), blocks of 5", "grid24x24_t0.10_s0"
     if name == "grid24_minfill":
         f = wl.grid_cnf(24, 24, 0.10, seed=0)
-        return f, dict(kind="minfill", seed=0, rank_cap=26, block=3), \
-            "grid CNF 24x24 lattice (as grid24), seeded min-fill tree (max rank 34) sliced to rank 26", \
+        return f, dict(kind="minfill", seed=0, rank_cap=26, block=3, slice_group=16), \
+            "grid CNF 24x24 lattice (as grid24), seeded min-fill tree (max rank 34) sliced to rank 26, " \
+            "16 slices side by side in every launch", \
             "grid24x24_t0.10_s0"
     if name == "grid12":
         f = wl.grid_cnf(12, 24, 0.10, seed=1)
@@ -215,7 +217,7 @@ def achievable(torch):
     return out
 
 
-def solo(W, torch, name, precision, steps, warmup, block=0, probes=None):
+def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_group=0):
     """Time `steps` whole solves of one workload, then attribute per-launch
     HIP-event time to kernels; returns a dict with the throughput, the
     roofline of the dominant kernel and the error against the oracle."""
@@ -224,6 +226,8 @@ def solo(W, torch, name, precision, steps, warmup, block=0, probes=None):
     net = W.Network.from_formula(f)
     blk = block if block > 0 else pkw.pop("block", 1)
     pkw.pop("block", None)
+    if slice_group > 0:
+        pkw["slice_group"] = slice_group
     t0 = time.perf_counter()
     plan = W.Plan(net, precision=precision, block=blk, **pkw)
     plan_s = time.perf_counter() - t0
@@ -306,7 +310,8 @@ def solo(W, torch, name, precision, steps, warmup, block=0, probes=None):
         "contraction_tflops": round(total_flops / (ms_step * 1e-3) / 1e12, 3),
         "algorithmic_gbs": round(total_bytes / (ms_step * 1e-3) / 1e9, 1),
         "max_rank": st["max_rank"], "max_rank_unsliced": st["max_rank_unsliced"], "n_nodes": st["n_nodes"],
-        "n_slices": n_slices, "class_hist": st["class_hist"], "plan_seconds": round(plan_s, 3),
+        "n_slices": n_slices, "slice_group": st["slice_group"], "class_hist": st["class_hist"],
+        "plan_seconds": round(plan_s, 3),
         "workspace_bytes": st["workspace_bytes"],
         "result": {"mantissa": v.mantissa, "exp2": v.exp2, "log2": v.log2_abs},
         "roofline": roof, "kernels": table,
@@ -437,6 +442,8 @@ def profile_only(W, torch, args):
     pkw = dict(pkw)
     block = args.block if args.block > 0 else pkw.pop("block", 1)
     pkw.pop("block", None)
+    if args.slice_group > 0:
+        pkw["slice_group"] = args.slice_group
     plan = W.Plan(W.Network.from_formula(f), precision=args.precision, block=block, **pkw)
     ws = W.workspace(plan)
     stream = torch.cuda.current_stream()
@@ -475,6 +482,7 @@ def main():
                          "batch512 | serve")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"], help="single-leg precision")
     ap.add_argument("--block", type=int, default=0, help="variables per elimination step (0 = workload default)")
+    ap.add_argument("--slice-group", type=int, default=0, help="slices per launch (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true", help="skip the achievable copy/GEMM probes")
     ap.add_argument("--queries", type=int, default=10000, help="serving: queries per rate")
@@ -524,7 +532,8 @@ def main():
 
     probes = None if args.no_probes else achievable(torch)
     if args.workload != "all":
-        r = solo(W, torch, args.workload, args.precision, args.steps, args.warmup, args.block, probes)
+        r = solo(W, torch, args.workload, args.precision, args.steps, args.warmup, args.block, probes,
+                 args.slice_group)
         out = {"metric": METRIC, "value": r["solves_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
                "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",

@@ -122,7 +122,11 @@ typedef struct {
                                 WMC_ERR_CAP_UNREACHABLE. */
     int32_t rank_cap;        /* bound on the largest storage rank; 0 = none */
     int32_t slice_objective; /* wmc_slice_objective: how ChooseSliceIndex picks the next variable */
-    int32_t reserved[6];
+    int32_t slice_group;     /* slices run side by side in every launch (the slices of Algorithm 3
+                                are independent): each has its own arena and meta table, so the
+                                workspace holds this many arenas; 0 or 1 = one slice at a time;
+                                capped at the slice count.  Results do not depend on it. */
+    int32_t reserved[5];
 } wmc_plan_options;
 
 /* Choice of the next sliced variable (Algorithm 3's ChooseSliceIndex, over
@@ -160,7 +164,7 @@ typedef struct {
     int64_t n_launches;         /* kernel launches per slice */
     double max_node_bytes;      /* largest single-node traffic */
     int32_t n_aux_vars;         /* auxiliary variables of factored long clauses */
-    int32_t reserved0;
+    int32_t slice_group;        /* slices per launch (workspace holds this many arenas) */
 } wmc_plan_info;
 
 wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *opts, wmc_plan_t **out);

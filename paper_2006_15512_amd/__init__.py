@@ -53,7 +53,8 @@ class wmc_plan_options(ctypes.Structure):
                 ("order", ctypes.POINTER(ctypes.c_int32)), ("order_len", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("parent", ctypes.POINTER(ctypes.c_int64)),
                 ("n_tree_nodes", ctypes.c_int64), ("mem_cap_bytes", ctypes.c_uint64),
-                ("rank_cap", ctypes.c_int32), ("slice_objective", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("rank_cap", ctypes.c_int32), ("slice_objective", ctypes.c_int32), ("slice_group", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class wmc_slice_state(ctypes.Structure):
@@ -70,7 +71,7 @@ class wmc_plan_info(ctypes.Structure):
                 ("bytes_per_slice", ctypes.c_double), ("peak_live_bytes", ctypes.c_double),
                 ("arena_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
                 ("class_hist", ctypes.c_int64 * N_CLASSES), ("n_launches", ctypes.c_int64),
-                ("max_node_bytes", ctypes.c_double), ("n_aux_vars", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("max_node_bytes", ctypes.c_double), ("n_aux_vars", ctypes.c_int32), ("slice_group", ctypes.c_int32)]
 
 
 _lib = None
@@ -210,7 +211,7 @@ class Plan:
     def __init__(self, net: Network, kind: str = "minfill", seed: int = 0,
                  order: Optional[Sequence[int]] = None, parent: Optional[Sequence[int]] = None,
                  mem_cap_bytes: int = 0, rank_cap: int = 0, precision: str = "fp64", block: int = 1,
-                 slice_objective: str = "memory"):
+                 slice_objective: str = "memory", slice_group: int = 1):
         o = wmc_plan_options()
         o.kind = {"minfill": TREE_MINFILL, "order": TREE_ORDER, "explicit": TREE_EXPLICIT}[kind]
         o.precision = {"fp64": FP64, "fp32": FP32_SCALED, "fp32_scaled": FP32_SCALED}[precision]
@@ -227,6 +228,7 @@ class Plan:
             o.n_tree_nodes = int(self._parent.size)
         o.mem_cap_bytes = int(mem_cap_bytes)
         o.rank_cap = int(rank_cap)
+        o.slice_group = int(slice_group)
         o.slice_objective = {"memory": SLICE_BY_MEMORY, "flops": SLICE_BY_FLOPS}[slice_objective]
         h = ctypes.c_void_p()
         _check(lib().wmc_plan(net._h, ctypes.byref(o), ctypes.byref(h)))

@@ -296,7 +296,7 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
                        (wmc_acc *)nullptr, 0);
     if (!B.leaves.empty())
         hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(B.leaf_work)), dim3(WMC_BLOCK), 0, st, L, (int)B.leaves.size(),
-                           (long long)B.leaf_work, w, arena, meta, 0ull,
+                           (long long)B.leaf_work, w, arena, meta, SliceGroup{0, 0, 0}, 0ull,
                            (const int *)(ws + B.off_tables) + B.leaf_tab_off);
     for (size_t k = 1; k < B.launches.size(); ++k) {
         const Launch &Ln = B.launches[k];
@@ -307,7 +307,7 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
         const int *tabs = (const int *)(ws + B.off_tables);
         if (Ln.count)
             hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first, Ln.count,
-                               (long long)Ln.work, arena, meta, tabs + B.wave_off[k]);
+                               (long long)Ln.work, arena, meta, SliceGroup{0, 0, 0}, tabs + B.wave_off[k]);
         const int tf = B.task_first[k];
         if (B.task_nk[k][4] > 0)
             launch_stream_multi<T>((const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf,

@@ -61,17 +61,23 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
     const int *TB = (const int *)(ws + P.off_tab);
     T *arena = (T *)(ws + P.off_arena);
     const int nt = (int)P.T.size();
-    for (long long eta = b; eta < e; ++eta) {
+    // slices run in groups of up to P.group, side by side in every launch
+    // (grid dimension z); per-slice results need one slice at a time
+    const long long G = per_slice ? 1 : (long long)P.group;
+    const SliceGroup sg{(long long)(P.arena_stride / sizeof(T)), (int)P.meta_stride, 0};
+    for (long long eta = b; eta < e; eta += G) {
+        const unsigned nz = (unsigned)std::min<long long>(G, e - eta);
         if (tm) {
             tm->k = 0;
             tm->mark();
         }
-        hipLaunchKernelGGL(k_begin, dim3((nt + WMC_BLOCK - 1) / WMC_BLOCK), dim3(WMC_BLOCK), 0, st, meta, nt, acc,
-                           eta == b && !keep_sum ? 1 : 0);
+        const long long nmeta = (long long)(nz - 1) * P.meta_stride + nt;
+        hipLaunchKernelGGL(k_begin, dim3((unsigned)((nmeta + WMC_BLOCK - 1) / WMC_BLOCK)), dim3(WMC_BLOCK), 0, st, meta,
+                           (int)nmeta, acc, eta == b && !keep_sum ? 1 : 0);
         if (tm) tm->mark();
         if (!P.leaves.empty())
-            hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(P.leaf_work)), dim3(WMC_BLOCK), 0, st, L,
-                               (int)P.leaves.size(), (long long)P.leaf_work, w, arena, meta,
+            hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(P.leaf_work), 1, nz), dim3(WMC_BLOCK), 0, st, L,
+                               (int)P.leaves.size(), (long long)P.leaf_work, w, arena, meta, sg,
                                (unsigned long long)eta, P.leaf_tab >= 0 ? TB + P.leaf_tab : nullptr);
         if (tm) tm->mark();
         for (size_t k = 1; k < P.launches.size(); ++k) {
@@ -80,20 +86,21 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
             StreamMfmaArgs ma;
             const int kern = solo_kernel<T>(P, k, &sa, &ma);
             if (kern == WMC_KERNEL_GEMM_P || kern == WMC_KERNEL_GEMM)
-                launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st);
+                launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st, sg, nz);
             else if (kern == WMC_KERNEL_STREAM_MFMA)
-                launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st);
+                launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st, 2048, sg, nz);
             else if ((kern == WMC_KERNEL_STREAM2 || kern == WMC_KERNEL_STREAM2_SPLIT) &&
                      launch_stream2<T>(sa, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
-                                      kern == WMC_KERNEL_STREAM2_SPLIT ? stream2_split_lanes<T>(P.nodes[(size_t)Ln.first].nk) : 0)) {
+                                      kern == WMC_KERNEL_STREAM2_SPLIT ? stream2_split_lanes<T>(P.nodes[(size_t)Ln.first].nk) : 0,
+                                      sg, nz)) {
             } else
-                hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first,
-                                   Ln.count, (long long)Ln.work, arena, meta,
+                hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work), 1, nz), dim3(WMC_BLOCK), 0, st, D + Ln.first,
+                                   Ln.count, (long long)Ln.work, arena, meta, sg,
                                    P.tab_off[k] >= 0 ? TB + P.tab_off[k] : nullptr);
             if (tm) tm->mark();
         }
         hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(1), 0, st, arena, (long long)P.T[(size_t)P.root].off, meta,
-                           P.root, acc);
+                           P.root, acc, (int)nz, sg.astride, sg.mstride);
         if (tm) tm->mark();
         HIP_TRY(hipGetLastError());
         if (tm) {

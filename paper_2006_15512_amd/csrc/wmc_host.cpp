@@ -1235,8 +1235,11 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     off += align_up(sizeof(wmc_acc), 256);
     P.off_w = off;
     off += align_up(sizeof(double) * 2 * (uint64_t)std::max(n, 1), 256);
+    if (o.slice_group < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: negative slice_group");
+    P.group = (int32_t)std::min<int64_t>(std::max(o.slice_group, 1), (int64_t)1 << P.sliced.size());
     P.off_meta = off;
-    off += align_up(sizeof(wmc_meta) * (uint64_t)std::max<size_t>(NT, 1), 256);
+    P.meta_stride = (int64_t)(align_up(sizeof(wmc_meta) * (uint64_t)std::max<size_t>(NT, 1), 256) / sizeof(wmc_meta));
+    off += (uint64_t)P.group * (uint64_t)P.meta_stride * sizeof(wmc_meta);
     P.off_leaf = off;
     off += align_up(sizeof(LeafDesc) * (uint64_t)std::max<size_t>(P.leaves.size(), 1), 256);
     P.off_node = off;
@@ -1281,7 +1284,8 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
         std::memcpy(P.desc_image.data() + (P.off_gemm - P.off_leaf), P.gemms.data(), sizeof(GemmDesc) * P.gemms.size());
     if (!tabs.empty())
         std::memcpy(P.desc_image.data() + (P.off_tab - P.off_leaf), tabs.data(), sizeof(int32_t) * tabs.size());
-    P.workspace_bytes = P.off_arena + align_up(P.arena_bytes, 256);
+    P.arena_stride = align_up(P.arena_bytes, 256);
+    P.workspace_bytes = P.off_arena + (uint64_t)P.group * P.arena_stride;
 
     // ---- statistics
     wmc_plan_info &I = P.info;
@@ -1316,6 +1320,7 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     I.arena_bytes = P.arena_bytes;
     I.workspace_bytes = P.workspace_bytes;
     I.n_launches = (int64_t)P.launches.size() + 2;  // + begin and finish kernels
+    I.slice_group = P.group;
     return WMC_OK;
 }
 

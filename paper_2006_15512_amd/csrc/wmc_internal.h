@@ -83,6 +83,12 @@ struct wmc_plan_t {
     uint64_t desc_bytes = 0;          // contiguous [off_leaf, off_arena) image
     std::vector<uint8_t> desc_image;
     uint64_t arena_bytes = 0, workspace_bytes = 0;
+    // slices per launch: slice z of a group uses the arena at
+    // off_arena + z * arena_stride bytes and the meta table at
+    // off_meta + z * meta_stride entries
+    int32_t group = 1;
+    uint64_t arena_stride = 0;   // bytes, 256-aligned
+    int64_t meta_stride = 0;     // wmc_meta entries
     wmc_plan_info info{};
 };
 

@@ -93,6 +93,23 @@ __device__ __forceinline__ unsigned long long pext_words(unsigned long long r, c
 template <typename T>
 __device__ __forceinline__ double ld(const T *p) { return (double)*p; }
 
+// Slices run side by side in one launch (Algorithm 3's slices are
+// independent): grid dimension z numbers the slice within the group, and
+// slice z of the group owns its own arena (astride elements apart) and meta
+// table (mstride entries apart).  A zero stride with one z leaves a kernel
+// on the single arena of a batch or a server.
+struct SliceGroup {
+    long long astride;
+    int mstride;
+    int pad;
+};
+
+#define WMC_ENTER_SLICE(arena, meta, sg)                       \
+    do {                                                       \
+        (arena) += (long long)blockIdx.z * (sg).astride;       \
+        (meta) += (long long)blockIdx.z * (long long)(sg).mstride; \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -117,8 +134,10 @@ static __global__ __attribute__((unused)) void k_begin(wmc_meta *meta, int nt, w
 template <typename T>
 __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict__ L, int nl, long long work,
                                                       const double *__restrict__ w, T *__restrict__ arena,
-                                                      wmc_meta *meta, unsigned long long eta,
+                                                      wmc_meta *meta, const SliceGroup sg, unsigned long long eta,
                                                       const int *__restrict__ wave_leaf = nullptr) {
+    WMC_ENTER_SLICE(arena, meta, sg);
+    eta += blockIdx.z;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
         // leaves start on wave boundaries: a wave's items belong to one leaf
@@ -166,8 +185,9 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict
 // multiple so that a wave never straddles two nodes.
 template <typename T>
 __global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict__ D, int nd, long long work,
-                                                     T *__restrict__ arena, wmc_meta *meta,
+                                                     T *__restrict__ arena, wmc_meta *meta, const SliceGroup sg,
                                                      const int *__restrict__ wave_node = nullptr) {
+    WMC_ENTER_SLICE(arena, meta, sg);
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
         // a wave's 64 items belong to one node (outputs are padded to waves):
@@ -259,7 +279,9 @@ __host__ __device__ inline int gemm_kc(int nk, int nn, int elem) {
 }
 
 template <typename T, int NT>
-__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T *__restrict__ arena, wmc_meta *meta) {
+__global__ void __launch_bounds__(256) k_gemm(const GemmDesc *__restrict__ G, T *__restrict__ arena, wmc_meta *meta,
+                                              const SliceGroup sg) {
+    WMC_ENTER_SLICE(arena, meta, sg);
     typedef typename Mfma<T>::acc_t acc_t;
     extern __shared__ char smem_raw[];
     T *Bs = (T *)smem_raw;
@@ -379,7 +401,8 @@ __host__ __device__ constexpr int gemm_tpw(int nt) { return (sizeof(T) == 8 && n
 // belong to rows, so that 16 lanes store 16 consecutive elements.
 template <typename T, int NT, int S, bool SW>
 __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, T *__restrict__ arena,
-                                                wmc_meta *meta) {
+                                                wmc_meta *meta, const SliceGroup sg) {
+    WMC_ENTER_SLICE(arena, meta, sg);
     typedef typename Mfma<T>::acc_t acc_t;
     extern __shared__ char smem_raw[];
     __shared__ GemmDesc sd;
@@ -569,7 +592,8 @@ static inline bool gemm_persistent(const GemmDesc &hd) {
 }
 
 template <typename T>
-static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_meta *meta, hipStream_t st) {
+static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_meta *meta, hipStream_t st,
+                        const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1) {
     const int N = 1 << hd.nn, K = 1 << hd.nk;
     const int NT = (N + 15) / 16;
     const unsigned long long tiles = 1ull << (hd.nm - 4);
@@ -584,12 +608,14 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
                 (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, padded) != hipSuccess || per_cu < 1)
                 per_cu = 2;
-            const unsigned long long total = (unsigned long long)cus * (unsigned long long)per_cu;
+            // resident workgroups, shared by the nz slices of the launch
+            unsigned long long total = (unsigned long long)cus * (unsigned long long)per_cu / nz;
+            if (total < 1) total = 1;
             unsigned long long per_beta = (total + (1ull << hd.nb) - 1) >> hd.nb;
             if (per_beta < 1) per_beta = 1;
             const unsigned long long tg = 4ull * (unsigned long long)gemm_tpw<T>(NTp);
             const unsigned long long pgroups = (tiles + tg - 1) / tg;
-            return dim3((unsigned)(pgroups < per_beta ? pgroups : per_beta), 1u << hd.nb);
+            return dim3((unsigned)(pgroups < per_beta ? pgroups : per_beta), 1u << hd.nb, nz);
         };
         // transposed tiles when C's lowest address bit is a row bit
         bool sw = false;
@@ -598,7 +624,7 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
 #define WMC_GP1(NTV, SV, SWV)                                                                                   \
     if (NTp == NTV && K / 4 == SV && sw == SWV) {                                                              \
         const void *fn = (const void *)&k_gemm_p<T, NTV, SV, SWV>;                                            \
-        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV, SWV>), grid_of(fn), dim3(256), padded, st, dd, arena, meta); \
+        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV, SWV>), grid_of(fn), dim3(256), padded, st, dd, arena, meta, sg); \
         return;                                                                                               \
     }
 #define WMC_GP(NTV, SV) WMC_GP1(NTV, SV, false) WMC_GP1(NTV, SV, true)
@@ -610,11 +636,11 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
     }
     const int KC = gemm_kc(hd.nk, hd.nn, (int)sizeof(T));
     const size_t smem = (size_t)KC * gemm_ldn(hd.nn, (int)sizeof(T)) * sizeof(T);
-    dim3 grid((unsigned)groups, 1u << hd.nb);
-    if (NT <= 1) hipLaunchKernelGGL((k_gemm<T, 1>), grid, dim3(256), smem, st, dd, arena, meta);
-    else if (NT <= 2) hipLaunchKernelGGL((k_gemm<T, 2>), grid, dim3(256), smem, st, dd, arena, meta);
-    else if (NT <= 4) hipLaunchKernelGGL((k_gemm<T, 4>), grid, dim3(256), smem, st, dd, arena, meta);
-    else hipLaunchKernelGGL((k_gemm<T, 8>), grid, dim3(256), smem, st, dd, arena, meta);
+    dim3 grid((unsigned)groups, 1u << hd.nb, nz);
+    if (NT <= 1) hipLaunchKernelGGL((k_gemm<T, 1>), grid, dim3(256), smem, st, dd, arena, meta, sg);
+    else if (NT <= 2) hipLaunchKernelGGL((k_gemm<T, 2>), grid, dim3(256), smem, st, dd, arena, meta, sg);
+    else if (NT <= 4) hipLaunchKernelGGL((k_gemm<T, 4>), grid, dim3(256), smem, st, dd, arena, meta, sg);
+    else hipLaunchKernelGGL((k_gemm<T, 8>), grid, dim3(256), smem, st, dd, arena, meta, sg);
 }
 
 // ---------------------------------------------------------------------------
@@ -695,7 +721,9 @@ __device__ __forceinline__ void load_chunk(const T *__restrict__ p, double *v) {
 // NP and NQ are compile-time so that the tile loops are straight-line code:
 // all loads issue before the first wait and no store waits on another.
 template <typename T, int NK, int NP, int NQ>
-__global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta) {
+__global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta,
+                                                 const SliceGroup sg) {
+    WMC_ENTER_SLICE(arena, meta, sg);
     extern __shared__ char smem_raw[];
     double *Os = (double *)smem_raw;  // 2^ro entries when O is staged, else none
     constexpr int K = 1 << NK;
@@ -823,7 +851,8 @@ __device__ __forceinline__ void group_reduce_scatter(double *v, int lane, int &f
 
 template <typename T, int NK, int NP, int NQ, int LG>
 __global__ void __launch_bounds__(256) k_stream2_split(const Stream2Args args, T *__restrict__ arena,
-                                                       wmc_meta *meta) {
+                                                       wmc_meta *meta, const SliceGroup sg) {
+    WMC_ENTER_SLICE(arena, meta, sg);
     constexpr int K = 1 << NK;
     constexpr int KL = K / LG;  // summed entries per lane and row
     constexpr int P = 1 << NP, Q = 1 << NQ, PQ = P * Q;
@@ -1049,7 +1078,8 @@ __device__ __forceinline__ void store_pair(float *p, float a, float b) { *(float
 
 template <typename T, int NK>
 __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, T *__restrict__ arena,
-                                                     wmc_meta *meta) {
+                                                     wmc_meta *meta, const SliceGroup sg) {
+    WMC_ENTER_SLICE(arena, meta, sg);
     typedef typename Mfma<T>::acc_t acc_t;
     constexpr int K = 1 << NK, KG = K / 4;
     constexpr int NBW = NK == 4 ? 4 : 2;  // blocks per wave (at most 16 / 8 per tile)
@@ -1275,13 +1305,15 @@ static inline bool stream_mfma_args(const NodeDesc &d, StreamMfmaArgs *a, int mi
 
 template <typename T>
 static void launch_stream_mfma(const StreamMfmaArgs &a, int nk, T *arena, wmc_meta *meta, hipStream_t st,
-                               unsigned cap = 2048) {
+                               unsigned cap = 2048, const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1) {
     const unsigned long long tiles = 1ull << (a.rc - a.nt);
-    unsigned long long blocks = tiles < cap ? tiles : cap;
+    // the cap holds for the whole launch: nz slices share it
+    const unsigned long long cz = cap / nz < 64 ? 64 : cap / nz;
+    unsigned long long blocks = tiles < cz ? tiles : cz;
     if (blocks >= 64) blocks &= ~7ull;  // whole XCD rounds
-    const dim3 g((unsigned)blocks), b(256);
-    if (nk == 4) hipLaunchKernelGGL((k_stream_mfma<T, 4>), g, b, 0, st, a, arena, meta);
-    else hipLaunchKernelGGL((k_stream_mfma<T, 5>), g, b, 0, st, a, arena, meta);
+    const dim3 g((unsigned)blocks, 1, nz), b(256);
+    if (nk == 4) hipLaunchKernelGGL((k_stream_mfma<T, 4>), g, b, 0, st, a, arena, meta, sg);
+    else hipLaunchKernelGGL((k_stream_mfma<T, 5>), g, b, 0, st, a, arena, meta, sg);
 }
 
 // Lanes per summed-index group for a single-node streaming launch (0: one
@@ -1297,13 +1329,16 @@ static inline int stream2_split_lanes(int nk) {
 
 // Returns false (nothing launched) if no instance covers the arguments.
 template <typename T>
-static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st, int lg = 0) {
+static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st, int lg = 0,
+                           const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1) {
     const unsigned long long threads = (1ull << (sa.rc - sa.np - sa.nq)) * (unsigned long long)(lg > 0 ? lg : 1);
     unsigned long long blocks = (threads + 255) / 256;
     // grid cap (measured on the sliced banded formula): FP32 runs fastest
     // with about one resident round of workgroups looping over the outputs,
     // FP64 with a few rounds
-    const unsigned long long cap = sizeof(T) == 4 ? 768 : 4096;
+    // (the cap holds for the whole launch: nz slices share it)
+    unsigned long long cap = (sizeof(T) == 4 ? 768 : 4096) / nz;
+    if (cap < 64) cap = 64;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     if (blocks >= 64) blocks = (blocks + 7) & ~7ull;  // whole XCD rounds; threads past the end idle
@@ -1313,12 +1348,12 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
     const unsigned long long outs_per_wg = (1ull << sa.rc) / blocks;
     if (a.o_lds && outs_per_wg < (16ull << sa.ro)) a.o_lds = 0;
     const size_t lds = a.o_lds ? sizeof(double) << a.ro : 0;
-    const dim3 g((unsigned)blocks), b(256);
+    const dim3 g((unsigned)blocks, 1, nz), b(256);
     if constexpr (sizeof(T) == 8) {
         if (lg > 0) {
 #define WMC_S2X(NKV, LGV, NPV, NQV)                                                                    \
     if (nk == NKV && lg == LGV && a.np == NPV && a.nq == NQV) {                                        \
-        hipLaunchKernelGGL((k_stream2_split<T, NKV, NPV, NQV, LGV>), g, b, 0, st, a, arena, meta);      \
+        hipLaunchKernelGGL((k_stream2_split<T, NKV, NPV, NQV, LGV>), g, b, 0, st, a, arena, meta, sg);  \
         return true;                                                                                   \
     }
 #define WMC_S2X_PQ(NKV, LGV)                                                                          \
@@ -1333,7 +1368,7 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
     }
 #define WMC_S2(NKV, NPV, NQV)                                                                  \
     if (nk == NKV && a.np == NPV && a.nq == NQV) {                                             \
-        hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, lds, st, a, arena, meta);      \
+        hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, lds, st, a, arena, meta, sg);  \
         return true;                                                                           \
     }
 #define WMC_S2_PQ(NKV)                                                                         \
@@ -1545,11 +1580,24 @@ static inline void split_stream(std::vector<NodeDesc> &generic, std::vector<Stre
     nk_first[4] = (int)tasks.size();
 }
 
-// Root of one slice: fold its value into the running sum (s + c) * 2^e.
+// Roots of nz consecutive slices (slice z's arena and meta table astride
+// elements and mstride entries after slice z-1's): fold each value, in
+// slice order, into the running sum (s + c) * 2^e.
+template <typename T>
+__device__ void finish_one(const T *__restrict__ arena, long long root_off, const wmc_meta *meta, int root,
+                           wmc_acc *acc);
+
 template <typename T>
 __global__ void k_finish(const T *__restrict__ arena, long long root_off, const wmc_meta *meta, int root,
-                         wmc_acc *acc) {
+                         wmc_acc *acc, int nz, long long astride, int mstride) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int z = 0; z < nz; ++z)
+        finish_one<T>(arena + (long long)z * astride, root_off, meta + (long long)z * mstride, root, acc);
+}
+
+template <typename T>
+__device__ void finish_one(const T *__restrict__ arena, long long root_off, const wmc_meta *meta, int root,
+                           wmc_acc *acc) {
     double v = (double)arena[root_off];
     long long e = meta[root].exp;
     if (v != 0.0) {

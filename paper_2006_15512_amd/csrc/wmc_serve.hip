@@ -527,11 +527,12 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     if (!leaves.empty())
         hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(leaf_work)), dim3(WMC_BLOCK), 0, st,
                            (const LeafDesc *)(stp + o_l), (int)leaves.size(), (long long)leaf_work,
-                           (const double *)(stp + o_w), arena, meta, 0ull, (const int *)(stp + o_lt));
+                           (const double *)(stp + o_w), arena, meta, SliceGroup{0, 0, 0}, 0ull,
+                           (const int *)(stp + o_lt));
     if (!nodes.empty())
         hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(node_work)), dim3(WMC_BLOCK), 0, st,
                            (const NodeDesc *)(stp + o_n), (int)nodes.size(), (long long)node_work, arena, meta,
-                           (const int *)(stp + o_wt));
+                           SliceGroup{0, 0, 0}, (const int *)(stp + o_wt));
     if (!tasks.empty())
         launch_stream_multi<T>((const StreamTask *)(stp + o_t), tasks.data(), nkf.data(), arena, meta, st,
                                (const int *)(stp + o_bt));

@@ -401,6 +401,60 @@ def test_slice_loop_checkpoint_resume_is_bit_exact(tmp_path, precision):
         W.contract_checkpointed(other, path)
 
 
+# ------------------------------------------------------------------ slices side by side
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_slice_groups_are_bit_identical(precision):
+    """Slices run G at a time in every launch (grid dimension z, one arena and
+    meta table per slice) give the bits of one slice at a time, for groups
+    that divide the slice count and groups that leave a partial last group;
+    slice ranges and the checkpointed loop split groups anywhere."""
+    f = wl.banded_3cnf(120, 400, 24, seed=1)
+    kw = dict(seed=1, rank_cap=16, precision=precision, block=2)
+    net = W.Network.from_formula(f)
+    p1 = W.Plan(net, **kw)
+    ns = p1.n_slices
+    assert ns >= 16
+    ref = W.wmc_contract(p1)
+    m, e = oracle.bucket(f)
+    assert rel(value_fraction(ref), Fraction(m) * Fraction(2) ** e) <= (1e-12 if precision == "fp64" else 1e-5)
+    for g in (2, 5, ns):
+        say(f"slice group {g} of {ns} ({precision})")
+        pg = W.Plan(net, slice_group=g, **kw)
+        st = pg.stats()
+        assert st["slice_group"] == g
+        assert st["workspace_bytes"] >= g * st["arena_bytes"]
+        v = W.wmc_contract(pg)
+        assert (v.mantissa, v.exp2) == (ref.mantissa, ref.exp2), g
+        a = W.wmc_contract_slices(pg, 0, 7)
+        a1 = W.wmc_contract_slices(p1, 0, 7)
+        assert (a.mantissa, a.exp2) == (a1.mantissa, a1.exp2), g
+        st_ = W.wmc_slice_state()
+        for chunk in (3, ns):
+            W.wmc_contract_resume(pg, st_, chunk)
+        r = W.wmc_contract_resume(pg, st_, 0)
+        assert (r.mantissa, r.exp2) == (ref.mantissa, ref.exp2), g
+    # the profile accounts the grouped launches in the same order
+    pg = W.Plan(net, slice_group=4, **kw)
+    v, ms = W.wmc_contract_profile(pg)
+    assert (v.mantissa, v.exp2) == (ref.mantissa, ref.exp2)
+    assert len(ms) == len(W.plan_launches(pg)[0]) and float(ms.sum()) > 0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_banded300_all_slices_in_one_group_vs_golden(precision, tol):
+    """The sliced 300-variable formula (8 slices) with every slice in each
+    launch, as the benchmark runs it, against the stored oracle value."""
+    with open(GOLDEN) as fh:
+        g = json.load(fh)["banded300_m1050_W37_s0"]
+    ref = Fraction(float.fromhex(g["mantissa_hex"])) * Fraction(2) ** g["exp2"]
+    f = wl.banded_3cnf(300, 1050, 37, seed=0)
+    say(f"banded300 group 8 {precision}")
+    p = W.Plan(W.Network.from_formula(f), seed=0, rank_cap=27, block=4, precision=precision, slice_group=8)
+    assert p.stats()["slice_group"] == 8
+    v = W.wmc_contract(p)
+    assert rel(value_fraction(v), ref) <= tol
+
+
 # ------------------------------------------------------------------ autotuned plan shape
 def test_autotune_plan_picks_fastest_and_caches(tmp_path):
     """The autotuner times every candidate block size, returns the fastest
