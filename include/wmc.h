@@ -45,7 +45,7 @@ typedef enum {
     WMC_ERR_DEVICE = 4,           /* a HIP call failed; message in wmc_last_error() */
     WMC_ERR_BUSY = 5,             /* server queue full */
     WMC_ERR_UNSUPPORTED = 6       /* rank too large, supplied tree over factored clauses,
-                                     sliced plan in a batch or server */
+                                     sliced plan in a server */
 } wmc_status;
 
 typedef enum { WMC_FP64 = 0, WMC_FP32_SCALED = 1 } wmc_precision;
@@ -312,8 +312,12 @@ wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, int64_t cap
  * The plans' launch lists are merged by index (launch k of one plan depends
  * only on its own launches < k), their descriptors concatenated into one
  * arena, meta table and weight vector, and every root finished by one kernel.
- * Plans must share a precision and be unsliced (WMC_ERR_UNSUPPORTED
- * otherwise).  The batch copies what it needs; the plans may be destroyed
+ * Plans must share a precision.  A sliced plan enters as one instance per
+ * slice (the slicing theorem: the slices are independent), each slice with
+ * its own arena region and its leaves filled for its slice bits, and its
+ * result is the FP64 compensated sum of its slices in slice order, as
+ * wmc_contract forms it; at most 2^20 slices per plan (WMC_ERR_UNSUPPORTED
+ * beyond).  The batch copies what it needs; the plans may be destroyed
  * afterwards.  A batch is used by one thread at a time (calls are
  * serialised internally). */
 typedef struct wmc_batch wmc_batch;
@@ -334,9 +338,10 @@ void wmc_batch_destroy(wmc_batch *b);
 /* Raw descriptor image of a batch (tools and tests): [leaf descriptors][node
  * descriptors][launch list][matrix-node descriptors][root tensor int32 x n]
  * [root offset int64 x n][streaming tasks][per launch: first task and the
- * start of each summed-rank group, 6 x int32]; info[0..9] = {n_leaves,
- * n_nodes, n_launches, arena_elems, n_instances, meta_total, elem_bytes,
- * n_gemms, n_vars_total, n_tasks}. */
+ * start of each summed-rank group, 6 x int32], with n root entries, one per
+ * slice of each plan; info[0..9] = {n_leaves, n_nodes, n_launches,
+ * arena_elems, n (root entries), meta_total, elem_bytes, n_gemms,
+ * n_vars_total, n_tasks}. */
 wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, uint64_t *needed,
                            int64_t *info /* 10 entries */);
 
@@ -406,6 +411,41 @@ wmc_status wmc_serve_poll(wmc_server *s, wmc_response *out, int32_t max, int32_t
 wmc_status wmc_serve(wmc_server *s, const wmc_request *trace, int64_t n, wmc_response *out);
 wmc_status wmc_serve_stats(const wmc_server *s, wmc_serve_info *out);
 void wmc_serve_destroy(wmc_server *s);
+
+/* ------------------------------------------------------------------ */
+/* Kernel tuning of the executor                                        */
+/* ------------------------------------------------------------------ */
+/* Launch shapes and kernel-family choices of wmc_contract's streaming
+ * nodes, one table per precision.  wmc_plan copies the table current for
+ * its precision into the plan, so a plan keeps the setting it was made
+ * with.  Any valid setting gives results within the precision's
+ * tolerance; the last bits can change where a node moves to another kernel
+ * family or its summed index is split differently (split_lanes).  The
+ * built-in defaults are measured MI355X settings; the autotuner replaces
+ * them with a table measured on the device at hand. */
+typedef struct {
+    int32_t stream2_grid_cap;        /* workgroups of one register-tiled streaming launch, 8..65536 */
+    int32_t stream_mfma_grid_cap;    /* workgroups of one matrix-core streaming launch, 8..65536 */
+    int32_t stream_mfma_min_bits;    /* row and column output bits a K >= 16 node needs to run on the
+                                        matrix cores, 2..8; 0 = never */
+    int32_t stream2_tile_bits;       /* output bits per operand side looped inside a thread, 0..2 */
+    int32_t stream2_min_thread_bits; /* looped bits are chosen so that 2^this threads remain, 0..30 */
+    int32_t stream2_low_bits;        /* lowest output bits numbering lanes in output order, 0..16 */
+    int32_t split_lanes;             /* FP64 nodes with K >= 16: lanes sharing one output's summed
+                                        index, 0 (one lane) or 4; ignored for FP32 */
+    int32_t multi_min_rank;          /* batches and servers: nodes of a merged step with at least
+                                        2^this outputs run on the multi-node streaming kernel, the
+                                        rest on the batched small-node kernel, 4..30 (taken from the
+                                        first plan of a batch, each registered structure's plan) */
+    int32_t reserved[8];
+} wmc_tuning;
+
+/* The current table for a precision (a copy). */
+wmc_status wmc_tuning_get(int32_t precision, wmc_tuning *out);
+/* Replace the table for a precision for plans made afterwards (process-wide,
+ * thread-safe); t == NULL restores the built-in defaults.
+ * INVALID_ARGUMENT for a field outside its range. */
+wmc_status wmc_tuning_set(int32_t precision, const wmc_tuning *t);
 
 /* Thread-local description of the last non-OK status on this thread. */
 const char *wmc_last_error(void);

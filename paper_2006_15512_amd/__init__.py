@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAP_UNRE
 FP64, FP32_SCALED = 0, 1
 TREE_MINFILL, TREE_ORDER, TREE_EXPLICIT = 0, 1, 2
 SLICE_BY_MEMORY, SLICE_BY_FLOPS = 0, 1
+_PREC = {"fp64": 0, "fp32": 1, "fp32_scaled": 1}
 MAX_RANK = 34
 MAX_SLICED = 40
 N_CLASSES = 4
@@ -55,6 +56,38 @@ class wmc_plan_options(ctypes.Structure):
                 ("n_tree_nodes", ctypes.c_int64), ("mem_cap_bytes", ctypes.c_uint64),
                 ("rank_cap", ctypes.c_int32), ("slice_objective", ctypes.c_int32), ("slice_group", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 5)]
+
+
+class wmc_tuning(ctypes.Structure):
+    _fields_ = [("stream2_grid_cap", ctypes.c_int32), ("stream_mfma_grid_cap", ctypes.c_int32),
+                ("stream_mfma_min_bits", ctypes.c_int32), ("stream2_tile_bits", ctypes.c_int32),
+                ("stream2_min_thread_bits", ctypes.c_int32), ("stream2_low_bits", ctypes.c_int32),
+                ("split_lanes", ctypes.c_int32), ("multi_min_rank", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+TUNING_FIELDS = [name for name, _ in wmc_tuning._fields_ if name != "reserved"]
+
+
+def tuning_get(precision: str = "fp64") -> Dict[str, int]:
+    """The executor tuning table that plans of this precision made now copy."""
+    t = wmc_tuning()
+    _check(lib().wmc_tuning_get(_PREC[precision], ctypes.byref(t)))
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
+
+
+def tuning_set(precision: str = "fp64", table: Optional[Dict[str, int]] = None) -> None:
+    """Replace the table for plans made afterwards (None: built-in defaults);
+    missing keys keep their current values."""
+    if table is None:
+        _check(lib().wmc_tuning_set(_PREC[precision], None))
+        return
+    cur = tuning_get(precision)
+    cur.update({k: int(v) for k, v in table.items() if k in TUNING_FIELDS})
+    t = wmc_tuning()
+    for k, v in cur.items():
+        setattr(t, k, v)
+    _check(lib().wmc_tuning_set(_PREC[precision], ctypes.byref(t)))
 
 
 class wmc_slice_state(ctypes.Structure):
@@ -117,6 +150,8 @@ def lib():
             "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
             "wmc_plan_kernels": [P, P, i64, P],
             "wmc_contract_noalloc": [P, P, P, ctypes.POINTER(wmc_value)],
+            "wmc_tuning_get": [i32, P],
+            "wmc_tuning_set": [i32, P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -205,6 +240,23 @@ def order_from_td(net: Network, td: str, root_bag: int = 0):
 # ---------------------------------------------------------------------------
 # planning
 # ---------------------------------------------------------------------------
+_TUNING_LOADED = False
+
+
+def _auto_tuning() -> None:
+    """Once per process, before the first plan: install the executor tuning
+    measured for this device, if one is stored (``autotune.load_tuning``);
+    WMC_NO_TUNING=1 keeps the built-in defaults."""
+    global _TUNING_LOADED
+    if _TUNING_LOADED:
+        return
+    _TUNING_LOADED = True
+    if os.environ.get("WMC_NO_TUNING"):
+        return
+    from .autotune import load_tuning
+    load_tuning()
+
+
 class Plan:
     """wmc_plan: contraction tree + slicing + layouts for one network."""
 
@@ -228,6 +280,7 @@ class Plan:
             o.n_tree_nodes = int(self._parent.size)
         o.mem_cap_bytes = int(mem_cap_bytes)
         o.rank_cap = int(rank_cap)
+        _auto_tuning()
         o.slice_group = int(slice_group)
         o.slice_objective = {"memory": SLICE_BY_MEMORY, "flops": SLICE_BY_FLOPS}[slice_objective]
         h = ctypes.c_void_p()

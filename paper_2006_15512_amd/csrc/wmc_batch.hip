@@ -1,6 +1,12 @@
 // Batched execution of many planned networks (many small formulas, or one
 // structure with many weight vectors) in shared launches.
 //
+// A sliced plan (Algorithm 3) enters as one instance per slice: the slices
+// share the plan's descriptors and weights, each has its own arena region
+// and meta entries, and its leaves read the slice's bits from a per-leaf
+// table.  The slices' roots are folded per plan on the host, in slice order,
+// with the same compensated sum as the solo executor's finish kernel.
+//
 // Launch k of one plan depends only on that plan's launches < k, so launch k
 // of every instance can run in the same kernel.  The batch concatenates the
 // instances' leaf and node descriptors (offsets patched into one arena, one
@@ -17,6 +23,42 @@
 struct BatchRes {
     double m;
     long long e;
+};
+
+// Running sum (s + c) * 2^e of normalised slice values m * 2^e, Neumaier
+// compensated, renormalised after every add: the arithmetic of the solo
+// executor's finish kernel, so a batch of slices gives the solo result.
+struct SliceSum {
+    double s = 0.0, c = 0.0;
+    long long e = 0;
+    void add(double v, long long ev) {
+        if (v == 0.0) return;
+        if (s == 0.0 && c == 0.0) {
+            s = v;
+            c = 0.0;
+            e = ev;
+            return;
+        }
+        if (ev > e) {
+            const long long d = e - ev;
+            const int di = d < -4000 ? -4000 : (int)d;
+            s = std::ldexp(s, di);
+            c = std::ldexp(c, di);
+            e = ev;
+        }
+        const long long d = ev - e;
+        const double t = std::ldexp(v, d < -4000 ? -4000 : (int)d);
+        const double r = s + t;
+        if (std::fabs(s) >= std::fabs(t)) c += (s - r) + t;
+        else c += (t - r) + s;
+        s = r;
+        if (s != 0.0) {
+            int k;
+            s = std::frexp(s, &k);
+            c = std::ldexp(c, -k);
+            e += k;
+        }
+    }
 };
 
 template <typename T>
@@ -45,7 +87,11 @@ __global__ void k_finish_batch(const T *__restrict__ arena, const long long *__r
 struct wmc_batch {
     int32_t precision = WMC_FP64;
     int32_t elem = 8;
-    int64_t n = 0;
+    int64_t n = 0;                     // plans (results)
+    int64_t n_inst = 0;                // instances: one per slice of each plan
+    std::vector<int64_t> inst_first;   // first instance of plan i (n + 1 entries)
+    std::vector<unsigned long long> leaf_eta;  // slice of each leaf's instance
+    uint64_t off_leaf_eta = 0;
     int64_t n_vars_total = 0;          // auxiliary variables included
     int64_t n_user_total = 0;          // caller weights: 2 * n_user of each plan, in plan order
     std::vector<int64_t> var_off;
@@ -106,8 +152,8 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
             wmc_set_error("wmc_batch_create: plans mix precisions");
             return WMC_ERR_INVALID_ARGUMENT;
         }
-        if (!plans[i]->sliced.empty()) {
-            wmc_set_error("wmc_batch_create: plan %lld is sliced (%zu variables); batches take unsliced plans",
+        if (plans[i]->sliced.size() > 20) {
+            wmc_set_error("wmc_batch_create: plan %lld has 2^%zu slices; batches take at most 2^20 per plan",
                           (long long)i, plans[i]->sliced.size());
             return WMC_ERR_UNSUPPORTED;
         }
@@ -117,36 +163,53 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         B->precision = plans[0]->precision;
         B->elem = plans[0]->elem;
         B->n = n;
-        std::vector<int64_t> abase((size_t)n), mbase((size_t)n);
+        // instances: slice eta of plan i is instance inst_first[i] + eta
+        B->inst_first.assign((size_t)n + 1, 0);
+        for (int64_t i = 0; i < n; ++i)
+            B->inst_first[(size_t)i + 1] = B->inst_first[(size_t)i] + ((int64_t)1 << plans[i]->sliced.size());
+        const int64_t ni = B->inst_first[(size_t)n];
+        B->n_inst = ni;
+        std::vector<int64_t> iplan((size_t)ni), ieta((size_t)ni);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = B->inst_first[(size_t)i]; j < B->inst_first[(size_t)i + 1]; ++j) {
+                iplan[(size_t)j] = i;
+                ieta[(size_t)j] = j - B->inst_first[(size_t)i];
+            }
+        std::vector<int64_t> abase((size_t)ni), mbase((size_t)ni);
         int64_t arena_elems = 0, meta = 0, vars = 0;
         size_t kmax = 0;
         for (int64_t i = 0; i < n; ++i) {
             const wmc_plan_t &P = *plans[i];
-            abase[(size_t)i] = arena_elems;
-            mbase[(size_t)i] = meta;
             B->var_off.push_back(vars);
             B->nvars.push_back(P.n);
             B->nuser.push_back(P.n_user);
             B->n_user_total += P.n_user;
             B->w.insert(B->w.end(), P.w.begin(), P.w.end());
-            arena_elems += (int64_t)bal(P.arena_bytes / (uint64_t)P.elem, 64);
-            meta += (int64_t)P.T.size();
             vars += P.n;
             kmax = std::max(kmax, P.launches.size());
+        }
+        for (int64_t j = 0; j < ni; ++j) {
+            const wmc_plan_t &P = *plans[iplan[(size_t)j]];
+            abase[(size_t)j] = arena_elems;
+            mbase[(size_t)j] = meta;
+            arena_elems += (int64_t)bal(P.arena_bytes / (uint64_t)P.elem, 64);
+            meta += (int64_t)P.T.size();
         }
         B->n_vars_total = vars;
         B->meta_total = std::max<int64_t>(meta, 1);
         // leaves
         B->launches.push_back({LAUNCH_LEAF, 0, 0, 0, 0});
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < ni; ++j) {
+            const int64_t i = iplan[(size_t)j];
             const wmc_plan_t &P = *plans[i];
             for (LeafDesc d : P.leaves) {
-                d.out += abase[(size_t)i];
-                d.tensor += (int)mbase[(size_t)i];
+                d.out += abase[(size_t)j];
+                d.tensor += (int)mbase[(size_t)j];
                 if (d.kind != WMC_LEAF_CLAUSE) d.var += (int)B->var_off[(size_t)i];
                 d.work_begin = B->leaf_work;
                 B->leaf_work += (int64_t)bal((uint64_t)1 << d.rank, WMC_WAVE);
                 B->leaves.push_back(d);
+                B->leaf_eta.push_back((unsigned long long)ieta[(size_t)j]);
             }
         }
         B->launches[0].work = B->leaf_work;
@@ -164,8 +227,9 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
             Launch merged{LAUNCH_NODES, (int32_t)B->nodes.size(), 0, 0, 0};
             std::vector<Launch> gemm_launches;
             std::vector<NodeDesc> step_nodes;
-            for (int64_t i = 0; i < n; ++i) {
-                const wmc_plan_t &P = *plans[i];
+            for (int64_t j = 0; j < ni; ++j) {
+                const wmc_plan_t &P = *plans[iplan[(size_t)j]];
+                const size_t i = (size_t)j;  // instance: arena and meta base
                 if (k >= P.launches.size()) continue;
                 const Launch &L = P.launches[k];
                 if (L.type == LAUNCH_GEMM) {
@@ -194,7 +258,7 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
             std::vector<StreamTask> tasks;
             std::vector<int> nkf;
             int64_t work = 0;
-            split_stream(step_nodes, tasks, nkf, work, WMC_STREAM_MIN_RANK);
+            split_stream(step_nodes, tasks, nkf, work, plans[0]->tune.multi_min_rank);
             merged.count = (int32_t)step_nodes.size();
             merged.work = work;
             B->nodes.insert(B->nodes.end(), step_nodes.begin(), step_nodes.end());
@@ -218,15 +282,15 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
                 B->btask_off.push_back(0);
             }
         }
-        for (int64_t i = 0; i < n; ++i) {
-            const wmc_plan_t &P = *plans[i];
-            B->roots.push_back(P.root < 0 ? -1 : P.root + (int)mbase[(size_t)i]);
-            B->root_off.push_back(P.root < 0 ? 0 : (long long)(P.T[(size_t)P.root].off + abase[(size_t)i]));
+        for (int64_t j = 0; j < ni; ++j) {
+            const wmc_plan_t &P = *plans[iplan[(size_t)j]];
+            B->roots.push_back(P.root < 0 ? -1 : P.root + (int)mbase[(size_t)j]);
+            B->root_off.push_back(P.root < 0 ? 0 : (long long)(P.T[(size_t)P.root].off + abase[(size_t)j]));
         }
         // workspace layout
         uint64_t off = 0;
         B->off_res = off;
-        off += bal(sizeof(BatchRes) * (uint64_t)n, 256);
+        off += bal(sizeof(BatchRes) * (uint64_t)ni, 256);
         B->off_w = off;
         off += bal(sizeof(double) * 2 * (uint64_t)std::max<int64_t>(vars, 1), 256);
         B->off_meta = off;
@@ -240,9 +304,11 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         B->off_tasks = off;
         off += bal(sizeof(StreamTask) * std::max<size_t>(B->tasks.size(), 1), 256);
         B->off_roots = off;
-        off += bal(sizeof(int) * (uint64_t)n, 256);
+        off += bal(sizeof(int) * (uint64_t)ni, 256);
         B->off_rootoff = off;
-        off += bal(sizeof(long long) * (uint64_t)n, 256);
+        off += bal(sizeof(long long) * (uint64_t)ni, 256);
+        B->off_leaf_eta = off;
+        off += bal(sizeof(unsigned long long) * std::max<size_t>(B->leaf_eta.size(), 1), 256);
         B->off_tables = off;
         off += bal(sizeof(int) * std::max<size_t>(B->tables.size(), 1), 256);
         B->off_arena = off;
@@ -261,6 +327,7 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         put(B->off_roots, B->roots.data(), sizeof(int) * B->roots.size());
         put(B->off_rootoff, B->root_off.data(), sizeof(long long) * B->root_off.size());
         put(B->off_tables, B->tables.data(), sizeof(int) * B->tables.size());
+        put(B->off_leaf_eta, B->leaf_eta.data(), sizeof(unsigned long long) * B->leaf_eta.size());
         *out = B;
     } catch (std::bad_alloc &) {
         wmc_set_error("wmc_batch_create: host allocation failed");
@@ -297,7 +364,8 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
     if (!B.leaves.empty())
         hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(B.leaf_work)), dim3(WMC_BLOCK), 0, st, L, (int)B.leaves.size(),
                            (long long)B.leaf_work, w, arena, meta, SliceGroup{0, 0, 0}, 0ull,
-                           (const int *)(ws + B.off_tables) + B.leaf_tab_off);
+                           (const int *)(ws + B.off_tables) + B.leaf_tab_off,
+                           (const unsigned long long *)(ws + B.off_leaf_eta));
     for (size_t k = 1; k < B.launches.size(); ++k) {
         const Launch &Ln = B.launches[k];
         if (Ln.type == LAUNCH_GEMM) {
@@ -313,8 +381,8 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
             launch_stream_multi<T>((const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf,
                                    B.task_nk[k].data(), arena, meta, st, tabs + B.btask_off[k]);
     }
-    hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n + 255) / 256)), dim3(256), 0, st, arena,
-                       (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n,
+    hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n_inst + 255) / 256)), dim3(256), 0, st, arena,
+                       (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n_inst,
                        (BatchRes *)(ws + B.off_res));
 }
 
@@ -385,10 +453,20 @@ extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, vo
         else batch_launches<float>(B, ws, st);
     }
     HIP_TRY(hipGetLastError());
-    std::vector<BatchRes> h((size_t)B.n);
-    HIP_TRY(hipMemcpyAsync(h.data(), ws + B.off_res, sizeof(BatchRes) * (size_t)B.n, hipMemcpyDeviceToHost, st));
+    std::vector<BatchRes> h((size_t)B.n_inst);
+    HIP_TRY(hipMemcpyAsync(h.data(), ws + B.off_res, sizeof(BatchRes) * (size_t)B.n_inst, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    for (int64_t i = 0; i < B.n; ++i) out[i] = make_value(h[(size_t)i].m, h[(size_t)i].e);
+    for (int64_t i = 0; i < B.n; ++i) {
+        const int64_t j0 = B.inst_first[(size_t)i], j1 = B.inst_first[(size_t)i + 1];
+        if (j1 - j0 == 1) {
+            out[i] = make_value(h[(size_t)j0].m, h[(size_t)j0].e);
+            continue;
+        }
+        // the slices of a sliced plan, in slice order
+        SliceSum acc;
+        for (int64_t j = j0; j < j1; ++j) acc.add(h[(size_t)j].m, h[(size_t)j].e);
+        out[i] = (acc.s == 0.0 && acc.c == 0.0) ? make_value(0.0, 0) : make_value(acc.s + acc.c, acc.e);
+    }
     return WMC_OK;
 }
 
@@ -414,7 +492,7 @@ extern "C" wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t ds
         info[1] = (int64_t)B.nodes.size();
         info[2] = (int64_t)B.launches.size();
         info[3] = (int64_t)(B.arena_bytes / (uint64_t)B.elem);
-        info[4] = B.n;
+        info[4] = B.n_inst;
         info[5] = B.meta_total;
         info[6] = B.elem;
         info[7] = (int64_t)B.gemms.size();

@@ -32,6 +32,13 @@ static hipError_t upload_weights(const wmc_plan_t &P, const double *weights, cha
     return e;
 }
 
+// Lanes per summed-index group of a streaming node of the plan: the tuned
+// split for FP64 nodes with K >= 16 (instances exist for K of 16 and 32).
+template <typename T>
+static inline int split_lanes_of(const wmc_plan_t &P, int nk) {
+    return sizeof(T) == 8 && nk >= 4 && nk <= 5 ? P.tune.split_lanes : 0;
+}
+
 // Kernel family that runs node launch k (1 <= k < P.launches.size()) of a
 // solo plan, with the streaming kernels' arguments filled in when one of
 // them is chosen.  The executor and wmc_plan_kernels share this choice.
@@ -42,9 +49,10 @@ static int solo_kernel(const wmc_plan_t &P, size_t k, Stream2Args *sa, StreamMfm
         return gemm_persistent<T>(P.gemms[(size_t)Ln.pad]) ? WMC_KERNEL_GEMM_P : WMC_KERNEL_GEMM;
     if (Ln.count == 1 && P.nodes[(size_t)Ln.first].cls == WMC_CLASS_STREAM) {
         const NodeDesc &d = P.nodes[(size_t)Ln.first];
-        if (stream_mfma_args(d, ma)) return WMC_KERNEL_STREAM_MFMA;
-        if (stream2_args(d, sa, 2, 14, 6))
-            return stream2_split_lanes<T>(d.nk) > 0 ? WMC_KERNEL_STREAM2_SPLIT : WMC_KERNEL_STREAM2;
+        const wmc_tuning &tu = P.tune;
+        if (tu.stream_mfma_min_bits > 0 && stream_mfma_args(d, ma, tu.stream_mfma_min_bits)) return WMC_KERNEL_STREAM_MFMA;
+        if (stream2_args(d, sa, tu.stream2_tile_bits, tu.stream2_min_thread_bits, tu.stream2_low_bits))
+            return split_lanes_of<T>(P, d.nk) > 0 ? WMC_KERNEL_STREAM2_SPLIT : WMC_KERNEL_STREAM2;
     }
     return WMC_KERNEL_NODES;
 }
@@ -88,11 +96,12 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
             if (kern == WMC_KERNEL_GEMM_P || kern == WMC_KERNEL_GEMM)
                 launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st, sg, nz);
             else if (kern == WMC_KERNEL_STREAM_MFMA)
-                launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st, 2048, sg, nz);
+                launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
+                                      (unsigned)P.tune.stream_mfma_grid_cap, sg, nz);
             else if ((kern == WMC_KERNEL_STREAM2 || kern == WMC_KERNEL_STREAM2_SPLIT) &&
                      launch_stream2<T>(sa, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
-                                      kern == WMC_KERNEL_STREAM2_SPLIT ? stream2_split_lanes<T>(P.nodes[(size_t)Ln.first].nk) : 0,
-                                      sg, nz)) {
+                                      kern == WMC_KERNEL_STREAM2_SPLIT ? split_lanes_of<T>(P, P.nodes[(size_t)Ln.first].nk) : 0,
+                                      sg, nz, (unsigned)P.tune.stream2_grid_cap)) {
             } else
                 hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work), 1, nz), dim3(WMC_BLOCK), 0, st, D + Ln.first,
                                    Ln.count, (long long)Ln.work, arena, meta, sg,

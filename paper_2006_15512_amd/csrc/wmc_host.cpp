@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <iterator>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -1324,6 +1325,56 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     return WMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Executor tuning tables (one per precision), copied into every plan
+// ---------------------------------------------------------------------------
+// Built-in MI355X settings, measured on the sliced banded formula and the
+// lattice: FP32 streaming launches run fastest with about one resident round
+// of workgroups, FP64 ones with a few; K >= 16 FP64 nodes off the matrix
+// cores split their summed index over groups of 4 lanes (with every K >= 16
+// node on the register-tiled path: 7.04 -> 7.82 solves/s; groups of 8:
+// 7.26), while FP32 (rows of 64 bytes) loses from the split.
+static wmc_tuning default_tuning(int32_t precision) {
+    wmc_tuning t;
+    std::memset(&t, 0, sizeof t);
+    t.stream2_grid_cap = precision == WMC_FP64 ? 4096 : 768;
+    t.stream_mfma_grid_cap = 2048;
+    t.stream_mfma_min_bits = 3;
+    t.stream2_tile_bits = 2;
+    t.stream2_min_thread_bits = 14;
+    t.stream2_low_bits = 6;
+    t.split_lanes = precision == WMC_FP64 ? 4 : 0;
+    t.multi_min_rank = 12;
+    return t;
+}
+
+static std::mutex g_tune_mu;
+static wmc_tuning g_tune[2] = {default_tuning(WMC_FP64), default_tuning(WMC_FP32_SCALED)};
+
+extern "C" wmc_status wmc_tuning_get(int32_t precision, wmc_tuning *out) {
+    if (!out || (precision != WMC_FP64 && precision != WMC_FP32_SCALED))
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_tuning_get: bad precision or NULL");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    *out = g_tune[precision];
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_tuning_set(int32_t precision, const wmc_tuning *t) {
+    if (precision != WMC_FP64 && precision != WMC_FP32_SCALED)
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_tuning_set: bad precision %d", precision);
+    wmc_tuning v = t ? *t : default_tuning(precision);
+    auto in = [](int32_t x, int32_t lo, int32_t hi) { return x >= lo && x <= hi; };
+    if (!in(v.stream2_grid_cap, 8, 65536) || !in(v.stream_mfma_grid_cap, 8, 65536) ||
+        !(v.stream_mfma_min_bits == 0 || in(v.stream_mfma_min_bits, 2, 8)) || !in(v.stream2_tile_bits, 0, 2) ||
+        !in(v.stream2_min_thread_bits, 0, 30) || !in(v.stream2_low_bits, 0, 16) ||
+        !(v.split_lanes == 0 || v.split_lanes == 4) || !in(v.multi_min_rank, 4, 30))
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_tuning_set: a field is outside its range");
+    std::memset(v.reserved, 0, sizeof v.reserved);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[precision] = v;
+    return WMC_OK;
+}
+
 extern "C" wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *opts, wmc_plan_t **out) {
     if (!out) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: out is NULL");
     *out = nullptr;
@@ -1339,6 +1390,10 @@ extern "C" wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *o
         P->precision = opts->precision;
         P->elem = opts->precision == WMC_FP64 ? 8 : 4;
         P->w = net->w;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            P->tune = g_tune[opts->precision];
+        }
         wmc_status st = WMC_OK;
         if (opts->kind == WMC_TREE_EXPLICIT) {
             if (net->n != net->n_user) {

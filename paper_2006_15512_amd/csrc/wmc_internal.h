@@ -86,6 +86,7 @@ struct wmc_plan_t {
     // slices per launch: slice z of a group uses the arena at
     // off_arena + z * arena_stride bytes and the meta table at
     // off_meta + z * meta_stride entries
+    wmc_tuning tune{};            // executor tuning copied at planning time
     int32_t group = 1;
     uint64_t arena_stride = 0;   // bytes, 256-aligned
     int64_t meta_stride = 0;     // wmc_meta entries

@@ -135,7 +135,8 @@ template <typename T>
 __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict__ L, int nl, long long work,
                                                       const double *__restrict__ w, T *__restrict__ arena,
                                                       wmc_meta *meta, const SliceGroup sg, unsigned long long eta,
-                                                      const int *__restrict__ wave_leaf = nullptr) {
+                                                      const int *__restrict__ wave_leaf = nullptr,
+                                                      const unsigned long long *__restrict__ leaf_eta = nullptr) {
     WMC_ENTER_SLICE(arena, meta, sg);
     eta += blockIdx.z;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -152,6 +153,8 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict
             }
         }
         const LeafDesc &d = L[lo];
+        // a batch of sliced plans gives every leaf the slice of its instance
+        const unsigned long long et = leaf_eta ? leaf_eta[lo] : eta;
         const long long e = g - d.work_begin;
         const bool valid = e < (1ll << d.rank);
         double v = 0.0;
@@ -160,13 +163,13 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict
                 unsigned a = 0;
                 for (int q = 0; q < d.k; ++q) {
                     int p = d.pos[q];
-                    unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((eta >> (-p - 1)) & 1ull);
+                    unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
                     a |= bit << q;
                 }
                 v = (d.taut || a != d.falsify) ? 1.0 : 0.0;
             } else if (d.kind == WMC_LEAF_WEIGHT) {
                 int p = d.pos[0];
-                unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((eta >> (-p - 1)) & 1ull);
+                unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
                 v = w[2 * d.var + bit];
             } else {
                 v = w[2 * d.var] + w[2 * d.var + 1];
@@ -1316,28 +1319,17 @@ static void launch_stream_mfma(const StreamMfmaArgs &a, int nk, T *arena, wmc_me
     else hipLaunchKernelGGL((k_stream_mfma<T, 5>), g, b, 0, st, a, arena, meta, sg);
 }
 
-// Lanes per summed-index group for a single-node streaming launch (0: one
-// lane per output tile), for nodes the matrix-core streaming kernel does not
-// take.  Measured on the sliced banded formula with every K >= 16 node on
-// this path: FP64 gains from groups of 4 (7.04 -> 7.82 solves/s; groups of
-// 8: 7.26); FP32 (rows of 64 bytes) and K = 8 lose (FP32 13.3 -> 11.7,
-// K = 8 with groups of 4: 2.93 -> 2.70).
-template <typename T>
-static inline int stream2_split_lanes(int nk) {
-    return sizeof(T) == 8 && nk >= 4 ? 4 : 0;
-}
-
 // Returns false (nothing launched) if no instance covers the arguments.
 template <typename T>
 static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st, int lg = 0,
-                           const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1) {
+                           const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1, unsigned grid_cap = 0) {
     const unsigned long long threads = (1ull << (sa.rc - sa.np - sa.nq)) * (unsigned long long)(lg > 0 ? lg : 1);
     unsigned long long blocks = (threads + 255) / 256;
     // grid cap (measured on the sliced banded formula): FP32 runs fastest
     // with about one resident round of workgroups looping over the outputs,
     // FP64 with a few rounds
     // (the cap holds for the whole launch: nz slices share it)
-    unsigned long long cap = (sizeof(T) == 4 ? 768 : 4096) / nz;
+    unsigned long long cap = (grid_cap ? grid_cap : (sizeof(T) == 4 ? 768u : 4096u)) / nz;
     if (cap < 64) cap = 64;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
@@ -1390,7 +1382,6 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
 // Tasks of one launch share NK.
 #define STREAM2_MULTI_THREADS 1024
 #define STREAM2_MULTI_LRUNS 4  // thread-index runs a merged-step task may use
-#define WMC_STREAM_MIN_RANK 12  // merged-step nodes with at least 2^12 outputs stream
 
 struct StreamTask {
     Stream2Args a;

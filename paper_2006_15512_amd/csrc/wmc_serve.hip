@@ -216,7 +216,7 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
         for (size_t q = 0; q < plan->nodes.size(); ++q) {
             const NodeDesc &d = plan->nodes[q];
             StreamTask t;
-            if (d.rc >= WMC_STREAM_MIN_RANK && d.cls != WMC_CLASS_GEMM && stream_task(d, &t)) {
+            if (d.rc >= plan->tune.multi_min_rank && d.cls != WMC_CLASS_GEMM && stream_task(d, &t)) {
                 s.task_of[q] = (int)s.tasks.size();
                 s.tasks.push_back(t);
             }

@@ -104,6 +104,37 @@ def test_batch_graph_replays_match_eager(instances):
         assert (frac(v) == 0) if r == 0 else rel(frac(v), r) <= 1e-12
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_batch_mixes_sliced_and_unsliced_plans(instances, precision, tol):
+    """Sliced plans (slices of uneven size: different slice counts and
+    sliced variables) batched with unsliced ones: every result against the
+    oracle, and each sliced plan's result equal to its solo wmc_contract (bit
+    for bit in FP64; the slices are summed in the same order with the same
+    compensated arithmetic)."""
+    fs, refs = instances
+    plans, want = [], []
+    for i, f in enumerate(fs[:12]):
+        r0 = W.Plan(W.Network.from_formula(f), seed=i).stats()["max_rank"]
+        cap = r0 - 1 - i % 3 if i % 3 else 0
+        plans.append(W.Plan(W.Network.from_formula(f), seed=i, rank_cap=cap, precision=precision))
+        want.append(refs[i])
+    ns = [p.n_slices for p in plans]
+    assert max(ns) >= 8 and min(ns) == 1 and len(set(ns)) >= 3
+    say(f"sliced batch {precision}: slices {ns}")
+    b = W.Batch(plans)
+    for flags in (0, W.BATCH_GRAPH, W.BATCH_GRAPH | W.BATCH_RESIDENT):
+        vals = b.contract(flags=flags)
+        for i, (v, r) in enumerate(zip(vals, want)):
+            got = frac(v)
+            assert (got == 0) if r == 0 else rel(got, r) <= tol, (i, ns[i])
+    for i, p in enumerate(plans):
+        solo = W.wmc_contract(p)
+        if precision == "fp64":
+            assert (solo.mantissa, solo.exp2) == (vals[i].mantissa, vals[i].exp2), i
+        else:
+            assert rel(frac(solo), frac(vals[i])) <= tol, i
+
+
 def test_batch_workspace_too_small(instances):
     import torch
     fs, _ = instances

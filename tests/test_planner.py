@@ -364,12 +364,20 @@ def test_emulated_batch_merging():
         assert (v == 0) if ref == 0 else rel_err(v, ref) < 1e-12
 
 
-def test_batch_rejects_sliced_and_mixed():
+def test_batch_takes_sliced_plans_as_slice_instances():
+    """A sliced plan enters a batch as one instance per slice: the image holds
+    one root per slice, each with its own arena region; mixed precisions are
+    refused."""
     f = wl.random_kcnf(14, 50, 3)
     net = W.Network.from_formula(f)
-    with pytest.raises(W.WmcError) as e:
-        W.Batch([W.Plan(net, seed=0), W.Plan(net, seed=0, rank_cap=4)])
-    assert e.value.status == 6
+    sliced = W.Plan(net, seed=0, rank_cap=4)
+    ns = sliced.stats()["n_slices"]
+    assert ns > 1
+    b = W.Batch([W.Plan(net, seed=0), sliced])
+    assert b.n == 2
+    _, info = b.image()
+    assert info["n_instances"] == 1 + ns
+    assert info["arena_elems"] >= ns * (sliced.stats()["arena_bytes"] // 8)
     with pytest.raises(W.WmcError) as e:
         W.Batch([W.Plan(net, seed=0), W.Plan(net, seed=0, precision="fp32")])
     assert e.value.status == 1
