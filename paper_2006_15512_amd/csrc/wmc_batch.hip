@@ -372,14 +372,21 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
             launch_gemm<T>(B.gemms[(size_t)Ln.pad], G + Ln.pad, arena, meta, st);
             continue;
         }
+        // the merged step's small nodes and streaming tasks in one launch
         const int *tabs = (const int *)(ws + B.off_tables);
-        if (Ln.count)
-            hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(Ln.work)), dim3(WMC_BLOCK), 0, st, D + Ln.first, Ln.count,
-                               (long long)Ln.work, arena, meta, SliceGroup{0, 0, 0}, tabs + B.wave_off[k]);
+        StepArgs a{};
         const int tf = B.task_first[k];
         if (B.task_nk[k][4] > 0)
-            launch_stream_multi<T>((const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf,
-                                   B.task_nk[k].data(), arena, meta, st, tabs + B.btask_off[k]);
+            step_stream_part(a, (const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf, B.task_nk[k].data(),
+                             tabs + B.btask_off[k]);
+        if (Ln.count) {
+            a.nodes = D + Ln.first;
+            a.nnodes = Ln.count;
+            a.node_work = Ln.work;
+            a.wave_node = tabs + B.wave_off[k];
+            a.nblocks = grid_for(Ln.work);
+        }
+        launch_step<T>(a, arena, meta, st);
     }
     hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n_inst + 255) / 256)), dim3(256), 0, st, arena,
                        (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n_inst,

@@ -131,16 +131,16 @@ static __global__ __attribute__((unused)) void k_begin(wmc_meta *meta, int nt, w
 
 // Leaf fill (Theorem 2): clause tables B_C restricted to the slice, weight
 // vectors [W(x,0), W(x,1)], or W(x,0)+W(x,1) for a variable in no clause.
+// The body takes its workgroup index and count, so that the fused step
+// kernel can run it on a share of its workgroups.
 template <typename T>
-__global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict__ L, int nl, long long work,
-                                                      const double *__restrict__ w, T *__restrict__ arena,
-                                                      wmc_meta *meta, const SliceGroup sg, unsigned long long eta,
-                                                      const int *__restrict__ wave_leaf = nullptr,
-                                                      const unsigned long long *__restrict__ leaf_eta = nullptr) {
-    WMC_ENTER_SLICE(arena, meta, sg);
-    eta += blockIdx.z;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
+__device__ __forceinline__ void leaves_body(const LeafDesc *__restrict__ L, int nl, long long work,
+                                            const double *__restrict__ w, T *__restrict__ arena, wmc_meta *meta,
+                                            unsigned long long eta, const int *__restrict__ wave_leaf,
+                                            const unsigned long long *__restrict__ leaf_eta, unsigned blk,
+                                            unsigned nblk) {
+    const long long stride = (long long)nblk * blockDim.x;
+    for (long long g = (long long)blk * blockDim.x + threadIdx.x; g < work; g += stride) {
         // leaves start on wave boundaries: a wave's items belong to one leaf
         int lo = 0;
         if (wave_leaf) {
@@ -182,17 +182,26 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict__ L, int nl, long long work,
+                                                      const double *__restrict__ w, T *__restrict__ arena,
+                                                      wmc_meta *meta, const SliceGroup sg, unsigned long long eta,
+                                                      const int *__restrict__ wave_leaf = nullptr,
+                                                      const unsigned long long *__restrict__ leaf_eta = nullptr) {
+    WMC_ENTER_SLICE(arena, meta, sg);
+    leaves_body<T>(L, nl, work, w, arena, meta, eta + blockIdx.z, wave_leaf, leaf_eta, blockIdx.x, gridDim.x);
+}
+
 // Pairwise contraction, any shape: one output entry per thread,
 // C[r] = 2^-(sA+sB) * sum_j A[(pext_A(r) << nk) | j] * B[(pext_B(r) << nk) | j].
 // A launch covers a run of nodes; each node's outputs are padded to a wave
 // multiple so that a wave never straddles two nodes.
 template <typename T>
-__global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict__ D, int nd, long long work,
-                                                     T *__restrict__ arena, wmc_meta *meta, const SliceGroup sg,
-                                                     const int *__restrict__ wave_node = nullptr) {
-    WMC_ENTER_SLICE(arena, meta, sg);
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < work; g += stride) {
+__device__ __forceinline__ void nodes_body(const NodeDesc *__restrict__ D, int nd, long long work,
+                                           T *__restrict__ arena, wmc_meta *meta, const int *__restrict__ wave_node,
+                                           unsigned blk, unsigned nblk) {
+    const long long stride = (long long)nblk * blockDim.x;
+    for (long long g = (long long)blk * blockDim.x + threadIdx.x; g < work; g += stride) {
         // a wave's 64 items belong to one node (outputs are padded to waves):
         // search with the wave's first item so the node index, and every
         // descriptor read, is wave-uniform (scalar loads)
@@ -227,6 +236,14 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict_
         publish_max(meta, d.tc, v);
         if (r == 0) meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WMC_BLOCK) k_nodes(const NodeDesc *__restrict__ D, int nd, long long work,
+                                                     T *__restrict__ arena, wmc_meta *meta, const SliceGroup sg,
+                                                     const int *__restrict__ wave_node = nullptr) {
+    WMC_ENTER_SLICE(arena, meta, sg);
+    nodes_body<T>(D, nd, work, arena, meta, wave_node, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1399,24 +1416,24 @@ static inline unsigned long long stream_task_blocks(const Stream2Args &a) {
 }
 
 template <typename T, int NK>
-__global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restrict__ tasks, int ntasks,
-                                                      T *__restrict__ arena, wmc_meta *meta,
-                                                      const int *__restrict__ block_task = nullptr) {
+__device__ __forceinline__ void stream_multi_body(const StreamTask *__restrict__ tasks, int ntasks,
+                                                  T *__restrict__ arena, wmc_meta *meta,
+                                                  const int *__restrict__ block_task, unsigned blk) {
     constexpr int K = 1 << NK;
     constexpr int KC = K < 4 ? K : 4;
     int lo = 0;
     if (block_task) {
-        lo = block_task[blockIdx.x];  // one load instead of a dependent search
+        lo = block_task[blk];  // one load instead of a dependent search
     } else {
         int hi = ntasks - 1;
         while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
-            if (tasks[mid].block_begin <= (long long)blockIdx.x) lo = mid; else hi = mid - 1;
+            if (tasks[mid].block_begin <= (long long)blk) lo = mid; else hi = mid - 1;
         }
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const Stream2Args &args = tasks[lo].a;
-    const unsigned long long lb = (unsigned long long)((long long)blockIdx.x - tasks[lo].block_begin);
+    const unsigned long long lb = (unsigned long long)((long long)blk - tasks[lo].block_begin);
     const int sS = scale_exp(meta[args.ts].maxbits);
     const int sO = scale_exp(meta[args.to].maxbits);
     const int se = -(sS + sO);
@@ -1466,6 +1483,64 @@ __global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restri
     }
     publish_max_block(meta, args.tc, vmax);
     if (lb == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
+}
+
+template <typename T, int NK>
+__global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restrict__ tasks, int ntasks,
+                                                      T *__restrict__ arena, wmc_meta *meta,
+                                                      const int *__restrict__ block_task = nullptr) {
+    stream_multi_body<T, NK>(tasks, ntasks, arena, meta, block_task, blockIdx.x);
+}
+
+// One merged step of a batch or a server in a single launch: workgroups
+// [0, sblocks) run the streaming tasks (their summed-index groups
+// concatenated in nk order, group k starting at workgroup gblock[k] and task
+// gtask[k]), the next nblocks the batched small nodes, the last lblocks the
+// leaf fills of the instances at their first launch.  The parts are
+// independent (each belongs to a different instance, or to different nodes
+// of one launch), so one launch replaces up to six.
+struct StepArgs {
+    const StreamTask *tasks;
+    const int *block_task;
+    long long gblock[5];
+    int gtask[5];
+    unsigned sblocks;
+    const NodeDesc *nodes;
+    const int *wave_node;
+    long long node_work;
+    int nnodes;
+    unsigned nblocks;
+    const LeafDesc *leaves;
+    const int *wave_leaf;
+    const unsigned long long *leaf_eta;
+    const double *w;
+    long long leaf_work;
+    int nleaves;
+    unsigned lblocks;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_step(const StepArgs a, T *__restrict__ arena, wmc_meta *meta) {
+    const unsigned bx = blockIdx.x;
+    if (bx < a.sblocks) {
+        int k = 0;
+        while (k < 3 && (long long)bx >= a.gblock[k + 1]) ++k;
+        const StreamTask *t = a.tasks + a.gtask[k];
+        const int nt = a.gtask[k + 1] - a.gtask[k];
+        const int *bt = a.block_task ? a.block_task + a.gblock[k] : nullptr;
+        const unsigned blk = bx - (unsigned)a.gblock[k];
+        switch (k) {
+        case 0: stream_multi_body<T, 0>(t, nt, arena, meta, bt, blk); break;
+        case 1: stream_multi_body<T, 1>(t, nt, arena, meta, bt, blk); break;
+        case 2: stream_multi_body<T, 2>(t, nt, arena, meta, bt, blk); break;
+        default: stream_multi_body<T, 3>(t, nt, arena, meta, bt, blk); break;
+        }
+    } else if (bx < a.sblocks + a.nblocks) {
+        nodes_body<T>(a.nodes, a.nnodes, a.node_work, arena, meta, a.wave_node, bx - a.sblocks, a.nblocks);
+    } else {
+        leaves_body<T>(a.leaves, a.nleaves, a.leaf_work, a.w, arena, meta, 0ull, a.wave_leaf, a.leaf_eta,
+                       bx - a.sblocks - a.nblocks, a.lblocks);
+    }
 }
 
 static inline bool stream_task(const NodeDesc &d, StreamTask *t) {
@@ -1535,6 +1610,29 @@ static void launch_stream_multi(const StreamTask *dev_tasks, const StreamTask *h
         default: hipLaunchKernelGGL((k_stream_multi<T, 3>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
         }
     }
+}
+
+// Fill the streaming part of a fused step from the nk groups of its tasks
+// (nk_first[k] .. nk_first[k+1] have nk == k; host copies give the sizes).
+static inline void step_stream_part(StepArgs &a, const StreamTask *dev_tasks, const StreamTask *host_tasks,
+                                    const int *nk_first, const int *dev_block_task) {
+    a.tasks = dev_tasks;
+    a.block_task = dev_block_task;
+    unsigned long long blocks = 0;
+    for (int k = 0; k < 4; ++k) {
+        a.gblock[k] = (long long)blocks;
+        a.gtask[k] = nk_first[k];
+        blocks += stream_multi_blocks(host_tasks, nk_first[k], nk_first[k + 1]);
+    }
+    a.gblock[4] = (long long)blocks;
+    a.gtask[4] = nk_first[4];
+    a.sblocks = (unsigned)blocks;
+}
+
+template <typename T>
+static void launch_step(const StepArgs &a, T *arena, wmc_meta *meta, hipStream_t st) {
+    const unsigned g = a.sblocks + a.nblocks + a.lblocks;
+    if (g) hipLaunchKernelGGL(k_step<T>, dim3(g), dim3(256), 0, st, a, arena, meta);
 }
 
 // Split a merged node list into (generic nodes, streaming tasks grouped by

@@ -524,18 +524,27 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     if (!clears.empty())
         hipLaunchKernelGGL(k_clear_meta, dim3((unsigned)clears.size()), dim3(256), 0, st,
                            (const ClearRange *)(stp + o_c), meta);
-    if (!leaves.empty())
-        hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(leaf_work)), dim3(WMC_BLOCK), 0, st,
-                           (const LeafDesc *)(stp + o_l), (int)leaves.size(), (long long)leaf_work,
-                           (const double *)(stp + o_w), arena, meta, SliceGroup{0, 0, 0}, 0ull,
-                           (const int *)(stp + o_lt));
-    if (!nodes.empty())
-        hipLaunchKernelGGL(k_nodes<T>, dim3(grid_for(node_work)), dim3(WMC_BLOCK), 0, st,
-                           (const NodeDesc *)(stp + o_n), (int)nodes.size(), (long long)node_work, arena, meta,
-                           SliceGroup{0, 0, 0}, (const int *)(stp + o_wt));
+    // leaf fills of newly admitted requests, small nodes and streaming tasks
+    // of the others: independent work, one launch
+    StepArgs a{};
     if (!tasks.empty())
-        launch_stream_multi<T>((const StreamTask *)(stp + o_t), tasks.data(), nkf.data(), arena, meta, st,
-                               (const int *)(stp + o_bt));
+        step_stream_part(a, (const StreamTask *)(stp + o_t), tasks.data(), nkf.data(), (const int *)(stp + o_bt));
+    if (!nodes.empty()) {
+        a.nodes = (const NodeDesc *)(stp + o_n);
+        a.nnodes = (int)nodes.size();
+        a.node_work = (long long)node_work;
+        a.wave_node = (const int *)(stp + o_wt);
+        a.nblocks = grid_for(node_work);
+    }
+    if (!leaves.empty()) {
+        a.leaves = (const LeafDesc *)(stp + o_l);
+        a.nleaves = (int)leaves.size();
+        a.leaf_work = (long long)leaf_work;
+        a.w = (const double *)(stp + o_w);
+        a.wave_leaf = (const int *)(stp + o_lt);
+        a.lblocks = grid_for(leaf_work);
+    }
+    launch_step<T>(a, arena, meta, st);
     for (size_t q = 0; q < gemms.size(); ++q)
         launch_gemm<T>(gemms[q], (const GemmDesc *)(stp + o_g) + q, arena, meta, st);
     ServeRes *res = (ServeRes *)(v->dev + v->off_res);
