@@ -34,8 +34,21 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (-O2 -fopenmp) into oracle/liboracle.so."""
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the C oracle with gcc (-O2 -fopenmp) into oracle/liboracle.so;
+    with ``sanitize``, an AddressSanitizer + UndefinedBehaviorSanitizer build
+    into oracle/liboracle_san.so (load it with WMC_ORACLE_LIBRARY and the
+    sanitizer runtime preloaded)."""
+    if sanitize:
+        tmp = _SAN_LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                               "-fno-sanitize-recover=undefined", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wno-unused-result", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SAN_LIB)
+        return _SAN_LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
@@ -46,20 +59,25 @@ def build(force: bool = True) -> str:
 
 def _load():
     global _lib
+    if _lib is None and os.environ.get("WMC_ORACLE_LIBRARY"):
+        _lib = _bind(ctypes.CDLL(os.environ["WMC_ORACLE_LIBRARY"]))
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        lib.oracle_brute.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P]
-        lib.oracle_brute.restype = ctypes.c_int
-        lib.oracle_bucket.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P,
-                                      ctypes.c_int32, P, P, P]
-        lib.oracle_bucket.restype = ctypes.c_int
-        lib.oracle_minfill.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P]
-        lib.oracle_minfill.restype = ctypes.c_int
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _bind(lib):
+    P = ctypes.c_void_p
+    lib.oracle_brute.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P]
+    lib.oracle_brute.restype = ctypes.c_int
+    lib.oracle_bucket.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P,
+                                  ctypes.c_int32, P, P, P]
+    lib.oracle_bucket.restype = ctypes.c_int
+    lib.oracle_minfill.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P]
+    lib.oracle_minfill.restype = ctypes.c_int
+    return lib
 
 
 class OracleError(RuntimeError):

@@ -19,7 +19,9 @@ from typing import Dict, List, NamedTuple, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwmc.so")
+# WMC_LIBRARY names another build of the same library (the sanitizer build
+# of the host code: python -m paper_2006_15512_amd.build --sanitize)
+LIB_PATH = os.environ.get("WMC_LIBRARY") or os.path.join(_HERE, "libwmc.so")
 
 WMC_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAP_UNREACHABLE",
@@ -206,6 +208,9 @@ class Network:
         self._h = h
         self.n = int(n)
         self.m = len(clauses)
+        # kept for checkpoint identities (the library holds its own copies)
+        self.clauses = [list(map(int, c)) for c in clauses]
+        self.weights = w.copy()
 
     @classmethod
     def from_formula(cls, f) -> "Network":
@@ -435,17 +440,32 @@ def wmc_contract_resume(plan: Plan, state: wmc_slice_state, count: int, weights=
     return Value.of(out)
 
 
+def checkpoint_identity(plan: Plan, weights=None) -> Dict:
+    """What a checkpointed slice loop's running sum depends on: the plan's
+    slices and precision, the formula's clauses and the weights used."""
+    import hashlib
+    st = plan.stats()
+    h = hashlib.sha256()
+    for c in plan.net.clauses:
+        h.update(np.asarray(c, dtype=np.int32).tobytes() + b";")
+    wsrc = plan.net.weights if weights is None else weights
+    wd = hashlib.sha256(np.ascontiguousarray(np.asarray(wsrc, dtype=np.float64).reshape(-1)).tobytes()).hexdigest()
+    return {"n_slices": int(st["n_slices"]), "sliced_vars": [int(x) for x in st["sliced_vars"]],
+            "n_vars": int(st["n_vars"]), "n_clauses": int(st["n_clauses"]), "precision": plan.precision,
+            "clauses_sha256": h.hexdigest(), "weights_sha256": wd}
+
+
 def contract_checkpointed(plan: Plan, path: str, chunk: int = 1, weights=None, ws=None, stream=None,
                           stop_after: Optional[int] = None) -> Optional[Value]:
     """The slice loop in chunks of ``chunk`` slices with its running sum saved
     to ``path`` (JSON, written atomically) after every chunk; an existing file
     resumes the loop where it stopped.  ``stop_after`` ends the call after
-    that many chunks (returns None if slices remain).  The file records the
-    plan's slice count and sliced variables and is refused for another plan."""
+    that many chunks (returns None if slices remain).  The file records what
+    the running sum depends on (slice count, sliced variables, precision, a
+    digest of the clauses and of the weights actually used) and is refused
+    for any other plan, formula or weight vector."""
     import json
-    st = plan.stats()
-    ident = {"n_slices": int(st["n_slices"]), "sliced_vars": [int(x) for x in st["sliced_vars"]],
-             "n_vars": int(st["n_vars"]), "n_clauses": int(st["n_clauses"])}
+    ident = checkpoint_identity(plan, weights)
     state = wmc_slice_state()
     if os.path.exists(path):
         with open(path) as fh:

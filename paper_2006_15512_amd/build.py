@@ -1,6 +1,7 @@
 """Build libwmc.so in-tree for gfx950.
 
-    python -m paper_2006_15512_amd.build
+    python -m paper_2006_15512_amd.build              # libwmc.so
+    python -m paper_2006_15512_amd.build --sanitize   # + _build/san/libwmc.so
 
 The host planner (C++17) is compiled with g++, the kernels with hipcc for
 gfx950 only; packed-FP32 instructions are disabled for all device code.
@@ -29,6 +30,30 @@ def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
+
+
+SAN_DIR = os.path.join(BUILD_DIR, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libwmc.so")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """The host planner (wmc_host.cpp) under AddressSanitizer and
+    UndefinedBehaviorSanitizer, linked with the ordinary device objects into
+    _build/san/libwmc.so (a CPU build for the planner tests: run them with
+    WMC_LIBRARY pointing at it and the sanitizer runtime preloaded).  The
+    device code is not instrumented."""
+    build(verbose)
+    os.makedirs(SAN_DIR, exist_ok=True)
+    inc = ["-I", CSRC, "-I", os.path.join(ROOT, "include")]
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
+    host_o = os.path.join(SAN_DIR, "wmc_host.cpp.o")
+    _run(["g++", "-std=c++17", "-O1", "-g", *san, "-fPIC", *inc, "-c", os.path.join(CSRC, "wmc_host.cpp"),
+          "-o", host_o], verbose)
+    dev_o = [os.path.join(BUILD_DIR, s + ".o") for s in DEVICE_SOURCES]
+    rocm = os.path.dirname(os.path.dirname(HIPCC))
+    _run(["g++", "-shared", *san, host_o, *dev_o, "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+          "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", SAN_LIB], verbose)
+    return SAN_LIB
 
 
 def build(verbose: bool = False, debug: bool = False) -> str:
@@ -62,4 +87,7 @@ def build(verbose: bool = False, debug: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, debug="--debug" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv, debug="--debug" in sys.argv))

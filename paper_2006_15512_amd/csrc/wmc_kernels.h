@@ -167,12 +167,23 @@ __device__ __forceinline__ void leaves_body(const LeafDesc *__restrict__ L, int 
                     a |= bit << q;
                 }
                 v = (d.taut || a != d.falsify) ? 1.0 : 0.0;
-            } else if (d.kind == WMC_LEAF_WEIGHT) {
-                int p = d.pos[0];
-                unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
-                v = w[2 * d.var + bit];
             } else {
-                v = w[2 * d.var] + w[2 * d.var + 1];
+                // a weight leaf carries its own power-of-two exponent, as every
+                // intermediate does: stored entries have magnitude below 1, so
+                // any finite weight fits the storage type (FP32 included)
+                const double w0 = w[2 * d.var], w1 = w[2 * d.var + 1];
+                if (d.kind == WMC_LEAF_WEIGHT) {
+                    int p = d.pos[0];
+                    unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
+                    v = bit ? w1 : w0;
+                } else {
+                    v = w0 + w1;
+                }
+                const double mx = d.kind == WMC_LEAF_WEIGHT ? fmax(fabs(w0), fabs(w1)) : fabs(v);
+                int ex = 0;
+                if (mx > 0.0) frexp(mx, &ex);
+                v = ldexp(v, -ex);
+                if (e == 0) meta[d.tensor].exp = ex;
             }
             T s = (T)v;
             arena[d.out + e] = s;

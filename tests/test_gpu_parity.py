@@ -76,6 +76,23 @@ def test_mixed_small(precision, tol):
             assert rel(got, ref) <= tol, (s, float(got), float(ref))
 
 
+@pytest.mark.parametrize("scale", [1e50, 1e-50, 1e300])
+def test_fp32_weights_beyond_the_fp32_range(scale):
+    """Weights far outside FP32's range (above its largest or below its
+    smallest normal number): each weight leaf carries a power-of-two
+    exponent, so scaled FP32 still matches the oracle."""
+    f = wl.random_kcnf(16, 50, seed=5)
+    rng = np.random.default_rng(11)
+    Wt = np.stack([rng.uniform(0.1, 0.9, f.n), rng.uniform(0.1, 0.9, f.n)], axis=1) * scale
+    g = f.with_weights(Wt)
+    m, e = oracle.bucket(g)
+    ref = Fraction(m) * Fraction(2) ** e
+    for prec, tol in (("fp32", 1e-5), ("fp64", 1e-12)):
+        v = W.wmc_contract(W.Plan(W.Network.from_formula(g), seed=0, precision=prec))
+        assert v.mantissa != 0.0 and math.isfinite(v.mantissa)
+        assert rel(value_fraction(v), ref) <= tol, (prec, scale)
+
+
 def test_negative_weights():
     for s in range(40):
         f = wl.random_mixed(s, n_max=12, m_max=20, negative=True)
@@ -453,6 +470,32 @@ def test_banded300_all_slices_in_one_group_vs_golden(precision, tol):
     assert p.stats()["slice_group"] == 8
     v = W.wmc_contract(p)
     assert rel(value_fraction(v), ref) <= tol
+
+
+# ------------------------------------------------------------------ Algorithm 1's anytime loop
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_anytime_plan_on_device_vs_oracle(precision, tol):
+    """The anytime planning loop (Algorithm 1) with the execution-time model
+    read from the rates measured on this device: the plan it returns runs
+    on the GPU and matches the oracle, and its measured time is within an
+    order of magnitude of the prediction."""
+    import time
+    from paper_2006_15512_amd.autotune import anytime_plan, measured_rates, time_cost
+    rates = measured_rates(precision)
+    assert rates is not None, "no measured rates stored for this device"
+    f = wl.banded_3cnf(160, 560, 24, seed=2)
+    p, rep = anytime_plan(f, alpha=1e-3, precision=precision, blocks=(1, 2, 3, 4), rank_cap=18, max_candidates=8)
+    say(f"anytime {precision}: {rep['candidates']} candidates, predicted {rep['predicted_seconds'] * 1e3:.3f} ms")
+    assert abs(time_cost(p) - rep["predicted_seconds"]) <= 1e-9 * rep["predicted_seconds"]
+    ws = W.workspace(p)
+    v = W.wmc_contract(p, None, ws)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        v = W.wmc_contract(p, None, ws)
+    dt = (time.perf_counter() - t0) / 3
+    m, e = oracle.bucket(f)
+    assert rel(value_fraction(v), Fraction(m) * Fraction(2) ** e) <= tol
+    assert rep["predicted_seconds"] / 10 <= dt <= rep["predicted_seconds"] * 10, (dt, rep["predicted_seconds"])
 
 
 # ------------------------------------------------------------------ autotuned plan shape

@@ -504,3 +504,29 @@ def test_time_cost_grows_with_slices():
     b = W.Plan(net, seed=1, rank_cap=a.stats()["max_rank"] - 3)
     assert b.stats()["n_slices"] >= 8
     assert time_cost(b) > time_cost(a)
+
+
+def test_checkpoint_refuses_other_weights_precision_or_formula(tmp_path):
+    """A saved slice-loop checkpoint resumes only the same plan, formula,
+    precision and weights: any other is refused before anything runs."""
+    import json
+    f = wl.banded_3cnf(60, 200, 14, seed=3)
+    p = W.Plan(W.Network.from_formula(f), seed=0, rank_cap=8)
+    path = str(tmp_path / "ck.json")
+    with open(path, "w") as fh:
+        json.dump({"plan": W.checkpoint_identity(p), "s": (0.5).hex(), "c": (0.0).hex(), "e": 0,
+                   "next_slice": 1, "n_slices": p.n_slices}, fh)
+    w2 = np.array(f.weights, dtype=np.float64).copy()
+    w2[0, 1] = 0.25
+    w2[0, 0] = 0.75
+    with pytest.raises(ValueError):
+        W.contract_checkpointed(p, path, weights=w2)
+    p32 = W.Plan(W.Network.from_formula(f), seed=0, rank_cap=8, precision="fp32")
+    with pytest.raises(ValueError):
+        W.contract_checkpointed(p32, path)
+    g = wl.banded_3cnf(60, 200, 14, seed=4)  # same shape, other clauses
+    pg = W.Plan(W.Network.from_formula(g.with_weights(f.weights)), seed=0, rank_cap=8)
+    if pg.n_slices == p.n_slices and pg.stats()["sliced_vars"] == p.stats()["sliced_vars"]:
+        with pytest.raises(ValueError):
+            W.contract_checkpointed(pg, path)
+    assert W.checkpoint_identity(pg)["clauses_sha256"] != W.checkpoint_identity(p)["clauses_sha256"]
