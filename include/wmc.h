@@ -53,7 +53,9 @@ typedef enum { WMC_FP64 = 0, WMC_FP32_SCALED = 1 } wmc_precision;
 typedef enum {
     WMC_TREE_MINFILL = 0,  /* seeded min-fill elimination order -> bucket tree */
     WMC_TREE_ORDER = 1,    /* caller-supplied elimination order -> bucket tree */
-    WMC_TREE_EXPLICIT = 2  /* caller-supplied contraction tree (parent array) */
+    WMC_TREE_EXPLICIT = 2, /* caller-supplied contraction tree (parent array) */
+    WMC_TREE_NETWORK = 3   /* the elimination order a network built by wmc_build_network_td
+                              carries (FactorTree) -> bucket tree */
 } wmc_tree_kind;
 
 #define WMC_MAX_CLAUSE 24   /* distinct variables of a clause tensor */
@@ -93,6 +95,32 @@ typedef struct wmc_plan_t wmc_plan_t;
  * never materialised. */
 wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
                              const int32_t *lits, const double *weights, wmc_network **out);
+
+/* FactorTree (Theorem 3; the FactorTree paragraph of Section 3.3): the
+ * network of Theorem 2 factored along a tree decomposition of the formula's
+ * INCIDENCE graph, with the elimination order that follows the
+ * decomposition (plan it with kind = WMC_TREE_NETWORK).
+ *   td:       NUL-terminated PACE ".td" text, host memory: "s td <bags>
+ *             <max bag size> <vertices>", "b <id> <v...>" lines and tree
+ *             edges "<id> <id>"; 'c' lines are comments.  Vertices are
+ *             1..n_vars for the variables and n_vars+1..n_vars+n_clauses for
+ *             the clauses, in input order (vertices = n_vars + n_clauses).
+ *   root_bag: bag to root the decomposition at (1-based; 0 = bag 1).
+ *   width:    out (may be NULL): max |bag| - 1.
+ * Every clause, an OR, is factored along the smallest subtree of bags that
+ * covers its incidences: each bag below the subtree's top gets an auxiliary
+ * variable (weight (1, 1)) holding the OR of the clause's literals in its
+ * part of the subtree, and the top keeps the clause over its inputs (gates
+ * of more than two inputs are chained, so no factor has more than three
+ * variables).  W is unchanged.  Tautologies are dropped (all-ones tensors);
+ * an empty clause gives W = 0.  Other arguments and the weights convention
+ * as wmc_build_network (callers pass 2*n_vars weights everywhere).
+ * WMC_ERR_INVALID_ARGUMENT for malformed text, a vertex count other than
+ * n_vars + n_clauses, bags that are not a tree, a vertex whose bags are not
+ * connected, or an incidence (variable, clause) that no bag covers. */
+wmc_status wmc_build_network_td(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
+                                const int32_t *lits, const double *weights, const char *td, int64_t root_bag,
+                                wmc_network **out, int32_t *width);
 
 /* Size of the Theorem-2 network: n_tensors = n_vars + n_clauses tensors
  * (auxiliary variables and chain clauses of factored long clauses included),

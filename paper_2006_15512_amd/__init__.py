@@ -27,7 +27,7 @@ WMC_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAP_UNREACHABLE",
                 4: "DEVICE", 5: "BUSY", 6: "UNSUPPORTED"}
 FP64, FP32_SCALED = 0, 1
-TREE_MINFILL, TREE_ORDER, TREE_EXPLICIT = 0, 1, 2
+TREE_MINFILL, TREE_ORDER, TREE_EXPLICIT, TREE_NETWORK = 0, 1, 2, 3
 SLICE_BY_MEMORY, SLICE_BY_FLOPS = 0, 1
 _PREC = {"fp64": 0, "fp32": 1, "fp32_scaled": 1}
 MAX_RANK = 34
@@ -152,6 +152,7 @@ def lib():
             "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
             "wmc_plan_kernels": [P, P, i64, P],
             "wmc_contract_noalloc": [P, P, P, ctypes.POINTER(wmc_value)],
+            "wmc_build_network_td": [i32, i64, P, P, P, ctypes.c_char_p, i64, P, P],
             "wmc_tuning_get": [i32, P],
             "wmc_tuning_set": [i32, P],
         }
@@ -216,6 +217,33 @@ class Network:
     def from_formula(cls, f) -> "Network":
         return cls(f.n, f.clauses, f.weights)
 
+    @classmethod
+    def from_td(cls, f, td: str, root_bag: int = 0) -> "Network":
+        """wmc_build_network_td (FactorTree): the network factored along a
+        tree decomposition ``td`` (PACE text) of the formula's incidence graph
+        (variables 1..n, clause c as vertex n + 1 + c); plan it with
+        kind="network".  The decomposition's width is in ``.td_width``."""
+        self = cls.__new__(cls)
+        clauses = f.clauses
+        ptr = np.zeros(len(clauses) + 1, dtype=np.int64)
+        for i, c in enumerate(clauses):
+            ptr[i + 1] = ptr[i] + len(c)
+        lits = np.array([l for c in clauses for l in c], dtype=np.int32)
+        w = np.ascontiguousarray(np.asarray(f.weights, dtype=np.float64).reshape(-1))
+        if w.size != 2 * f.n:
+            raise ValueError("weights must have 2*n entries")
+        h = ctypes.c_void_p()
+        wd = ctypes.c_int32()
+        _check(lib().wmc_build_network_td(int(f.n), len(clauses), _p(ptr) if len(clauses) else None, _p(lits), _p(w),
+                                          td.encode(), int(root_bag), ctypes.byref(h), ctypes.byref(wd)))
+        self._h = h
+        self.n = int(f.n)
+        self.m = len(clauses)
+        self.clauses = [list(map(int, c)) for c in clauses]
+        self.weights = w.copy()
+        self.td_width = int(wd.value)
+        return self
+
     def info(self) -> Dict[str, int]:
         nt, ni = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().wmc_network_info(self._h, ctypes.byref(nt), ctypes.byref(ni)))
@@ -270,7 +298,8 @@ class Plan:
                  mem_cap_bytes: int = 0, rank_cap: int = 0, precision: str = "fp64", block: int = 1,
                  slice_objective: str = "memory", slice_group: int = 1):
         o = wmc_plan_options()
-        o.kind = {"minfill": TREE_MINFILL, "order": TREE_ORDER, "explicit": TREE_EXPLICIT}[kind]
+        o.kind = {"minfill": TREE_MINFILL, "order": TREE_ORDER, "explicit": TREE_EXPLICIT,
+                  "network": TREE_NETWORK}[kind]
         o.precision = {"fp64": FP64, "fp32": FP32_SCALED, "fp32_scaled": FP32_SCALED}[precision]
         o.seed = int(seed)
         o.block = int(block)

@@ -46,30 +46,74 @@ extern "C" const char *wmc_version(void) { return "wmc-mi355x 0.1 (gfx950)"; }
 // Reduction (Theorem 2).  B_C is stored as (variables, falsifying assignment,
 // tautology flag); A_x is symbolic: its degree and the two weights.
 // ---------------------------------------------------------------------------
+// The network of Theorem 2 over clause list cls (DIMACS literals over the
+// caller's n_vars variables and the auxiliary ones after them, which weigh
+// (1, 1); aux_prefix[i] lists the caller variables auxiliary variable
+// n_vars + 1 + i depends on).
+static wmc_network *make_network(int32_t n_vars, const double *weights, const std::vector<std::vector<int32_t>> &cls,
+                                 std::vector<std::vector<int32_t>> aux_prefix) {
+    const int32_t n_aux = (int32_t)aux_prefix.size();
+    wmc_network *net = new wmc_network();
+    net->n = n_vars + n_aux;
+    net->n_user = n_vars;
+    net->aux_prefix = std::move(aux_prefix);
+    net->w.assign(weights, weights + 2 * (size_t)n_vars);
+    net->w.resize(2 * (size_t)net->n, 1.0);
+    net->degree.assign((size_t)net->n, 0);
+    net->clauses.resize(cls.size());
+    std::vector<int8_t> sign((size_t)net->n + 1, 0);  // bit0: positive seen, bit1: negative seen
+    for (size_t c = 0; c < cls.size(); ++c) {
+        WClause &cl = net->clauses[c];
+        for (int32_t l : cls[c]) {
+            int32_t v = l > 0 ? l : -l;
+            if (!sign[v]) cl.vars.push_back(v);
+            sign[v] |= (l > 0) ? 1 : 2;
+        }
+        std::sort(cl.vars.begin(), cl.vars.end());
+        for (size_t i = 0; i < cl.vars.size(); ++i) {
+            int32_t v = cl.vars[i];
+            if (sign[v] == 3) cl.taut = true;
+            // a positive literal is falsified by 0, a negative one by 1
+            if (sign[v] == 2) cl.falsify |= 1u << i;
+            sign[v] = 0;
+            net->degree[(size_t)v - 1]++;
+        }
+        net->n_indices += (int64_t)cl.vars.size();
+    }
+    return net;
+}
+
+// Checks shared by the network builders: sizes, CSR offsets, literals in
+// range, finite weights.
+static wmc_status check_formula(const char *who, int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
+                                const int32_t *lits, const double *weights) {
+    if (n_vars < 0 || n_clauses < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: negative size", who);
+    if (n_clauses > 0 && !clause_ptr) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: clause_ptr is NULL", who);
+    if (n_vars > 0 && !weights) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: weights is NULL", who);
+    if (n_clauses > 0) {
+        for (int64_t c = 0; c < n_clauses; ++c)
+            if (clause_ptr[c + 1] < clause_ptr[c] || clause_ptr[c] < 0)
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: clause_ptr not non-decreasing at %lld", who, (long long)c);
+        if (clause_ptr[n_clauses] > clause_ptr[0] && !lits) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: lits is NULL", who);
+    }
+    for (int64_t i = 0; i < 2 * (int64_t)n_vars; ++i)
+        if (!std::isfinite(weights[i]))
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: weight %lld is not finite", who, (long long)i);
+    for (int64_t j = n_clauses > 0 ? clause_ptr[0] : 0; n_clauses > 0 && j < clause_ptr[n_clauses]; ++j)
+        if (lits[j] == 0 || lits[j] > n_vars || lits[j] < -n_vars)
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: literal %d out of range", who, (int)lits[j]);
+    return WMC_OK;
+}
+
 extern "C" wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
                                         const int32_t *lits, const double *weights,
                                         wmc_network **out) {
     if (!out) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: out is NULL");
     *out = nullptr;
-    if (n_vars < 0 || n_clauses < 0)
-        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: negative size");
-    if (n_clauses > 0 && !clause_ptr)
-        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: clause_ptr is NULL");
-    if (n_vars > 0 && !weights) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: weights is NULL");
-    if (n_clauses > 0) {
-        for (int64_t c = 0; c < n_clauses; ++c)
-            if (clause_ptr[c + 1] < clause_ptr[c] || clause_ptr[c] < 0)
-                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: clause_ptr not non-decreasing at %lld",
-                         (long long)c);
-        if (clause_ptr[n_clauses] > clause_ptr[0] && !lits)
-            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: lits is NULL");
+    {
+        const wmc_status st = check_formula("wmc_build_network", n_vars, n_clauses, clause_ptr, lits, weights);
+        if (st != WMC_OK) return st;
     }
-    for (int64_t i = 0; i < 2 * (int64_t)n_vars; ++i)
-        if (!std::isfinite(weights[i]))
-            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: weight %lld is not finite", (long long)i);
-    for (int64_t j = n_clauses > 0 ? clause_ptr[0] : 0; n_clauses > 0 && j < clause_ptr[n_clauses]; ++j)
-        if (lits[j] == 0 || lits[j] > n_vars || lits[j] < -n_vars)
-            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_build_network: literal %d out of range", (int)lits[j]);
     try {
         // Clauses with more than WMC_FACTOR_ABOVE distinct variables are
         // factored into a chain of clauses of at most three literals over
@@ -118,37 +162,9 @@ extern "C" wmc_status wmc_build_network(int32_t n_vars, int64_t n_clauses, const
                 cls.push_back({prev, lv[(size_t)k - 1]});
             }
         }
-        const int32_t n_aux = (int32_t)aux_prefix.size();
-        if ((int64_t)n_vars + n_aux > (int64_t)INT32_MAX / 2)
+        if ((int64_t)n_vars + (int64_t)aux_prefix.size() > (int64_t)INT32_MAX / 2)
             WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_build_network: too many variables after clause factoring");
-        wmc_network *net = new wmc_network();
-        net->n = n_vars + n_aux;
-        net->n_user = n_vars;
-        net->aux_prefix = std::move(aux_prefix);
-        net->w.assign(weights, weights + 2 * (size_t)n_vars);
-        net->w.resize(2 * (size_t)net->n, 1.0);
-        net->degree.assign((size_t)net->n, 0);
-        net->clauses.resize(cls.size());
-        std::vector<int8_t> sign((size_t)net->n + 1, 0);  // bit0: positive seen, bit1: negative seen
-        for (size_t c = 0; c < cls.size(); ++c) {
-            WClause &cl = net->clauses[c];
-            for (int32_t l : cls[c]) {
-                int32_t v = l > 0 ? l : -l;
-                if (!sign[v]) cl.vars.push_back(v);
-                sign[v] |= (l > 0) ? 1 : 2;
-            }
-            std::sort(cl.vars.begin(), cl.vars.end());
-            for (size_t i = 0; i < cl.vars.size(); ++i) {
-                int32_t v = cl.vars[i];
-                if (sign[v] == 3) cl.taut = true;
-                // a positive literal is falsified by 0, a negative one by 1
-                if (sign[v] == 2) cl.falsify |= 1u << i;
-                sign[v] = 0;
-                net->degree[(size_t)v - 1]++;
-            }
-            net->n_indices += (int64_t)cl.vars.size();
-        }
-        *out = net;
+        *out = make_network(n_vars, weights, cls, std::move(aux_prefix));
     } catch (std::bad_alloc &) {
         WMC_FAIL(WMC_ERR_OUT_OF_MEMORY, "wmc_build_network: host allocation failed");
     }
@@ -1401,9 +1417,15 @@ extern "C" wmc_status wmc_plan(const wmc_network *net, const wmc_plan_options *o
                 WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_plan: a supplied tree cannot cover factored long clauses");
             }
             st = explicit_tree(*net, opts->parent, opts->n_tree_nodes, P->T, &P->root);
-        } else if (opts->kind == WMC_TREE_ORDER || opts->kind == WMC_TREE_MINFILL) {
+        } else if (opts->kind == WMC_TREE_ORDER || opts->kind == WMC_TREE_MINFILL || opts->kind == WMC_TREE_NETWORK) {
             std::vector<int32_t> order;
-            if (opts->kind == WMC_TREE_ORDER) {
+            if (opts->kind == WMC_TREE_NETWORK) {
+                if (net->order.empty() && net->n > 0) {
+                    delete P;
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_plan: the network carries no elimination order");
+                }
+                order = net->order;
+            } else if (opts->kind == WMC_TREE_ORDER) {
                 const int32_t nu = net->n_user;
                 if (!opts->order || opts->order_len != nu) {
                     delete P;
@@ -1572,13 +1594,22 @@ extern "C" wmc_status wmc_plan_launches(const wmc_plan_t *plan, double *bytes, d
 // subtree that is not entirely below the top bag (else it would be gone
 // already), so the subtree passes through the top bag.  The bucket of x
 // therefore spans at most the top bag's size.
-extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, int64_t root_bag,
-                                        int32_t *order, int32_t *width) {
-    if (!net || !td || !order) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: NULL argument");
-    const int32_t n = net->n_user;
-    long long nb = -1, nv = -1;
-    std::vector<std::vector<int32_t>> bags;
+// A tree decomposition read from PACE ".td" text, rooted and checked: a
+// tree over its bags, and every vertex's bags connected.
+struct ParsedTD {
+    long long nb = 0;
+    std::vector<std::vector<int32_t>> bags;          // sorted vertex ids, 1-based
     std::vector<std::pair<long long, long long>> edges;
+    std::vector<int64_t> bfs, par, depth;            // from the root: parents before children
+    std::vector<int64_t> top;                        // per vertex: its bag of least depth, -1 if none
+    std::vector<std::vector<int64_t>> bags_of;       // per vertex: its bags, in bfs order
+    int32_t width = 0;
+};
+
+static wmc_status parse_td(const char *who, const char *td, long long nvert, int64_t root_bag, ParsedTD &T) {
+    long long nb = -1, nv = -1;
+    std::vector<std::vector<int32_t>> &bags = T.bags;
+    std::vector<std::pair<long long, long long>> &edges = T.edges;
     const char *p = td;
     long long line = 0;
     while (*p) {
@@ -1592,34 +1623,30 @@ extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, 
         if (s[i] == 's') {
             long long w = 0;
             if (nb >= 0 || std::sscanf(s.c_str() + i, "s td %lld %lld %lld", &nb, &w, &nv) != 3 || nb < 0 || nv < 0)
-                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad solution line %lld", line);
-            if (nv != n)
-                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: %lld vertices, the formula has %d variables",
-                         nv, (int)n);
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: bad solution line %lld", who, line);
+            if (nv != nvert)
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: %lld vertices, the graph has %lld", who, nv, nvert);
             // a tree of nb bags needs nb - 1 edge lines: more bags than
             // characters cannot be a well-formed file (and would only
             // allocate)
             if (nb > (long long)std::strlen(td))
-                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: %lld bags in a text of %zu bytes", nb,
-                         std::strlen(td));
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: %lld bags in a text of %zu bytes", who, nb, std::strlen(td));
             bags.assign((size_t)nb, {});
             continue;
         }
-        if (nb < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: line %lld before the 's td' line", line);
+        if (nb < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: line %lld before the 's td' line", who, line);
         const char *q = s.c_str() + i;
         char *end = nullptr;
         if (s[i] == 'b') {
             ++q;
             const long long id = std::strtoll(q, &end, 10);
-            if (end == q || id < 1 || id > nb)
-                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad bag id on line %lld", line);
+            if (end == q || id < 1 || id > nb) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: bad bag id on line %lld", who, line);
             std::vector<int32_t> &B = bags[(size_t)(id - 1)];
             for (q = end;;) {
                 const long long v = std::strtoll(q, &end, 10);
                 if (end == q) break;
-                if (v < 1 || v > n)
-                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: vertex %lld out of range on line %lld", v,
-                             line);
+                if (v < 1 || v > nvert)
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: vertex %lld out of range on line %lld", who, v, line);
                 B.push_back((int32_t)v);
                 q = end;
             }
@@ -1630,14 +1657,15 @@ extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, 
             const char *q2 = end;
             const long long b = std::strtoll(q2, &end, 10);
             if (end == q2 || a < 1 || a > nb || b < 1 || b > nb || a == b)
-                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad edge on line %lld", line);
+                WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: bad edge on line %lld", who, line);
             edges.push_back({a - 1, b - 1});
         }
     }
-    if (nb < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: no 's td' line");
-    if (nb == 0 && n > 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: no bags");
+    if (nb < 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: no 's td' line", who);
+    if (nb == 0 && nvert > 0) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: no bags", who);
     if ((long long)edges.size() != (nb > 0 ? nb - 1 : 0))
-        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: %zu edges for %lld bags (not a tree)", edges.size(), nb);
+        WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: %zu edges for %lld bags (not a tree)", who, edges.size(), nb);
+    T.nb = nb;
     // breadth-first order from the root: parents before children
     std::vector<std::vector<int64_t>> adj((size_t)nb);
     for (auto &e : edges) {
@@ -1645,38 +1673,243 @@ extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, 
         adj[(size_t)e.second].push_back(e.first);
     }
     const int64_t root = root_bag > 0 ? root_bag - 1 : 0;
-    if (nb > 0 && (root < 0 || root >= nb)) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bad root bag");
-    std::vector<int64_t> bfs, par((size_t)nb, -2);
+    if (nb > 0 && (root < 0 || root >= nb)) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: bad root bag", who);
+    T.par.assign((size_t)nb, -2);
+    T.depth.assign((size_t)nb, 0);
     if (nb > 0) {
-        bfs.push_back(root);
-        par[(size_t)root] = -1;
+        T.bfs.push_back(root);
+        T.par[(size_t)root] = -1;
     }
-    for (size_t h = 0; h < bfs.size(); ++h)
-        for (int64_t c : adj[(size_t)bfs[h]])
-            if (par[(size_t)c] == -2) {
-                par[(size_t)c] = bfs[h];
-                bfs.push_back(c);
+    for (size_t h = 0; h < T.bfs.size(); ++h)
+        for (int64_t c : adj[(size_t)T.bfs[h]])
+            if (T.par[(size_t)c] == -2) {
+                T.par[(size_t)c] = T.bfs[h];
+                T.depth[(size_t)c] = T.depth[(size_t)T.bfs[h]] + 1;
+                T.bfs.push_back(c);
             }
-    if ((long long)bfs.size() != nb) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bags not connected");
-    // each variable's bags must form a subtree (bags holding it minus tree
+    if ((long long)T.bfs.size() != nb) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: bags not connected", who);
+    // each vertex's bags must form a subtree (bags holding it minus tree
     // edges joining two of them = 1)
-    std::vector<int64_t> top((size_t)n + 1, -1), nbags((size_t)n + 1, 0), nedges((size_t)n + 1, 0);
-    std::vector<std::vector<int64_t>> bags_of((size_t)n + 1);
-    for (int64_t b : bfs)
+    T.top.assign((size_t)nvert + 1, -1);
+    T.bags_of.assign((size_t)nvert + 1, {});
+    std::vector<int64_t> nedges((size_t)nvert + 1, 0);
+    for (int64_t b : T.bfs) {
+        T.width = std::max(T.width, (int32_t)bags[(size_t)b].size() - 1);
         for (int32_t v : bags[(size_t)b]) {
-            if (top[(size_t)v] < 0) top[(size_t)v] = b;
-            ++nbags[(size_t)v];
-            bags_of[(size_t)v].push_back(b);
+            if (T.top[(size_t)v] < 0) T.top[(size_t)v] = b;
+            T.bags_of[(size_t)v].push_back(b);
         }
+    }
     for (auto &e : edges) {
         const std::vector<int32_t> &A = bags[(size_t)e.first], &B = bags[(size_t)e.second];
         std::vector<int32_t> both;
         std::set_intersection(A.begin(), A.end(), B.begin(), B.end(), std::back_inserter(both));
         for (int32_t v : both) ++nedges[(size_t)v];
     }
-    for (int32_t v = 1; v <= n; ++v)
-        if (nbags[(size_t)v] > 0 && nedges[(size_t)v] != nbags[(size_t)v] - 1)
-            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: bags of variable %d are not connected", (int)v);
+    for (long long v = 1; v <= nvert; ++v)
+        if (!T.bags_of[(size_t)v].empty() && nedges[(size_t)v] != (int64_t)T.bags_of[(size_t)v].size() - 1)
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: bags of vertex %lld are not connected", who, v);
+    return WMC_OK;
+}
+
+// FactorTree (Theorem 3; the FactorTree paragraph of Section 3.3): the
+// network is factored along a tree decomposition of the formula's incidence
+// graph (variables 1..n_vars, clause c as vertex n_vars + 1 + c), and the
+// elimination order follows the decomposition.
+//
+// A clause C is an OR, which is tree-factorable (Def. 4).  Each literal of C
+// is assigned to the bag nearest the root that holds both its variable and C
+// (the edge of the incidence graph lies in some bag, and the bags of each
+// vertex are connected).  Let T'_C be the smallest subtree spanning the
+// assigned bags, L its top.  At every bag b of T'_C below L an auxiliary
+// variable a_b = OR(literals assigned to b, a_c of b's children in T'_C) is
+// introduced (clauses a_b -> OR(inputs) and input -> a_b); at L the clause
+// OR(inputs) remains.  Every assignment of the formula's variables extends
+// to exactly one assignment of the a_b, which weigh (1, 1), so W is
+// unchanged (the network of Theorem 2 is a partial contraction of the
+// factored one).  Gates wider than two inputs are chained through local
+// auxiliary variables, so every factor has at most three variables.
+//
+// Elimination order, bags children first: at bag b the carries a_c of its
+// children, then b's local chain variables, then the formula's variables
+// whose bag of least depth is b.  When a bag's turn comes, every open
+// variable is a variable of the bag or the carry of a clause in it, so
+// intermediates stay near the width of the decomposition.
+extern "C" wmc_status wmc_build_network_td(int32_t n_vars, int64_t n_clauses, const int64_t *clause_ptr,
+                                           const int32_t *lits, const double *weights, const char *td,
+                                           int64_t root_bag, wmc_network **out, int32_t *width) {
+    const char *who = "wmc_build_network_td";
+    if (!out || !td) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: NULL argument", who);
+    *out = nullptr;
+    {
+        const wmc_status st = check_formula(who, n_vars, n_clauses, clause_ptr, lits, weights);
+        if (st != WMC_OK) return st;
+    }
+    if ((long long)n_vars + n_clauses > (long long)INT32_MAX / 4)
+        WMC_FAIL(WMC_ERR_UNSUPPORTED, "%s: incidence graph too large", who);
+    ParsedTD T;
+    {
+        const wmc_status st = parse_td(who, td, (long long)n_vars + n_clauses, root_bag, T);
+        if (st != WMC_OK) return st;
+    }
+    try {
+        std::vector<std::vector<int32_t>> cls, aux_prefix;
+        std::vector<int64_t> aux_node;     // bag at which each auxiliary variable is eliminated
+        std::vector<uint8_t> aux_carry;    // a child's carry (eliminated before the bag's local chain)
+        auto new_aux = [&](std::vector<int32_t> prefix, int64_t node, bool carry) {
+            std::sort(prefix.begin(), prefix.end());
+            prefix.erase(std::unique(prefix.begin(), prefix.end()), prefix.end());
+            aux_prefix.push_back(std::move(prefix));
+            aux_node.push_back(node);
+            aux_carry.push_back(carry ? 1 : 0);
+            return n_vars + (int32_t)aux_prefix.size();
+        };
+        // inputs of a gate or of the final clause: literal and the caller
+        // variables it depends on
+        struct In {
+            int32_t lit;
+            std::vector<int32_t> pre;
+        };
+        // out = 0: the clause OR(in); out = a: a <-> OR(in).  Inputs beyond
+        // two are folded pairwise into local variables at `node` first.
+        auto emit = [&](std::vector<In> in, int32_t out_lit, int64_t node) {
+            const size_t keep = out_lit ? 2 : 3;
+            while (in.size() > keep) {
+                std::vector<int32_t> pre = in[0].pre;
+                pre.insert(pre.end(), in[1].pre.begin(), in[1].pre.end());
+                const int32_t t = new_aux(pre, node, false);
+                cls.push_back({-t, in[0].lit, in[1].lit});
+                cls.push_back({t, -in[0].lit});
+                cls.push_back({t, -in[1].lit});
+                In folded{t, aux_prefix.back()};
+                in.erase(in.begin(), in.begin() + 2);
+                in.insert(in.begin(), std::move(folded));
+            }
+            std::vector<int32_t> big;
+            if (out_lit) big.push_back(-out_lit);
+            for (const In &x : in) big.push_back(x.lit);
+            cls.push_back(big);
+            if (out_lit)
+                for (const In &x : in) cls.push_back({out_lit, -x.lit});
+        };
+        std::vector<int8_t> sign((size_t)n_vars + 1, 0);
+        std::vector<int64_t> cnt((size_t)T.nb, 0);
+        std::vector<std::vector<In>> inputs((size_t)T.nb);
+        for (int64_t c = 0; c < n_clauses; ++c) {
+            std::vector<int32_t> lv;
+            bool taut = false;
+            for (int64_t j = clause_ptr[c]; j < clause_ptr[c + 1]; ++j) {
+                const int32_t l = lits[j], v = l > 0 ? l : -l;
+                const int8_t bit = l > 0 ? 1 : 2;
+                if (!(sign[v] & bit)) {
+                    if (sign[v]) taut = true;
+                    else lv.push_back(l);
+                    sign[v] |= bit;
+                }
+            }
+            for (int32_t l : lv) sign[(size_t)(l > 0 ? l : -l)] = 0;
+            if (taut) continue;  // an all-ones tensor: dropping it leaves W unchanged
+            if (lv.empty()) {
+                cls.push_back({});  // the empty clause: W = 0
+                continue;
+            }
+            const int32_t cv = n_vars + 1 + (int32_t)c;
+            if (T.bags_of[(size_t)cv].empty()) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: clause %lld in no bag", who, (long long)c);
+            const int64_t topc = T.top[(size_t)cv];
+            std::vector<int64_t> S;
+            for (int32_t l : lv) {
+                const int32_t x = l > 0 ? l : -l;
+                int64_t at = -1;
+                for (int64_t b : T.bags_of[(size_t)x])  // in bfs order: least depth first
+                    if (std::binary_search(T.bags[(size_t)b].begin(), T.bags[(size_t)b].end(), cv)) {
+                        at = b;
+                        break;
+                    }
+                if (at < 0)
+                    WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: no bag holds variable %d with clause %lld", who, (int)x,
+                             (long long)c);
+                if (inputs[(size_t)at].empty()) S.push_back(at);
+                inputs[(size_t)at].push_back(In{l, {x}});
+            }
+            if (S.size() == 1 && lv.size() <= WMC_FACTOR_ABOVE) {
+                cls.push_back(lv);  // the clause lies in one bag: kept whole
+                inputs[(size_t)S[0]].clear();
+                continue;
+            }
+            // smallest subtree spanning S: paths up to the clause's top bag,
+            // cut at the deepest bag every path passes (their meeting point)
+            std::vector<int64_t> touched;
+            for (int64_t b0 : S)
+                for (int64_t b = b0;; b = T.par[(size_t)b]) {
+                    if (cnt[(size_t)b]++ == 0) touched.push_back(b);
+                    if (b == topc || T.par[(size_t)b] < 0) break;
+                }
+            int64_t lca = -1;
+            for (int64_t b : touched)
+                if (cnt[(size_t)b] == (int64_t)S.size() && (lca < 0 || T.depth[(size_t)b] > T.depth[(size_t)lca])) lca = b;
+            std::vector<int64_t> sub;
+            for (int64_t b : touched)
+                if (T.depth[(size_t)b] >= T.depth[(size_t)lca]) sub.push_back(b);
+            std::sort(sub.begin(), sub.end(),
+                      [&](int64_t a, int64_t b) { return T.depth[(size_t)a] > T.depth[(size_t)b]; });
+            for (int64_t b : sub) {
+                if (b == lca) {
+                    emit(std::move(inputs[(size_t)b]), 0, b);
+                } else {
+                    std::vector<int32_t> pre;
+                    for (const In &x : inputs[(size_t)b]) pre.insert(pre.end(), x.pre.begin(), x.pre.end());
+                    const int64_t up = T.par[(size_t)b];
+                    const int32_t a = new_aux(pre, up, true);
+                    emit(std::move(inputs[(size_t)b]), a, b);
+                    inputs[(size_t)up].push_back(In{a, aux_prefix.back()});
+                }
+                inputs[(size_t)b].clear();
+            }
+            for (int64_t b : touched) cnt[(size_t)b] = 0;
+        }
+        const int32_t n_aux = (int32_t)aux_prefix.size();
+        if ((int64_t)n_vars + n_aux > (int64_t)INT32_MAX / 2)
+            WMC_FAIL(WMC_ERR_UNSUPPORTED, "%s: too many variables after factoring", who);
+        wmc_network *net = make_network(n_vars, weights, cls, aux_prefix);
+        // elimination order: variables in no bag first, then bags children
+        // first (carries into the bag, its local chain, its own variables)
+        std::vector<std::vector<int32_t>> carry_at((size_t)T.nb), local_at((size_t)T.nb);
+        for (int32_t i = 0; i < n_aux; ++i)
+            (aux_carry[(size_t)i] ? carry_at : local_at)[(size_t)aux_node[(size_t)i]].push_back(n_vars + 1 + i);
+        for (int32_t v = 1; v <= n_vars; ++v)
+            if (T.top[(size_t)v] < 0) net->order.push_back(v);
+        for (size_t h = T.bfs.size(); h-- > 0;) {
+            const int64_t b = T.bfs[h];
+            for (int32_t a : carry_at[(size_t)b]) net->order.push_back(a);
+            for (int32_t a : local_at[(size_t)b]) net->order.push_back(a);
+            for (int32_t v : T.bags[(size_t)b])
+                if (v <= n_vars && T.top[(size_t)v] == b) net->order.push_back(v);
+        }
+        if ((int32_t)net->order.size() != net->n) {
+            delete net;
+            WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "%s: internal order of %zu variables, network has %d", who,
+                     net->order.size(), (int)net->n);
+        }
+        if (width) *width = T.width;
+        *out = net;
+    } catch (std::bad_alloc &) {
+        WMC_FAIL(WMC_ERR_OUT_OF_MEMORY, "%s: host allocation failed", who);
+    }
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, int64_t root_bag,
+                                        int32_t *order, int32_t *width) {
+    if (!net || !td || !order) WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_order_from_td: NULL argument");
+    const int32_t n = net->n_user;
+    ParsedTD T;
+    {
+        const wmc_status st = parse_td("wmc_order_from_td", td, n, root_bag, T);
+        if (st != WMC_OK) return st;
+    }
+    const std::vector<std::vector<int32_t>> &bags = T.bags;
+    const std::vector<int64_t> &bfs = T.bfs, &top = T.top;
+    const std::vector<std::vector<int64_t>> &bags_of = T.bags_of;
     // every clause (its caller variables) inside one bag
     for (size_t c = 0; c < net->clauses.size(); ++c) {
         std::vector<int32_t> vs;
@@ -1685,7 +1918,7 @@ extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, 
         if (vs.empty()) continue;
         int32_t lead = vs[0];
         for (int32_t v : vs)
-            if (nbags[(size_t)v] < nbags[(size_t)lead]) lead = v;
+            if (bags_of[(size_t)v].size() < bags_of[(size_t)lead].size()) lead = v;
         bool ok = false;
         for (int64_t b : bags_of[(size_t)lead]) {
             const std::vector<int32_t> &B = bags[(size_t)b];
@@ -1698,13 +1931,11 @@ extern "C" wmc_status wmc_order_from_td(const wmc_network *net, const char *td, 
     size_t k = 0;
     for (int32_t v = 1; v <= n; ++v)
         if (top[(size_t)v] < 0) order[k++] = v;
-    int32_t wmax = 0;
     for (size_t h = bfs.size(); h-- > 0;) {
         const int64_t b = bfs[h];
-        wmax = std::max(wmax, (int32_t)bags[(size_t)b].size() - 1);
         for (int32_t v : bags[(size_t)b])
             if (top[(size_t)v] == b) order[k++] = v;
     }
-    if (width) *width = wmax;
+    if (width) *width = T.width;
     return WMC_OK;
 }

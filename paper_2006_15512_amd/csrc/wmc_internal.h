@@ -28,6 +28,9 @@ struct wmc_network {
     // auxiliary variable n_user+1+i stands for the OR of the literals over
     // aux_prefix[i] (caller variables), the leading part of a long clause
     std::vector<std::vector<int32_t>> aux_prefix;
+    // elimination order over all n variables carried by a network factored
+    // along a tree decomposition (empty otherwise)
+    std::vector<int32_t> order;
 };
 
 // A tensor of the contraction tree (leaf or internal node output).
