@@ -44,8 +44,9 @@ typedef enum {
     WMC_ERR_CAP_UNREACHABLE = 3,  /* slicing cannot meet the memory / rank cap */
     WMC_ERR_DEVICE = 4,           /* a HIP call failed; message in wmc_last_error() */
     WMC_ERR_BUSY = 5,             /* server queue full */
-    WMC_ERR_UNSUPPORTED = 6       /* rank too large, supplied tree over factored clauses,
+    WMC_ERR_UNSUPPORTED = 6,      /* rank too large, supplied tree over factored clauses,
                                      sliced plan in a server */
+    WMC_ERR_CANCELLED = 7         /* serving: the request was cancelled or passed its deadline */
 } wmc_status;
 
 typedef enum { WMC_FP64 = 0, WMC_FP32_SCALED = 1 } wmc_precision;
@@ -378,6 +379,10 @@ wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, ui
 /* ------------------------------------------------------------------ */
 /* Each request is the paper's execution stage (Algorithm 2) on a registered
  * plan with the request's weights W (Definition 1); requests share launches.
+ * A registered structure's descriptors are uploaded once, into the request
+ * region pool (they stay resident and count against it); a step uploads
+ * only one small work entry per running request and the weights of newly
+ * admitted ones.
  * A server owns a caller-supplied device buffer: two staging areas for step
  * descriptors (2 * step_bytes), a result table, and the request regions (at
  * most hbm_budget_bytes).  Registered structures are unsliced plans of the
@@ -426,6 +431,16 @@ wmc_status wmc_serve_register(wmc_server *s, const wmc_plan_t *plan, int32_t *st
 /* Non-blocking: queue one request (WMC_ERR_BUSY if the queue is full). */
 wmc_status wmc_serve_submit(wmc_server *s, int32_t structure, const double *weights,
                             uint64_t request_id);
+/* As wmc_serve_submit, with a deadline timeout_s seconds from now: a request
+ * not finished by then ends with status WMC_ERR_CANCELLED (checked at every
+ * step; a running request stops issuing launches). */
+wmc_status wmc_serve_submit_deadline(wmc_server *s, int32_t structure, const double *weights,
+                                     uint64_t request_id, double timeout_s);
+/* Cancel a queued or running request: its response carries status
+ * WMC_ERR_CANCELLED (at once if queued; after the step in flight if
+ * running, whose region is released only when no step can touch it).
+ * INVALID_ARGUMENT if no such request is queued or running. */
+wmc_status wmc_serve_cancel(wmc_server *s, uint64_t request_id);
 /* Admit what fits and issue one step on the server's stream, then wait for
  * the step issued by the previous call and collect its completions, so the
  * host prepares step k+1 while the device runs step k.  *n_active counts
@@ -434,6 +449,9 @@ wmc_status wmc_serve_submit(wmc_server *s, int32_t structure, const double *weig
 wmc_status wmc_serve_step(wmc_server *s, int32_t *n_active, int32_t *n_queued);
 /* Move up to max completed responses into out. */
 wmc_status wmc_serve_poll(wmc_server *s, wmc_response *out, int32_t max, int32_t *n_out);
+/* Step the server until a response is ready, nothing is queued or running,
+ * or timeout_us microseconds have passed; then poll as wmc_serve_poll. */
+wmc_status wmc_serve_wait(wmc_server *s, wmc_response *out, int32_t max, int32_t *n_out, int64_t timeout_us);
 /* Replay timed arrivals (sorted by t_arrive) until all n complete; out gets
  * the n responses in completion order. */
 wmc_status wmc_serve(wmc_server *s, const wmc_request *trace, int64_t n, wmc_response *out);

@@ -25,7 +25,8 @@ LIB_PATH = os.environ.get("WMC_LIBRARY") or os.path.join(_HERE, "libwmc.so")
 
 WMC_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "CAP_UNREACHABLE",
-                4: "DEVICE", 5: "BUSY", 6: "UNSUPPORTED"}
+                4: "DEVICE", 5: "BUSY", 6: "UNSUPPORTED", 7: "CANCELLED"}
+CANCELLED = 7
 FP64, FP32_SCALED = 0, 1
 TREE_MINFILL, TREE_ORDER, TREE_EXPLICIT, TREE_NETWORK = 0, 1, 2, 3
 SLICE_BY_MEMORY, SLICE_BY_FLOPS = 0, 1
@@ -147,6 +148,9 @@ def lib():
             "wmc_serve_submit": [P, i32, P, u64],
             "wmc_serve_step": [P, P, P],
             "wmc_serve_poll": [P, P, i32, P],
+            "wmc_serve_wait": [P, P, i32, P, i64],
+            "wmc_serve_cancel": [P, u64],
+            "wmc_serve_submit_deadline": [P, i32, P, u64, ctypes.c_double],
             "wmc_serve": [P, P, i64, P],
             "wmc_serve_stats": [P, P],
             "wmc_contract_profile": [P, P, P, u64, P, P, i64, ctypes.POINTER(wmc_value)],
@@ -690,6 +694,19 @@ class Server:
     def submit(self, structure: int, weights, request_id: int) -> None:
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
         _check(lib().wmc_serve_submit(self._h, int(structure), _p(w), int(request_id)))
+
+    def submit_deadline(self, structure: int, weights, request_id: int, timeout_s: float) -> None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        _check(lib().wmc_serve_submit_deadline(self._h, int(structure), _p(w), int(request_id), float(timeout_s)))
+
+    def cancel(self, request_id: int) -> None:
+        _check(lib().wmc_serve_cancel(self._h, int(request_id)))
+
+    def wait(self, timeout_s: float, max_n: int = 1 << 16) -> List[Response]:
+        arr = (wmc_response * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().wmc_serve_wait(self._h, arr, int(max_n), ctypes.byref(n), int(timeout_s * 1e6)))
+        return [Response.of(arr[i]) for i in range(n.value)]
 
     def step(self):
         na, nq = ctypes.c_int32(), ctypes.c_int32()

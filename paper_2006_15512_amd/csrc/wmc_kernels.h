@@ -80,7 +80,8 @@ __device__ __forceinline__ unsigned long long pext_runs(unsigned long long r, co
 }
 
 // the same for packed run words (src | len << 8 | dst << 16)
-__device__ __forceinline__ unsigned long long pext_words(unsigned long long r, const unsigned *runs, int nr) {
+template <typename RP>
+__device__ __forceinline__ unsigned long long pext_words(unsigned long long r, RP runs, int nr) {
     unsigned long long out = 0;
     for (int q = 0; q < nr; ++q) {
         const unsigned w = runs[q];
@@ -131,6 +132,47 @@ static __global__ __attribute__((unused)) void k_begin(wmc_meta *meta, int nt, w
 
 // Leaf fill (Theorem 2): clause tables B_C restricted to the slice, weight
 // vectors [W(x,0), W(x,1)], or W(x,0)+W(x,1) for a variable in no clause.
+// Entry e of leaf d filled for slice bits et (every lane of the wave calls
+// it; e past the leaf's entries contributes nothing).
+template <typename T, typename DP>
+__device__ __forceinline__ void leaf_item(DP d, long long e, const double *__restrict__ w,
+                                          T *__restrict__ arena, wmc_meta *meta, unsigned long long et) {
+    const bool valid = e < (1ll << d->rank);
+    double v = 0.0;
+    if (valid) {
+        if (d->kind == WMC_LEAF_CLAUSE) {
+            unsigned a = 0;
+            for (int q = 0; q < d->k; ++q) {
+                int p = d->pos[q];
+                unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
+                a |= bit << q;
+            }
+            v = (d->taut || a != d->falsify) ? 1.0 : 0.0;
+        } else {
+            // a weight leaf carries its own power-of-two exponent, as every
+            // intermediate does: stored entries have magnitude below 1, so
+            // any finite weight fits the storage type (FP32 included)
+            const double w0 = w[2 * d->var], w1 = w[2 * d->var + 1];
+            if (d->kind == WMC_LEAF_WEIGHT) {
+                int p = d->pos[0];
+                unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
+                v = bit ? w1 : w0;
+            } else {
+                v = w0 + w1;
+            }
+            const double mx = d->kind == WMC_LEAF_WEIGHT ? fmax(fabs(w0), fabs(w1)) : fabs(v);
+            int ex = 0;
+            if (mx > 0.0) frexp(mx, &ex);
+            v = ldexp(v, -ex);
+            if (e == 0) meta[d->tensor].exp = ex;
+        }
+        T s = (T)v;
+        arena[d->out + e] = s;
+        v = fabs((double)s);
+    }
+    publish_max(meta, d->tensor, v);
+}
+
 // The body takes its workgroup index and count, so that the fused step
 // kernel can run it on a share of its workgroups.
 template <typename T>
@@ -138,9 +180,11 @@ __device__ __forceinline__ void leaves_body(const LeafDesc *__restrict__ L, int 
                                             const double *__restrict__ w, T *__restrict__ arena, wmc_meta *meta,
                                             unsigned long long eta, const int *__restrict__ wave_leaf,
                                             const unsigned long long *__restrict__ leaf_eta, unsigned blk,
-                                            unsigned nblk) {
-    const long long stride = (long long)nblk * blockDim.x;
-    for (long long g = (long long)blk * blockDim.x + threadIdx.x; g < work; g += stride) {
+                                            unsigned nblk, unsigned width = 0, unsigned tid = 0) {
+    // units of `width` threads (a workgroup by default, or one wave)
+    const unsigned W = width ? width : blockDim.x, t = width ? tid : threadIdx.x;
+    const long long stride = (long long)nblk * W;
+    for (long long g = (long long)blk * W + t; g < work; g += stride) {
         // leaves start on wave boundaries: a wave's items belong to one leaf
         int lo = 0;
         if (wave_leaf) {
@@ -152,44 +196,8 @@ __device__ __forceinline__ void leaves_body(const LeafDesc *__restrict__ L, int 
                 if (L[mid].work_begin <= g) lo = mid; else hi = mid - 1;
             }
         }
-        const LeafDesc &d = L[lo];
         // a batch of sliced plans gives every leaf the slice of its instance
-        const unsigned long long et = leaf_eta ? leaf_eta[lo] : eta;
-        const long long e = g - d.work_begin;
-        const bool valid = e < (1ll << d.rank);
-        double v = 0.0;
-        if (valid) {
-            if (d.kind == WMC_LEAF_CLAUSE) {
-                unsigned a = 0;
-                for (int q = 0; q < d.k; ++q) {
-                    int p = d.pos[q];
-                    unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
-                    a |= bit << q;
-                }
-                v = (d.taut || a != d.falsify) ? 1.0 : 0.0;
-            } else {
-                // a weight leaf carries its own power-of-two exponent, as every
-                // intermediate does: stored entries have magnitude below 1, so
-                // any finite weight fits the storage type (FP32 included)
-                const double w0 = w[2 * d.var], w1 = w[2 * d.var + 1];
-                if (d.kind == WMC_LEAF_WEIGHT) {
-                    int p = d.pos[0];
-                    unsigned bit = p >= 0 ? (unsigned)((e >> p) & 1) : (unsigned)((et >> (-p - 1)) & 1ull);
-                    v = bit ? w1 : w0;
-                } else {
-                    v = w0 + w1;
-                }
-                const double mx = d.kind == WMC_LEAF_WEIGHT ? fmax(fabs(w0), fabs(w1)) : fabs(v);
-                int ex = 0;
-                if (mx > 0.0) frexp(mx, &ex);
-                v = ldexp(v, -ex);
-                if (e == 0) meta[d.tensor].exp = ex;
-            }
-            T s = (T)v;
-            arena[d.out + e] = s;
-            v = fabs((double)s);
-        }
-        publish_max(meta, d.tensor, v);
+        leaf_item<T>(L + lo, g - L[lo].work_begin, w, arena, meta, leaf_eta ? leaf_eta[lo] : eta);
     }
 }
 
@@ -207,12 +215,40 @@ __global__ void __launch_bounds__(WMC_BLOCK) k_leaves(const LeafDesc *__restrict
 // C[r] = 2^-(sA+sB) * sum_j A[(pext_A(r) << nk) | j] * B[(pext_B(r) << nk) | j].
 // A launch covers a run of nodes; each node's outputs are padded to a wave
 // multiple so that a wave never straddles two nodes.
+// Output r of small node d (every lane of the wave calls it; r past the
+// node's outputs contributes nothing): C[r] = 2^-(sA+sB) * sum_j
+// A[(pext_A(r) << nk) | j] * B[(pext_B(r) << nk) | j].
+// DP is a pointer to the descriptor: generic, or in the constant address
+// space for descriptors read through the scalar path.
+template <typename T, typename DP>
+__device__ __forceinline__ void node_item(DP d, unsigned long long r, T *__restrict__ arena,
+                                          wmc_meta *meta) {
+    const bool valid = r < (1ull << d->rc);
+    const int sA = scale_exp(meta[d->ta].maxbits);
+    const int sB = scale_exp(meta[d->tb].maxbits);
+    double v = 0.0;
+    if (valid) {
+        const T *A = arena + d->a + (pext_words(r, d->ra, d->nra) << d->nk);
+        const T *B = arena + d->b + (pext_words(r, d->rb, d->nrb) << d->nk);
+        const int K = 1 << d->nk;
+        double acc = 0.0;
+        for (int j = 0; j < K; ++j) acc = fma(ld(A + j), ld(B + j), acc);
+        T s = (T)ldexp(acc, -(sA + sB));
+        arena[d->c + (long long)r] = s;
+        v = fabs((double)s);
+    }
+    publish_max(meta, d->tc, v);
+    if (r == 0) meta[d->tc].exp = meta[d->ta].exp + meta[d->tb].exp + sA + sB;
+}
+
 template <typename T>
 __device__ __forceinline__ void nodes_body(const NodeDesc *__restrict__ D, int nd, long long work,
                                            T *__restrict__ arena, wmc_meta *meta, const int *__restrict__ wave_node,
-                                           unsigned blk, unsigned nblk) {
-    const long long stride = (long long)nblk * blockDim.x;
-    for (long long g = (long long)blk * blockDim.x + threadIdx.x; g < work; g += stride) {
+                                           unsigned blk, unsigned nblk, unsigned width = 0, unsigned tid = 0) {
+    // units of `width` threads (a workgroup by default, or one wave)
+    const unsigned W = width ? width : blockDim.x, t = width ? tid : threadIdx.x;
+    const long long stride = (long long)nblk * W;
+    for (long long g = (long long)blk * W + t; g < work; g += stride) {
         // a wave's 64 items belong to one node (outputs are padded to waves):
         // search with the wave's first item so the node index, and every
         // descriptor read, is wave-uniform (scalar loads)
@@ -228,24 +264,7 @@ __device__ __forceinline__ void nodes_body(const NodeDesc *__restrict__ D, int n
             }
         }
         lo = __builtin_amdgcn_readfirstlane(lo);
-        const NodeDesc &d = D[lo];
-        const unsigned long long r = (unsigned long long)(g - d.work_begin);
-        const bool valid = r < (1ull << d.rc);
-        const int sA = scale_exp(meta[d.ta].maxbits);
-        const int sB = scale_exp(meta[d.tb].maxbits);
-        double v = 0.0;
-        if (valid) {
-            const T *A = arena + d.a + (pext_words(r, d.ra, d.nra) << d.nk);
-            const T *B = arena + d.b + (pext_words(r, d.rb, d.nrb) << d.nk);
-            const int K = 1 << d.nk;
-            double acc = 0.0;
-            for (int j = 0; j < K; ++j) acc = fma(ld(A + j), ld(B + j), acc);
-            T s = (T)ldexp(acc, -(sA + sB));
-            arena[d.c + (long long)r] = s;
-            v = fabs((double)s);
-        }
-        publish_max(meta, d.tc, v);
-        if (r == 0) meta[d.tc].exp = meta[d.ta].exp + meta[d.tb].exp + sA + sB;
+        node_item<T>(D + lo, (unsigned long long)(g - D[lo].work_begin), arena, meta);
     }
 }
 
@@ -711,8 +730,8 @@ struct Stream2Args {
 
 // Bit extraction along at most MAX runs (unrolled with static indices, so
 // run words passed in kernel arguments stay in scalar registers).
-template <int MAX>
-__device__ __forceinline__ unsigned long long apply_runs(unsigned long long r, const unsigned *runs, int n) {
+template <int MAX, typename RP>
+__device__ __forceinline__ unsigned long long apply_runs(unsigned long long r, RP runs, int n) {
     unsigned long long out = 0;
 #pragma unroll
     for (int i = 0; i < MAX; ++i)
@@ -1426,8 +1445,8 @@ static inline unsigned long long stream_task_blocks(const Stream2Args &a) {
     return (threads + STREAM2_MULTI_THREADS - 1) / STREAM2_MULTI_THREADS;
 }
 
-template <typename T, int NK>
-__device__ __forceinline__ void stream_multi_body(const StreamTask *__restrict__ tasks, int ntasks,
+template <typename T, int NK, typename TP = const StreamTask *>
+__device__ __forceinline__ void stream_multi_body(TP tasks, int ntasks,
                                                   T *__restrict__ arena, wmc_meta *meta,
                                                   const int *__restrict__ block_task, unsigned blk) {
     constexpr int K = 1 << NK;
@@ -1443,7 +1462,7 @@ __device__ __forceinline__ void stream_multi_body(const StreamTask *__restrict__
         }
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
-    const Stream2Args &args = tasks[lo].a;
+    const auto &args = tasks[lo].a;
     const unsigned long long lb = (unsigned long long)((long long)blk - tasks[lo].block_begin);
     const int sS = scale_exp(meta[args.ts].maxbits);
     const int sO = scale_exp(meta[args.to].maxbits);

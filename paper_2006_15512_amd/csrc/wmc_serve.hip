@@ -1,17 +1,25 @@
 // Serving: weight-vector queries against registered formula structures, with
 // continuous batching.
 //
-// Every registered structure is an unsliced plan.  A request (structure,
-// weights) is admitted when a slot is free and a region of the device buffer
-// large enough for its footprint (meta table + arena of its plan) is free:
-// admission is by HBM footprint within a fixed budget.  The server advances
-// in steps: one step runs, for every admitted request, the next launch of its
-// plan (leaf fill for a newly admitted one), all merged into shared kernels
-// (one k_nodes launch for the generic/streaming nodes of every request, one
-// MFMA launch per matrix node).  A request that arrives while others are on
-// the GPU joins at the next step; one that finishes frees its slot and
-// region at once.  Each request's descriptors are its plan's, shifted into
-// its region, so its arithmetic is the same alone or in any mix.
+// Every registered structure is an unsliced plan whose descriptors (leaves,
+// nodes, streaming tasks, matrix nodes and the lookup tables of the merged
+// kernels) are uploaded once, at registration, into the server's buffer and
+// stay there.  A request (structure, weights) is admitted when a slot is
+// free and a region of the buffer large enough for its footprint (meta table
+// + arena of its plan) is free: admission is by HBM footprint within a fixed
+// budget.  The server advances in steps: one step runs, for every admitted
+// request, the next launch of its plan (leaf fill for a newly admitted one).
+// A step uploads only one small work entry per request (its region's arena
+// and meta offsets and where its launch's descriptors live) plus the weights
+// of newly admitted requests; one fused kernel runs every request's leaf
+// fill, small nodes and streaming tasks, each workgroup finding its request
+// by a search over the entries' first workgroups, and matrix nodes run as
+// their own launches on the request's shifted arena.  A request that arrives
+// while others are on the GPU joins at the next step; one that finishes
+// frees its slot and region.  Each request's descriptors are its plan's, read
+// relative to its region, so its arithmetic is the same alone or in any mix.
+// A request can be cancelled, or given a deadline; either ends it with
+// WMC_ERR_CANCELLED.
 #include <chrono>
 #include <deque>
 #include <map>
@@ -20,22 +28,45 @@
 
 namespace {
 
+// Where one launch of a registered structure keeps its resident descriptors
+// (byte offsets into the server buffer).
+struct SLaunch {
+    int32_t type = LAUNCH_NODES;
+    int32_t gemm = -1;                 // LAUNCH_GEMM: index into gemms
+    uint64_t nodes_off = 0;            // generic nodes
+    int32_t nnodes = 0;
+    long long node_work = 0;
+    uint64_t tasks_off = 0, btask_off = 0;  // streaming tasks (by nk) and their workgroup -> task table
+    long long gblock[5] = {0, 0, 0, 0, 0};
+    int32_t gtask[5] = {0, 0, 0, 0, 0};
+    unsigned sblocks = 0;
+    // per wave of the generic nodes: descriptor offset and first output
+    std::vector<std::pair<uint64_t, int32_t>> waves;
+    // per streaming workgroup: task descriptor offset, summed-index bits and
+    // workgroup number (counted from the task group's start)
+    struct Blk {
+        uint64_t off;
+        int32_t nk, blk;
+    };
+    std::vector<Blk> blocks;
+};
+
 struct SStruct {
     int32_t n = 0;                // variables, auxiliary ones included
     int32_t n_user = 0;           // a request brings 2 * n_user weights
     std::vector<double> w_aux;    // (1, 1) per auxiliary variable
-    std::vector<int> task_of;     // per node: index into tasks if it streams in merged steps, else -1
-    std::vector<StreamTask> tasks;  // streaming arguments of those nodes (region offsets not yet added)
-    std::vector<LeafDesc> leaves;
-    std::vector<NodeDesc> nodes;
-    std::vector<GemmDesc> gemms;
-    std::vector<Launch> launches;
+    std::vector<GemmDesc> gemms;  // host copies (launch shapes); the device reads the resident ones
+    std::vector<SLaunch> L;       // per launch of the plan; L[0] is the leaf fill
+    uint64_t img_off = 0, img_bytes = 0;   // resident image (offset into the region pool)
+    uint64_t leaves_off = 0, gemms_off = 0;
+    std::vector<std::pair<uint64_t, int32_t>> leaf_waves;  // per wave of the leaf fill
+    int32_t nleaves = 0;
     int32_t root = -1;
     long long root_off = 0;
     int64_t nt = 0;
     uint64_t meta_bytes = 0, arena_bytes = 0, footprint = 0;
     int64_t leaf_work = 0;
-    uint64_t max_step_bytes = 0;  // largest staging contribution of one launch
+    uint64_t max_step_bytes = 0;  // largest staging contribution of one request in one step
 };
 
 struct SReq {
@@ -46,6 +77,8 @@ struct SReq {
     size_t k = 0;
     std::vector<double> w;
     double t_arrive = 0, t_admit = 0;
+    double deadline = 0;          // server clock, 0 = none
+    bool cancelled = false;
 };
 
 struct FinishEntry {
@@ -61,6 +94,38 @@ struct ClearRange {
 
 }  // namespace
 
+// One request's share of a fused serving step: its streaming workgroups
+// [sb0, sb0 + sn) of the step's streaming part, its region's arena and meta
+// offsets, its weights (leaf fill) and its launch's resident streaming
+// tasks.
+struct ServeWork {
+    unsigned sb0, sn;
+    long long abase, mbase;
+    const double *w;
+    const StreamTask *tasks;
+    const int *block_task;
+    long long gblock[5];
+    int gtask[5];
+    int pad;
+};
+
+// One streaming workgroup of a step: the task's resident descriptor, its
+// summed-index bits, the request's work entry and the workgroup's number
+// within the task's group.
+struct ServeBlock {
+    const StreamTask *task;
+    int entry, nk, blk, pad;
+};
+
+// One wave of a step's small-node or leaf part: the node's (leaf's)
+// resident descriptor, the request's work entry and the wave's first
+// output.  Waves of different requests share workgroups.
+struct ServeWave {
+    const void *desc;
+    int entry;
+    int item;
+};
+
 static uint64_t sal(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 __global__ void k_clear_meta(const ClearRange *__restrict__ r, wmc_meta *meta) {
@@ -68,6 +133,55 @@ __global__ void k_clear_meta(const ClearRange *__restrict__ r, wmc_meta *meta) {
     for (long long i = threadIdx.x; i < c.count; i += blockDim.x) {
         meta[c.first + i].maxbits = 0ull;
         meta[c.first + i].exp = 0;
+    }
+}
+
+// A descriptor the host wrote before the launch, addressed through the
+// constant address space so that the wave reads it with scalar loads, as it
+// reads descriptors whose pointers are kernel arguments.
+template <typename D>
+__device__ __forceinline__ const __attribute__((address_space(4))) D *const_desc(const void *p) {
+    return (const __attribute__((address_space(4))) D *)(unsigned long long)p;
+}
+
+// A step: workgroups [0, sblocks) run the streaming tasks (blocks[]), then
+// workgroups of four waves run the nwaves
+// small-node waves and the leaf waves after them (waves[]); padding waves
+// at the end exit at once.
+template <typename T>
+__global__ void __launch_bounds__(256) k_step_serve(const ServeWork *__restrict__ work, const ServeBlock *__restrict__ blocks,
+                                                    const ServeWave *__restrict__ waves, unsigned sblocks,
+                                                    unsigned nwaves, unsigned lwaves, T *__restrict__ arena,
+                                                    wmc_meta *meta) {
+    const unsigned bx = blockIdx.x;
+    if (bx >= sblocks) {
+        // wave-uniform index, so that the record, the work entry and the
+        // descriptor are read with scalar loads
+        const unsigned wv = __builtin_amdgcn_readfirstlane(((bx - sblocks) << 2) | (threadIdx.x >> 6));
+        if (wv >= nwaves + lwaves) return;
+        const ServeWave &rec = waves[wv];
+        const ServeWork &w = work[rec.entry];
+        const unsigned long long lane = threadIdx.x & (WMC_WAVE - 1);
+        if (wv < nwaves)
+            node_item<T>(const_desc<NodeDesc>(rec.desc), (unsigned long long)rec.item + lane, arena + w.abase,
+                         meta + w.mbase);
+        else
+            leaf_item<T>(const_desc<LeafDesc>(rec.desc), (long long)rec.item + (long long)lane, w.w, arena + w.abase,
+                         meta + w.mbase, 0ull);
+        return;
+    }
+    const ServeBlock &b = blocks[bx];
+    const ServeWork &w = work[b.entry];
+    T *ar = arena + w.abase;
+    wmc_meta *me = meta + w.mbase;
+    // the task is found directly: a one-task list whose first workgroup
+    // number is the task's own
+    const auto t = const_desc<StreamTask>(b.task);
+    switch (b.nk) {
+    case 0: stream_multi_body<T, 0>(t, 1, ar, me, nullptr, b.blk); break;
+    case 1: stream_multi_body<T, 1>(t, 1, ar, me, nullptr, b.blk); break;
+    case 2: stream_multi_body<T, 2>(t, 1, ar, me, nullptr, b.blk); break;
+    default: stream_multi_body<T, 3>(t, 1, ar, me, nullptr, b.blk); break;
     }
 }
 
@@ -112,7 +226,9 @@ struct wmc_server {
     std::vector<SReq> active;
     std::vector<int32_t> free_slots;
     std::map<uint64_t, uint64_t> free_regions;  // offset -> size
-    uint64_t used_bytes = 0, peak_used = 0;
+    uint64_t used_bytes = 0, peak_used = 0, structure_bytes = 0;
+    int64_t queued_deadlines = 0;                // queued requests with a deadline
+    double next_deadline = 0;                    // no queued deadline before this
     int64_t peak_active = 0, steps = 0;
     uint8_t *stage[2] = {nullptr, nullptr};     // pinned staging, one per step parity
     ServeRes *res_host[2] = {nullptr, nullptr};  // pinned results, one per step parity
@@ -193,114 +309,6 @@ extern "C" wmc_status wmc_serve_create(const wmc_serve_options *opts, void *devi
 
 extern "C" void wmc_serve_destroy(wmc_server *v) { delete v; }
 
-extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, int32_t *structure_id) {
-    if (!v || !plan) {
-        wmc_set_error("wmc_serve_register: NULL argument");
-        return WMC_ERR_INVALID_ARGUMENT;
-    }
-    if (plan->precision != v->opt.precision) {
-        wmc_set_error("wmc_serve_register: plan precision differs from the server's");
-        return WMC_ERR_INVALID_ARGUMENT;
-    }
-    if (!plan->sliced.empty()) {
-        wmc_set_error("wmc_serve_register: sliced plans are not served");
-        return WMC_ERR_UNSUPPORTED;
-    }
-    try {
-        SStruct s;
-        s.n = plan->n;
-        s.n_user = plan->n_user;
-        s.w_aux.assign(plan->w.begin() + 2 * (size_t)plan->n_user, plan->w.end());
-        s.leaves = plan->leaves;
-        s.task_of.assign(plan->nodes.size(), -1);
-        for (size_t q = 0; q < plan->nodes.size(); ++q) {
-            const NodeDesc &d = plan->nodes[q];
-            StreamTask t;
-            if (d.rc >= plan->tune.multi_min_rank && d.cls != WMC_CLASS_GEMM && stream_task(d, &t)) {
-                s.task_of[q] = (int)s.tasks.size();
-                s.tasks.push_back(t);
-            }
-        }
-        s.nodes = plan->nodes;
-        s.gemms = plan->gemms;
-        s.launches = plan->launches;
-        s.root = plan->root;
-        s.root_off = plan->root >= 0 ? plan->T[(size_t)plan->root].off : 0;
-        s.nt = (int64_t)std::max<size_t>(plan->T.size(), 1);
-        s.meta_bytes = sal(sizeof(wmc_meta) * (uint64_t)s.nt, 256);
-        s.arena_bytes = sal(std::max<uint64_t>(plan->arena_bytes, 256), 256);
-        s.footprint = s.meta_bytes + s.arena_bytes;
-        s.leaf_work = plan->leaf_work;
-        uint64_t mx = sal(sizeof(double) * 2 * (uint64_t)s.n, 8) + sizeof(ClearRange) +
-                      sizeof(LeafDesc) * s.leaves.size() + sizeof(int) * ((uint64_t)s.leaf_work / WMC_WAVE + 1) +
-                      sizeof(FinishEntry);
-        for (size_t k = 1; k < s.launches.size(); ++k) {
-            const Launch &L = s.launches[k];
-            // descriptors, plus the lookup tables of the merged kernels (one
-            // int per wave of small nodes and per streaming workgroup)
-            uint64_t b = L.type == LAUNCH_GEMM
-                             ? sizeof(GemmDesc)
-                             : sizeof(NodeDesc) * (uint64_t)L.count +
-                                   sizeof(int) * ((uint64_t)L.work / WMC_WAVE + (uint64_t)L.work / 4096 +
-                                                  (uint64_t)L.count + 2);
-            mx = std::max(mx, b + sizeof(FinishEntry));
-        }
-        s.max_step_bytes = mx + 8 * 256;
-        if (s.footprint > v->regions_bytes || s.max_step_bytes > v->step_cap) {
-            wmc_set_error("wmc_serve_register: structure needs %llu bytes of region and %llu of staging",
-                          (unsigned long long)s.footprint, (unsigned long long)s.max_step_bytes);
-            return WMC_ERR_CAP_UNREACHABLE;
-        }
-        v->S.push_back(std::move(s));
-        if (structure_id) *structure_id = (int32_t)v->S.size() - 1;
-    } catch (std::bad_alloc &) {
-        wmc_set_error("wmc_serve_register: host allocation failed");
-        return WMC_ERR_OUT_OF_MEMORY;
-    }
-    return WMC_OK;
-}
-
-static wmc_status serve_submit_at(wmc_server *v, int32_t structure, const double *weights, uint64_t request_id,
-                                  double t_arrive) {
-    if (structure < 0 || structure >= (int32_t)v->S.size()) {
-        wmc_set_error("wmc_serve_submit: unknown structure %d", structure);
-        return WMC_ERR_INVALID_ARGUMENT;
-    }
-    if ((int64_t)v->queue.size() >= v->opt.max_queue) {
-        wmc_set_error("wmc_serve_submit: queue full (%d)", v->opt.max_queue);
-        return WMC_ERR_BUSY;
-    }
-    const SStruct &s = v->S[(size_t)structure];
-    SReq r;
-    r.id = request_id;
-    r.s = structure;
-    r.t_arrive = t_arrive;
-    if (s.n_user > 0) {
-        if (!weights) {
-            wmc_set_error("wmc_serve_submit: weights are NULL");
-            return WMC_ERR_INVALID_ARGUMENT;
-        }
-        r.w.assign(weights, weights + 2 * (size_t)s.n_user);
-        for (double x : r.w)
-            if (!std::isfinite(x)) {
-                wmc_set_error("wmc_serve_submit: non-finite weight");
-                return WMC_ERR_INVALID_ARGUMENT;
-            }
-    }
-    r.w.insert(r.w.end(), s.w_aux.begin(), s.w_aux.end());
-    v->queue.push_back(std::move(r));
-    return WMC_OK;
-}
-
-extern "C" wmc_status wmc_serve_submit(wmc_server *v, int32_t structure, const double *weights,
-                                       uint64_t request_id) {
-    if (!v) {
-        wmc_set_error("wmc_serve_submit: server is NULL");
-        return WMC_ERR_INVALID_ARGUMENT;
-    }
-    return serve_submit_at(v, structure, weights, request_id, v->now());
-}
-
 static bool region_alloc(wmc_server *v, uint64_t size, uint64_t *off) {
     for (auto it = v->free_regions.begin(); it != v->free_regions.end(); ++it) {
         if (it->second < size) continue;
@@ -332,6 +340,222 @@ static void region_free(wmc_server *v, uint64_t off, uint64_t size) {
     }
 }
 
+// Registration builds the structure's resident image -- leaves and their
+// wave table, matrix-node descriptors, and per node launch its generic nodes
+// with their wave table and its streaming tasks (grouped by summed-index
+// size) with their workgroup table -- and uploads it once into the region
+// pool, where it stays for the server's life.
+extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, int32_t *structure_id) {
+    if (!v || !plan) {
+        wmc_set_error("wmc_serve_register: NULL argument");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (plan->precision != v->opt.precision) {
+        wmc_set_error("wmc_serve_register: plan precision differs from the server's");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (!plan->sliced.empty()) {
+        wmc_set_error("wmc_serve_register: sliced plans are not served");
+        return WMC_ERR_UNSUPPORTED;
+    }
+    try {
+        SStruct s;
+        s.n = plan->n;
+        s.n_user = plan->n_user;
+        s.w_aux.assign(plan->w.begin() + 2 * (size_t)plan->n_user, plan->w.end());
+        s.gemms = plan->gemms;
+        s.root = plan->root;
+        s.root_off = plan->root >= 0 ? plan->T[(size_t)plan->root].off : 0;
+        s.nt = (int64_t)std::max<size_t>(plan->T.size(), 1);
+        s.meta_bytes = sal(sizeof(wmc_meta) * (uint64_t)s.nt, 256);
+        s.arena_bytes = sal(std::max<uint64_t>(plan->arena_bytes, 256), 256);
+        s.footprint = s.meta_bytes + s.arena_bytes;
+        s.leaf_work = plan->leaf_work;
+        s.nleaves = (int32_t)plan->leaves.size();
+        // image, offsets relative to its start
+        std::vector<uint8_t> img;
+        auto put = [&](const void *src, size_t bytes) {
+            const uint64_t at = sal(img.size(), 256);
+            img.resize(at + bytes);
+            if (bytes) std::memcpy(img.data() + at, src, bytes);
+            return at;
+        };
+        s.leaves_off = put(plan->leaves.data(), sizeof(LeafDesc) * plan->leaves.size());
+        for (size_t q = 0; q < plan->leaves.size(); ++q)
+            for (uint64_t e = 0; e < (1ull << plan->leaves[q].rank); e += WMC_WAVE)
+                s.leaf_waves.push_back({s.leaves_off + sizeof(LeafDesc) * q, (int32_t)e});
+        std::vector<int> tab;
+        s.gemms_off = put(plan->gemms.data(), sizeof(GemmDesc) * plan->gemms.size());
+        s.L.resize(plan->launches.size());
+        for (size_t k = 1; k < plan->launches.size(); ++k) {
+            const Launch &Ln = plan->launches[k];
+            SLaunch &sl = s.L[k];
+            sl.type = Ln.type;
+            if (Ln.type == LAUNCH_GEMM) {
+                sl.gemm = Ln.pad;
+                continue;
+            }
+            std::vector<NodeDesc> generic(plan->nodes.begin() + Ln.first, plan->nodes.begin() + Ln.first + Ln.count);
+            std::vector<StreamTask> tasks;
+            std::vector<int> nkf;
+            int64_t work = 0;
+            split_stream(generic, tasks, nkf, work, plan->tune.multi_min_rank);
+            sl.nnodes = (int32_t)generic.size();
+            sl.node_work = work;
+            sl.nodes_off = put(generic.data(), sizeof(NodeDesc) * generic.size());
+            for (size_t q = 0; q < generic.size(); ++q)
+                for (uint64_t e = 0; e < (1ull << generic[q].rc); e += WMC_WAVE)
+                    sl.waves.push_back({sl.nodes_off + sizeof(NodeDesc) * q, (int32_t)e});
+            sl.tasks_off = put(tasks.data(), sizeof(StreamTask) * tasks.size());
+            block_task_table(tasks, nkf, tab);
+            sl.btask_off = put(tab.data(), sizeof(int) * tab.size());
+            unsigned long long blocks = 0;
+            for (int q = 0; q < 4; ++q) {
+                sl.gblock[q] = (long long)blocks;
+                sl.gtask[q] = nkf[(size_t)q];
+                blocks += stream_multi_blocks(tasks.data(), nkf[(size_t)q], nkf[(size_t)q + 1]);
+            }
+            sl.gblock[4] = (long long)blocks;
+            sl.gtask[4] = nkf[4];
+            sl.sblocks = (unsigned)blocks;
+            for (int q = 0; q < 4; ++q)
+                for (int t = nkf[(size_t)q]; t < nkf[(size_t)q + 1]; ++t) {
+                    const long long b0 = tasks[(size_t)t].block_begin;
+                    const long long nb = (long long)stream_task_blocks(tasks[(size_t)t].a);
+                    for (long long b = 0; b < nb; ++b)
+                        sl.blocks.push_back({sl.tasks_off + sizeof(StreamTask) * (uint64_t)t, q, (int32_t)(b0 + b)});
+                }
+        }
+        s.img_bytes = sal(std::max<uint64_t>(img.size(), 256), 256);
+        // staging per request and step: its weights (first step), a work
+        // entry, a clear range or a finish entry
+        uint64_t units = sizeof(ServeWave) * s.leaf_waves.size();
+        for (const SLaunch &sl : s.L)
+            units = std::max<uint64_t>(units, sizeof(ServeBlock) * sl.sblocks + sizeof(ServeWave) * sl.waves.size());
+        s.max_step_bytes = sal(sizeof(double) * 2 * (uint64_t)s.n, 256) + sizeof(ServeWork) + sizeof(ClearRange) +
+                           sizeof(FinishEntry) + units + 6 * 256;
+        if (s.footprint > v->regions_bytes || s.max_step_bytes > v->step_cap) {
+            wmc_set_error("wmc_serve_register: structure needs %llu bytes of region and %llu of staging",
+                          (unsigned long long)s.footprint, (unsigned long long)s.max_step_bytes);
+            return WMC_ERR_CAP_UNREACHABLE;
+        }
+        const uint64_t peak = v->peak_used;
+        if (!region_alloc(v, s.img_bytes, &s.img_off)) {
+            wmc_set_error("wmc_serve_register: no room for the structure's %llu bytes of descriptors",
+                          (unsigned long long)s.img_bytes);
+            return WMC_ERR_OUT_OF_MEMORY;
+        }
+        // descriptors are resident: they leave the budget for requests
+        v->used_bytes -= s.img_bytes;
+        v->peak_used = peak;
+        v->structure_bytes += s.img_bytes;
+        if (v->inflight) HIP_TRY(hipEventSynchronize(v->ev[v->parity]));
+        HIP_TRY(hipMemcpyAsync(v->dev + v->off_regions + s.img_off, img.data(), img.size(), hipMemcpyHostToDevice,
+                               v->st));
+        HIP_TRY(hipStreamSynchronize(v->st));
+        v->S.push_back(std::move(s));
+        if (structure_id) *structure_id = (int32_t)v->S.size() - 1;
+    } catch (std::bad_alloc &) {
+        wmc_set_error("wmc_serve_register: host allocation failed");
+        return WMC_ERR_OUT_OF_MEMORY;
+    }
+    return WMC_OK;
+}
+
+static wmc_status serve_submit_at(wmc_server *v, int32_t structure, const double *weights, uint64_t request_id,
+                                  double t_arrive, double deadline = 0.0) {
+    if (structure < 0 || structure >= (int32_t)v->S.size()) {
+        wmc_set_error("wmc_serve_submit: unknown structure %d", structure);
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if ((int64_t)v->queue.size() >= v->opt.max_queue) {
+        wmc_set_error("wmc_serve_submit: queue full (%d)", v->opt.max_queue);
+        return WMC_ERR_BUSY;
+    }
+    const SStruct &s = v->S[(size_t)structure];
+    SReq r;
+    r.id = request_id;
+    r.s = structure;
+    r.t_arrive = t_arrive;
+    r.deadline = deadline;
+    if (s.n_user > 0) {
+        if (!weights) {
+            wmc_set_error("wmc_serve_submit: weights are NULL");
+            return WMC_ERR_INVALID_ARGUMENT;
+        }
+        r.w.assign(weights, weights + 2 * (size_t)s.n_user);
+        for (double x : r.w)
+            if (!std::isfinite(x)) {
+                wmc_set_error("wmc_serve_submit: non-finite weight");
+                return WMC_ERR_INVALID_ARGUMENT;
+            }
+    }
+    r.w.insert(r.w.end(), s.w_aux.begin(), s.w_aux.end());
+    if (deadline > 0.0) {
+        v->next_deadline = v->queued_deadlines ? std::min(v->next_deadline, deadline) : deadline;
+        ++v->queued_deadlines;
+    }
+    v->queue.push_back(std::move(r));
+    return WMC_OK;
+}
+
+extern "C" wmc_status wmc_serve_submit(wmc_server *v, int32_t structure, const double *weights,
+                                       uint64_t request_id) {
+    if (!v) {
+        wmc_set_error("wmc_serve_submit: server is NULL");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    return serve_submit_at(v, structure, weights, request_id, v->now());
+}
+
+extern "C" wmc_status wmc_serve_submit_deadline(wmc_server *v, int32_t structure, const double *weights,
+                                                uint64_t request_id, double timeout_s) {
+    if (!v) {
+        wmc_set_error("wmc_serve_submit_deadline: server is NULL");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    if (!(timeout_s > 0.0) || !std::isfinite(timeout_s)) {
+        wmc_set_error("wmc_serve_submit_deadline: timeout must be positive and finite");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    const double t = v->now();
+    return serve_submit_at(v, structure, weights, request_id, t, t + timeout_s);
+}
+
+static void respond_cancelled(wmc_server *v, const SReq &r) {
+    wmc_response resp;
+    std::memset(&resp, 0, sizeof resp);
+    resp.request_id = r.id;
+    resp.structure = r.s;
+    resp.status = WMC_ERR_CANCELLED;
+    resp.value = make_value(0.0, 0);
+    resp.t_arrive = r.t_arrive;
+    resp.t_admit = r.t_admit;
+    resp.t_done = v->now();
+    v->done.push_back(resp);
+}
+
+extern "C" wmc_status wmc_serve_cancel(wmc_server *v, uint64_t request_id) {
+    if (!v) {
+        wmc_set_error("wmc_serve_cancel: server is NULL");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    for (auto it = v->queue.begin(); it != v->queue.end(); ++it)
+        if (it->id == request_id) {
+            respond_cancelled(v, *it);
+            if (it->deadline > 0.0) --v->queued_deadlines;
+            v->queue.erase(it);
+            return WMC_OK;
+        }
+    for (SReq &r : v->active)
+        if (r.id == request_id && !r.cancelled) {
+            r.cancelled = true;  // released once no step in flight can touch its region
+            return WMC_OK;
+        }
+    wmc_set_error("wmc_serve_cancel: request %llu is not queued or running", (unsigned long long)request_id);
+    return WMC_ERR_INVALID_ARGUMENT;
+}
+
 // Collect the step in flight: wait for it, publish its finished requests and
 // release their slots and regions.
 static wmc_status serve_collect(wmc_server *v) {
@@ -342,6 +566,12 @@ static wmc_status serve_collect(wmc_server *v) {
     const ServeRes *res = v->res_host[v->parity];
     for (SReq &r : v->finishing) {
         const SStruct &s = v->S[(size_t)r.s];
+        if (r.cancelled) {
+            respond_cancelled(v, r);
+            region_free(v, r.region, s.footprint);
+            v->free_slots.push_back(r.slot);
+            continue;
+        }
         wmc_response resp;
         std::memset(&resp, 0, sizeof resp);
         resp.request_id = r.id;
@@ -368,6 +598,27 @@ template <typename T>
 static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishing, bool *issued) {
     *issued = false;
     const uint64_t elem = (uint64_t)v->elem;
+    const double tnow = v->now();
+    // deadlines: queued requests past theirs end at once (the queue is
+    // scanned only once the earliest queued deadline has passed), running
+    // ones like a cancellation
+    if (v->queued_deadlines > 0 && tnow > v->next_deadline) {
+        v->queued_deadlines = 0;
+        for (auto it = v->queue.begin(); it != v->queue.end();) {
+            if (it->deadline > 0.0 && tnow > it->deadline) {
+                respond_cancelled(v, *it);
+                it = v->queue.erase(it);
+                continue;
+            }
+            if (it->deadline > 0.0) {
+                v->next_deadline = v->queued_deadlines ? std::min(v->next_deadline, it->deadline) : it->deadline;
+                ++v->queued_deadlines;
+            }
+            ++it;
+        }
+    }
+    for (SReq &r : v->active)
+        if (r.deadline > 0.0 && tnow > r.deadline) r.cancelled = true;
     uint64_t stage_need = 0;
     for (const SReq &r : v->active) stage_need += v->S[(size_t)r.s].max_step_bytes;
     while (!v->queue.empty() && !v->free_slots.empty()) {
@@ -382,78 +633,83 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
         r.k = 0;
         r.t_admit = v->now();
         stage_need += s.max_step_bytes;
+        if (r.deadline > 0.0) --v->queued_deadlines;  // next_deadline stays a lower bound
         v->active.push_back(std::move(r));
         v->queue.pop_front();
     }
     if (v->active.empty()) return WMC_OK;
     v->peak_active = std::max<int64_t>(v->peak_active, (int64_t)v->active.size());
 
+    // staging image: [weights][clears][work entries][finish entries]; the
+    // work entries point into the staging half this step uploads to
+    char *stp = v->dev + v->off_step + (uint64_t)h * v->step_cap;
+    const char *img = v->dev + v->off_regions;
     std::vector<double> wts;
     std::vector<ClearRange> clears;
-    std::vector<LeafDesc> leaves;
-    std::vector<NodeDesc> nodes;
-    std::vector<GemmDesc> gemms;
+    std::vector<ServeWork> works;
+    std::vector<long long> work_woff;  // weight offset (doubles) of each work entry's leaf fill, or -1
+    struct GemmCall {
+        const GemmDesc *host;
+        const GemmDesc *dev;
+        long long abase, mbase;
+    };
+    std::vector<GemmCall> gemms;
     std::vector<FinishEntry> fin;
-    std::vector<StreamTask> by_nk[4];
-    int64_t leaf_work = 0, node_work = 0;
+    std::vector<ServeBlock> sblk;      // streaming workgroups
+    std::vector<ServeWave> node_waves, leaf_waves;
+    unsigned sblocks = 0;
     std::vector<SReq> keep;
     keep.reserve(v->active.size());
     for (size_t i = 0; i < v->active.size(); ++i) {
         SReq &r = v->active[i];
         const SStruct &s = v->S[(size_t)r.s];
+        if (r.cancelled) {  // no further launches; released after the steps in flight
+            finishing.push_back(std::move(r));
+            continue;
+        }
         const long long mbase = (long long)(r.region / sizeof(wmc_meta));
         const long long abase = (long long)((r.region + s.meta_bytes) / elem);
+        const char *base = img + s.img_off;
+        const int entry = (int)works.size();
+        ServeWork w;
+        std::memset(&w, 0, sizeof w);
+        w.abase = abase;
+        w.mbase = mbase;
+        long long woff = -1;
+        bool used = false;
         if (r.k == 0) {
             clears.push_back({mbase, s.nt});
-            const int woff = (int)(wts.size() / 2);
+            woff = (long long)wts.size();
             wts.insert(wts.end(), r.w.begin(), r.w.end());
-            for (LeafDesc d : s.leaves) {
-                d.out += abase;
-                d.tensor += (int)mbase;
-                if (d.kind != WMC_LEAF_CLAUSE) d.var += woff;
-                d.work_begin = leaf_work;
-                leaf_work += (int64_t)sal((uint64_t)1 << d.rank, WMC_WAVE);
-                leaves.push_back(d);
-            }
+            for (const auto &x : s.leaf_waves) leaf_waves.push_back({base + x.first, entry, x.second});
+            used = !s.leaf_waves.empty();
         } else {
-            const Launch &L = s.launches[r.k];
+            const SLaunch &L = s.L[r.k];
             if (L.type == LAUNCH_GEMM) {
-                GemmDesc g = s.gemms[(size_t)L.pad];
-                g.a += abase;
-                g.b += abase;
-                g.c += abase;
-                g.ta += (int)mbase;
-                g.tb += (int)mbase;
-                g.tc += (int)mbase;
-                gemms.push_back(g);
+                gemms.push_back({&s.gemms[(size_t)L.gemm], (const GemmDesc *)(base + s.gemms_off) + L.gemm, abase, mbase});
             } else {
-                for (int32_t q = 0; q < L.count; ++q) {
-                    const int ti = s.task_of[(size_t)(L.first + q)];
-                    if (ti >= 0) {  // streams: arguments precomputed at registration
-                        StreamTask t = s.tasks[(size_t)ti];
-                        t.a.s += abase;
-                        t.a.o += abase;
-                        t.a.c += abase;
-                        t.a.ts += (int)mbase;
-                        t.a.to += (int)mbase;
-                        t.a.tc += (int)mbase;
-                        by_nk[s.nodes[(size_t)(L.first + q)].nk].push_back(t);
-                        continue;
+                if (L.sblocks) {
+                    w.tasks = (const StreamTask *)(base + L.tasks_off);
+                    w.block_task = (const int *)(base + L.btask_off);
+                    for (int q = 0; q < 5; ++q) {
+                        w.gblock[q] = L.gblock[q];
+                        w.gtask[q] = L.gtask[q];
                     }
-                    NodeDesc d = s.nodes[(size_t)(L.first + q)];
-                    d.a += abase;
-                    d.b += abase;
-                    d.c += abase;
-                    d.ta += (int)mbase;
-                    d.tb += (int)mbase;
-                    d.tc += (int)mbase;
-                    d.work_begin = node_work;
-                    node_work += (int64_t)sal((uint64_t)1 << d.rc, WMC_WAVE);
-                    nodes.push_back(d);
+                    w.sn = L.sblocks;
+                    w.sb0 = sblocks;
+                    sblocks += L.sblocks;
+                    for (const SLaunch::Blk &x : L.blocks)
+                        sblk.push_back({(const StreamTask *)(base + x.off), entry, x.nk, x.blk, 0});
                 }
+                for (const auto &x : L.waves) node_waves.push_back({base + x.first, entry, x.second});
+                used = L.sblocks > 0 || !L.waves.empty();
             }
         }
-        if (r.k + 1 >= s.launches.size()) {
+        if (used) {
+            works.push_back(w);
+            work_woff.push_back(woff);
+        }
+        if (r.k + 1 >= s.L.size()) {
             fin.push_back({s.root < 0 ? -1 : s.root + (int)mbase, r.slot, s.root_off + abase});
             finishing.push_back(std::move(r));
         } else {
@@ -462,25 +718,8 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
         }
     }
     v->active.swap(keep);
-    // big streaming nodes of the merged step run in the multi-node streaming
-    // kernel, one launch per summed-index size
-    std::vector<StreamTask> tasks;
-    std::vector<int> nkf(5, 0);
-    for (int k = 0; k < 4; ++k) {
-        nkf[(size_t)k] = (int)tasks.size();
-        long long blocks = 0;
-        for (StreamTask &t : by_nk[k]) {
-            t.block_begin = blocks;
-            blocks += (long long)stream_task_blocks(t.a);
-            tasks.push_back(t);
-        }
-    }
-    nkf[4] = (int)tasks.size();
-    std::vector<int> wtab, btab, ltab;
-    wave_leaf_table(leaves, leaf_work, ltab);
-    wave_node_table(nodes, node_work, wtab);
-    block_task_table(tasks, nkf, btab);
-    // staging image: [weights][clears][leaves][nodes][gemms][finish][tasks][tables]
+    const unsigned nwaves = (unsigned)node_waves.size(), lwaves = (unsigned)leaf_waves.size();
+    node_waves.insert(node_waves.end(), leaf_waves.begin(), leaf_waves.end());
     uint64_t o = 0;
     auto place = [&](size_t bytes) {
         uint64_t at = o;
@@ -489,64 +728,41 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
     };
     const uint64_t o_w = place(sizeof(double) * wts.size());
     const uint64_t o_c = place(sizeof(ClearRange) * clears.size());
-    const uint64_t o_l = place(sizeof(LeafDesc) * leaves.size());
-    const uint64_t o_n = place(sizeof(NodeDesc) * nodes.size());
-    const uint64_t o_g = place(sizeof(GemmDesc) * gemms.size());
+    const uint64_t o_k = place(sizeof(ServeWork) * works.size());
+    const uint64_t o_b = place(sizeof(ServeBlock) * sblk.size());
+    const uint64_t o_v = place(sizeof(ServeWave) * node_waves.size());
     const uint64_t o_f = place(sizeof(FinishEntry) * fin.size());
-    const uint64_t o_t = place(sizeof(StreamTask) * tasks.size());
-    const uint64_t o_lt = place(sizeof(int) * ltab.size());
-    const uint64_t o_wt = place(sizeof(int) * wtab.size());
-    const uint64_t o_bt = place(sizeof(int) * btab.size());
     if (o > v->step_cap) {
         wmc_set_error("wmc_serve: step staging overflow (%llu > %llu)", (unsigned long long)o,
                       (unsigned long long)v->step_cap);
         return WMC_ERR_OUT_OF_MEMORY;
     }
+    for (size_t q = 0; q < works.size(); ++q)
+        if (work_woff[q] >= 0) works[q].w = (const double *)(stp + o_w) + work_woff[q];
     uint8_t *stage = v->stage[h];
     auto cp = [&](uint64_t at, const void *src, size_t bytes) {
         if (bytes) std::memcpy(stage + at, src, bytes);
     };
     cp(o_w, wts.data(), sizeof(double) * wts.size());
     cp(o_c, clears.data(), sizeof(ClearRange) * clears.size());
-    cp(o_l, leaves.data(), sizeof(LeafDesc) * leaves.size());
-    cp(o_n, nodes.data(), sizeof(NodeDesc) * nodes.size());
-    cp(o_g, gemms.data(), sizeof(GemmDesc) * gemms.size());
+    cp(o_k, works.data(), sizeof(ServeWork) * works.size());
+    cp(o_b, sblk.data(), sizeof(ServeBlock) * sblk.size());
+    cp(o_v, node_waves.data(), sizeof(ServeWave) * node_waves.size());
     cp(o_f, fin.data(), sizeof(FinishEntry) * fin.size());
-    cp(o_t, tasks.data(), sizeof(StreamTask) * tasks.size());
-    cp(o_lt, ltab.data(), sizeof(int) * ltab.size());
-    cp(o_wt, wtab.data(), sizeof(int) * wtab.size());
-    cp(o_bt, btab.data(), sizeof(int) * btab.size());
     hipStream_t st = v->st;
-    char *stp = v->dev + v->off_step + (uint64_t)h * v->step_cap;
-    HIP_TRY(hipMemcpyAsync(stp, stage, o, hipMemcpyHostToDevice, st));
+    if (o) HIP_TRY(hipMemcpyAsync(stp, stage, o, hipMemcpyHostToDevice, st));
     wmc_meta *meta = (wmc_meta *)(v->dev + v->off_regions);
     T *arena = (T *)(v->dev + v->off_regions);
     if (!clears.empty())
         hipLaunchKernelGGL(k_clear_meta, dim3((unsigned)clears.size()), dim3(256), 0, st,
                            (const ClearRange *)(stp + o_c), meta);
-    // leaf fills of newly admitted requests, small nodes and streaming tasks
-    // of the others: independent work, one launch
-    StepArgs a{};
-    if (!tasks.empty())
-        step_stream_part(a, (const StreamTask *)(stp + o_t), tasks.data(), nkf.data(), (const int *)(stp + o_bt));
-    if (!nodes.empty()) {
-        a.nodes = (const NodeDesc *)(stp + o_n);
-        a.nnodes = (int)nodes.size();
-        a.node_work = (long long)node_work;
-        a.wave_node = (const int *)(stp + o_wt);
-        a.nblocks = grid_for(node_work);
-    }
-    if (!leaves.empty()) {
-        a.leaves = (const LeafDesc *)(stp + o_l);
-        a.nleaves = (int)leaves.size();
-        a.leaf_work = (long long)leaf_work;
-        a.w = (const double *)(stp + o_w);
-        a.wave_leaf = (const int *)(stp + o_lt);
-        a.lblocks = grid_for(leaf_work);
-    }
-    launch_step<T>(a, arena, meta, st);
-    for (size_t q = 0; q < gemms.size(); ++q)
-        launch_gemm<T>(gemms[q], (const GemmDesc *)(stp + o_g) + q, arena, meta, st);
+    const unsigned wblocks = (nwaves + lwaves + 3) / 4;
+    if (sblocks + wblocks)
+        hipLaunchKernelGGL(k_step_serve<T>, dim3(sblocks + wblocks), dim3(256), 0, st, (const ServeWork *)(stp + o_k),
+                           (const ServeBlock *)(stp + o_b), (const ServeWave *)(stp + o_v), sblocks, nwaves, lwaves, arena,
+                           meta);
+    for (const GemmCall &g : gemms)
+        launch_gemm<T>(*g.host, g.dev, arena + g.abase, meta + g.mbase, st);
     ServeRes *res = (ServeRes *)(v->dev + v->off_res);
     if (!fin.empty()) {
         hipLaunchKernelGGL(k_finish_serve<T>, dim3((unsigned)((fin.size() + 255) / 256)), dim3(256), 0, st,
@@ -602,6 +818,20 @@ extern "C" wmc_status wmc_serve_poll(wmc_server *v, wmc_response *out, int32_t m
     v->done.erase(v->done.begin(), v->done.begin() + n);
     if (n_out) *n_out = n;
     return WMC_OK;
+}
+
+extern "C" wmc_status wmc_serve_wait(wmc_server *v, wmc_response *out, int32_t max, int32_t *n_out,
+                                      int64_t timeout_us) {
+    if (!v || (!out && max > 0)) {
+        wmc_set_error("wmc_serve_wait: NULL argument");
+        return WMC_ERR_INVALID_ARGUMENT;
+    }
+    const double t_end = v->now() + (double)std::max<int64_t>(timeout_us, 0) * 1e-6;
+    while (v->done.empty() && (!v->active.empty() || !v->queue.empty() || v->inflight) && v->now() < t_end) {
+        const wmc_status st = wmc_serve_step(v, nullptr, nullptr);
+        if (st != WMC_OK) return st;
+    }
+    return wmc_serve_poll(v, out, max, n_out);
 }
 
 extern "C" wmc_status wmc_serve_stats(const wmc_server *v, wmc_serve_info *out) {

@@ -200,3 +200,55 @@ def test_serve_big_structures_vs_oracle(precision, tol):
             assert rel(frac(solo), frac(got[q].value)) <= tol, q
         m, e = oracle.bucket(fs[s].with_weights(Wt))
         assert rel(frac(got[q].value), Fraction(m) * Fraction(2) ** e) <= tol, q
+
+
+def test_serve_cancel_queued_and_running(structures):
+    """A cancelled request ends with CANCELLED (at once when queued, after
+    the step in flight when running), its slot and region come back, and
+    every other request still matches the oracle."""
+    srv, plans, ids = make_server(structures, max_slots=4, buffer_bytes=1 << 28)
+    rng = np.random.default_rng(21)
+    reqs = []
+    for q in range(10):
+        s = int(rng.integers(0, len(structures)))
+        w = rng.uniform(0.1, 0.9, size=structures[s].n)
+        Wt = np.stack([1 - w, w], axis=1)
+        reqs.append((s, Wt))
+        srv.submit(ids[s], Wt, q)
+    srv.cancel(9)                # still queued (4 slots)
+    srv.step()
+    srv.step()
+    srv.cancel(0)                # running
+    with pytest.raises(W.WmcError):
+        srv.cancel(12345)        # unknown
+    got = {r.request_id: r for r in srv.drain()}
+    assert sorted(got) == list(range(10))
+    assert got[9].status == W.CANCELLED and got[0].status == W.CANCELLED
+    for q in range(1, 9):
+        s, Wt = reqs[q]
+        m, e = oracle.bucket(structures[s].with_weights(Wt))
+        assert got[q].status == 0 and rel(frac(got[q].value), Fraction(m) * Fraction(2) ** e) <= 1e-12, q
+    st = srv.stats()
+    assert st["n_active"] == 0 and st["used_bytes"] == 0
+
+
+def test_serve_deadlines_and_wait(structures):
+    """Requests past their deadline end with CANCELLED; ones with room to
+    spare complete; wait() steps the server until a response is ready."""
+    srv, plans, ids = make_server(structures, max_slots=2, buffer_bytes=1 << 28)
+    rng = np.random.default_rng(22)
+    w = [np.stack([1 - x, x], axis=1) for x in (rng.uniform(0.1, 0.9, size=f.n) for f in structures)]
+    srv.submit_deadline(ids[0], w[0], 0, 60.0)
+    srv.submit_deadline(ids[1], w[1], 1, 60.0)
+    for q in range(2, 8):        # queued behind two slots, deadlines that pass at once
+        srv.submit_deadline(ids[q % len(ids)], w[q % len(ids)], q, 1e-9)
+    out = []
+    while len(out) < 8:
+        got = srv.wait(10.0)
+        assert got, "wait returned nothing"
+        out += got
+    by = {r.request_id: r for r in out}
+    assert by[0].status == 0 and by[1].status == 0
+    assert all(by[q].status == W.CANCELLED for q in range(2, 8))
+    m, e = oracle.bucket(structures[0].with_weights(w[0]))
+    assert rel(frac(by[0].value), Fraction(m) * Fraction(2) ** e) <= 1e-12
