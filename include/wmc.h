@@ -483,7 +483,11 @@ typedef struct {
                                         2^this outputs run on the multi-node streaming kernel, the
                                         rest on the batched small-node kernel, 4..30 (taken from the
                                         first plan of a batch, each registered structure's plan) */
-    int32_t reserved[8];
+    int32_t gemm_tpw_max_nt;         /* matrix nodes: largest count of 16-column tiles (1, 2, 4) for
+                                        which a wave computes two row tiles; 0 = never */
+    int32_t gemm_orient;             /* matrix nodes: 0 = transposed tiles when the output's lowest
+                                        address bit is a row bit, 1 = always, 2 = never */
+    int32_t reserved[6];
 } wmc_tuning;
 
 /* The current table for a precision (a copy). */

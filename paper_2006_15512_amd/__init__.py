@@ -66,7 +66,8 @@ class wmc_tuning(ctypes.Structure):
                 ("stream_mfma_min_bits", ctypes.c_int32), ("stream2_tile_bits", ctypes.c_int32),
                 ("stream2_min_thread_bits", ctypes.c_int32), ("stream2_low_bits", ctypes.c_int32),
                 ("split_lanes", ctypes.c_int32), ("multi_min_rank", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("gemm_tpw_max_nt", ctypes.c_int32), ("gemm_orient", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 TUNING_FIELDS = [name for name, _ in wmc_tuning._fields_ if name != "reserved"]

@@ -197,17 +197,18 @@ def time_cost(plan, rates: Optional[Dict] = None) -> float:
 SEARCH_SPACE = {
     "fp64": {"stream2_grid_cap": [2048, 4096, 8192, 16384], "stream_mfma_grid_cap": [1024, 2048, 4096, 8192],
              "stream_mfma_min_bits": [0, 3, 4], "stream2_low_bits": [4, 6, 8], "split_lanes": [0, 4],
-             "stream2_tile_bits": [1, 2], "stream2_min_thread_bits": [12, 14, 16]},
+             "stream2_tile_bits": [1, 2], "stream2_min_thread_bits": [12, 14, 16],
+             "gemm_tpw_max_nt": [0, 1, 2, 4], "gemm_orient": [0, 1, 2]},
     "fp32": {"stream2_grid_cap": [768, 1536, 3072, 6144, 12288], "stream_mfma_grid_cap": [1024, 2048, 4096, 8192],
              "stream_mfma_min_bits": [0, 3, 4], "stream2_low_bits": [4, 6, 8], "stream2_tile_bits": [1, 2],
-             "stream2_min_thread_bits": [12, 14, 16]},
+             "stream2_min_thread_bits": [12, 14, 16], "gemm_tpw_max_nt": [0, 1, 2, 4], "gemm_orient": [0, 1, 2]},
 }
 
 
-def _time_plans(cases, precision: str, reps: int) -> float:
-    """Sum over the cases of the best-of-``reps`` seconds per solve."""
+def _time_plans(cases, precision: str, reps: int) -> List[float]:
+    """Best-of-``reps`` seconds per solve of each case."""
     import torch
-    total = 0.0
+    total = []
     for net, kw in cases:
         p = Plan(net, precision=precision, **kw)
         ws = workspace(p)
@@ -219,7 +220,7 @@ def _time_plans(cases, precision: str, reps: int) -> float:
             wmc_contract(p, None, ws)
             best = min(best, time.perf_counter() - t0)
         del ws
-        total += best
+        total.append(best)
     return total
 
 
@@ -275,9 +276,15 @@ def tune_executor(cases: Sequence[Tuple], precisions: Sequence[str] = ("fp64", "
     for prec in precisions:
         tuning_set(prec, None)
         cur = tuning_get(prec)
-        best_t = _time_plans(cases, prec, reps)
-        start_t = best_t
-        trace = [{"table": dict(cur), "s": best_t}]
+        # objective: mean time relative to the built-in table, so that every
+        # case counts alike whatever its length
+        base = _time_plans(cases, prec, reps)
+
+        def score(ts):
+            return sum(t / b for t, b in zip(ts, base)) / len(base)
+
+        best_t = 1.0
+        trace = [{"table": dict(cur), "s": base}]
         for _ in range(passes):
             changed = False
             for field, values in space[prec].items():
@@ -286,17 +293,19 @@ def tune_executor(cases: Sequence[Tuple], precisions: Sequence[str] = ("fp64", "
                         continue
                     trial = dict(cur, **{field: v})
                     tuning_set(prec, trial)
-                    t = _time_plans(cases, prec, reps)
-                    trace.append({field: v, "s": t})
+                    ts = _time_plans(cases, prec, reps)
+                    t = score(ts)
+                    trace.append({field: v, "s": ts})
                     if log:
-                        log(f"{prec} {field}={v}: {t * 1e3:.2f} ms (best {best_t * 1e3:.2f})")
-                    if t < best_t * 0.99:
+                        log(f"{prec} {field}={v}: relative {t:.4f} (best {best_t:.4f}) "
+                            f"[{', '.join(f'{x * 1e3:.2f}' for x in ts)} ms]")
+                    if t < best_t * 0.995:
                         best_t, cur, changed = t, trial, True
                 tuning_set(prec, cur)
             if not changed:
                 break
         tuning_set(prec, cur)
-        result[prec] = {"table": cur, "seconds": best_t, "default_seconds": start_t,
+        result[prec] = {"table": cur, "relative_time": best_t, "default_seconds": base,
                         "rates": _fit_rates(cases, prec), "trials": len(trace)}
     entry = {"device": device, **result}
     if path:

@@ -92,6 +92,7 @@ struct wmc_batch {
     std::vector<int64_t> inst_first;   // first instance of plan i (n + 1 entries)
     std::vector<unsigned long long> leaf_eta;  // slice of each leaf's instance
     uint64_t off_leaf_eta = 0;
+    GemmShape gemm_shape;              // from the first plan's tuning table
     int64_t n_vars_total = 0;          // auxiliary variables included
     int64_t n_user_total = 0;          // caller weights: 2 * n_user of each plan, in plan order
     std::vector<int64_t> var_off;
@@ -161,6 +162,7 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
     try {
         wmc_batch *B = new wmc_batch();
         B->precision = plans[0]->precision;
+        B->gemm_shape = GemmShape{plans[0]->tune.gemm_tpw_max_nt, plans[0]->tune.gemm_orient};
         B->elem = plans[0]->elem;
         B->n = n;
         // instances: slice eta of plan i is instance inst_first[i] + eta
@@ -369,7 +371,7 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
     for (size_t k = 1; k < B.launches.size(); ++k) {
         const Launch &Ln = B.launches[k];
         if (Ln.type == LAUNCH_GEMM) {
-            launch_gemm<T>(B.gemms[(size_t)Ln.pad], G + Ln.pad, arena, meta, st);
+            launch_gemm<T>(B.gemms[(size_t)Ln.pad], G + Ln.pad, arena, meta, st, SliceGroup{0, 0, 0}, 1, B.gemm_shape);
             continue;
         }
         // the merged step's small nodes and streaming tasks in one launch

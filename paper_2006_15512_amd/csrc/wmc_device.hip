@@ -94,7 +94,8 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
             StreamMfmaArgs ma;
             const int kern = solo_kernel<T>(P, k, &sa, &ma);
             if (kern == WMC_KERNEL_GEMM_P || kern == WMC_KERNEL_GEMM)
-                launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st, sg, nz);
+                launch_gemm<T>(P.gemms[(size_t)Ln.pad], Gd + Ln.pad, arena, meta, st, sg, nz,
+                               GemmShape{P.tune.gemm_tpw_max_nt, P.tune.gemm_orient});
             else if (kern == WMC_KERNEL_STREAM_MFMA)
                 launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
                                       (unsigned)P.tune.stream_mfma_grid_cap, sg, nz);

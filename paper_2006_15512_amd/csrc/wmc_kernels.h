@@ -449,7 +449,7 @@ __host__ __device__ constexpr int gemm_tpw(int nt) { return (sizeof(T) == 8 && n
 // computes the transposed tile (operands swapped: B^T A^T), so lane l holds
 // row l%16 and columns out_row(l/16, v); used when C's lowest address bits
 // belong to rows, so that 16 lanes store 16 consecutive elements.
-template <typename T, int NT, int S, bool SW>
+template <typename T, int NT, int S, bool SW, int TPW>
 __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, T *__restrict__ arena,
                                                 wmc_meta *meta, const SliceGroup sg) {
     WMC_ENTER_SLICE(arena, meta, sg);
@@ -470,7 +470,6 @@ __global__ void __launch_bounds__(256) k_gemm_p(const GemmDesc *__restrict__ G, 
     const int N = 1 << d.nn;
     constexpr int LDN = NT * 16 + (sizeof(T) == 8 ? 2 : 4);
     const unsigned long long tiles = 1ull << (d.nm - 4);
-    constexpr int TPW = gemm_tpw<T>(NT);
     const unsigned long long groups = (tiles + 4 * TPW - 1) / (4 * TPW);
     const unsigned long long beta = blockIdx.y;
     const long long a0 = d.a, c0 = d.c;
@@ -641,9 +640,18 @@ static inline bool gemm_persistent(const GemmDesc &hd) {
     return K >= 4 && K <= 64 && gemm_p_lds<T>(hd) <= (size_t)lds_budget();
 }
 
+// Launch shape of the persistent matrix kernel from the executor tuning
+// table: the largest column-tile count that takes two row tiles per wave
+// (-1: the built-in rule), and the orientation (0: transposed tiles when C's
+// lowest address bit is a row bit, 1: always transposed, 2: never).
+struct GemmShape {
+    int tpw_max_nt = -1;
+    int orient = 0;
+};
+
 template <typename T>
 static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_meta *meta, hipStream_t st,
-                        const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1) {
+                        const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1, GemmShape shape = GemmShape{}) {
     const int N = 1 << hd.nn, K = 1 << hd.nk;
     const int NT = (N + 15) / 16;
     const unsigned long long tiles = 1ull << (hd.nm - 4);
@@ -651,6 +659,8 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
     const size_t padded = gemm_p_lds<T>(hd);
     if (gemm_persistent<T>(hd)) {
         const int NTp = NT <= 1 ? 1 : NT <= 2 ? 2 : NT <= 4 ? 4 : 8;
+        // two row tiles per wave up to 4 column tiles (8 would not fit the registers)
+        const int tpw = NTp <= 4 && (shape.tpw_max_nt < 0 ? gemm_tpw<T>(NTp) == 2 : NTp <= shape.tpw_max_nt) ? 2 : 1;
         // persistent grid: as many workgroups as fit on the device at once
         auto grid_of = [&](const void *fn) {
             int dev = 0, cus = 256, per_cu = 2;
@@ -663,7 +673,7 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
             if (total < 1) total = 1;
             unsigned long long per_beta = (total + (1ull << hd.nb) - 1) >> hd.nb;
             if (per_beta < 1) per_beta = 1;
-            const unsigned long long tg = 4ull * (unsigned long long)gemm_tpw<T>(NTp);
+            const unsigned long long tg = 4ull * (unsigned long long)tpw;
             const unsigned long long pgroups = (tiles + tg - 1) / tg;
             return dim3((unsigned)(pgroups < per_beta ? pgroups : per_beta), 1u << hd.nb, nz);
         };
@@ -671,15 +681,20 @@ static void launch_gemm(const GemmDesc &hd, const GemmDesc *dd, T *arena, wmc_me
         bool sw = false;
         for (int q = 0; q < hd.nrun[GR_MU_C]; ++q)
             if (hd.run[GR_MU_C][q][2] == 0) sw = true;
-#define WMC_GP1(NTV, SV, SWV)                                                                                   \
-    if (NTp == NTV && K / 4 == SV && sw == SWV) {                                                              \
-        const void *fn = (const void *)&k_gemm_p<T, NTV, SV, SWV>;                                            \
-        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV, SWV>), grid_of(fn), dim3(256), padded, st, dd, arena, meta, sg); \
-        return;                                                                                               \
+        if (shape.orient == 1) sw = true;
+        if (shape.orient == 2) sw = false;
+#define WMC_GP1(NTV, SV, SWV, TPWV)                                                                            \
+    if (NTp == NTV && K / 4 == SV && sw == SWV && tpw == TPWV) {                                             \
+        const void *fn = (const void *)&k_gemm_p<T, NTV, SV, SWV, TPWV>;                                     \
+        hipLaunchKernelGGL((k_gemm_p<T, NTV, SV, SWV, TPWV>), grid_of(fn), dim3(256), padded, st, dd, arena, meta, \
+                           sg);                                                                              \
+        return;                                                                                              \
     }
-#define WMC_GP(NTV, SV) WMC_GP1(NTV, SV, false) WMC_GP1(NTV, SV, true)
-#define WMC_GP_S(NTV) WMC_GP(NTV, 1) WMC_GP(NTV, 2) WMC_GP(NTV, 4) WMC_GP(NTV, 8) WMC_GP(NTV, 16)
-        WMC_GP_S(1) WMC_GP_S(2) WMC_GP_S(4) WMC_GP_S(8)
+#define WMC_GP(NTV, SV, TPWV) WMC_GP1(NTV, SV, false, TPWV) WMC_GP1(NTV, SV, true, TPWV)
+#define WMC_GP_S(NTV, TPWV) \
+    WMC_GP(NTV, 1, TPWV) WMC_GP(NTV, 2, TPWV) WMC_GP(NTV, 4, TPWV) WMC_GP(NTV, 8, TPWV) WMC_GP(NTV, 16, TPWV)
+        WMC_GP_S(1, 1) WMC_GP_S(2, 1) WMC_GP_S(4, 1) WMC_GP_S(8, 1)
+        WMC_GP_S(1, 2) WMC_GP_S(2, 2) WMC_GP_S(4, 2)
 #undef WMC_GP_S
 #undef WMC_GP
 #undef WMC_GP1

@@ -56,6 +56,7 @@ struct SStruct {
     int32_t n_user = 0;           // a request brings 2 * n_user weights
     std::vector<double> w_aux;    // (1, 1) per auxiliary variable
     std::vector<GemmDesc> gemms;  // host copies (launch shapes); the device reads the resident ones
+    GemmShape gemm_shape;         // from the plan's tuning table
     std::vector<SLaunch> L;       // per launch of the plan; L[0] is the leaf fill
     uint64_t img_off = 0, img_bytes = 0;   // resident image (offset into the region pool)
     uint64_t leaves_off = 0, gemms_off = 0;
@@ -364,6 +365,7 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
         s.n_user = plan->n_user;
         s.w_aux.assign(plan->w.begin() + 2 * (size_t)plan->n_user, plan->w.end());
         s.gemms = plan->gemms;
+        s.gemm_shape = GemmShape{plan->tune.gemm_tpw_max_nt, plan->tune.gemm_orient};
         s.root = plan->root;
         s.root_off = plan->root >= 0 ? plan->T[(size_t)plan->root].off : 0;
         s.nt = (int64_t)std::max<size_t>(plan->T.size(), 1);
@@ -652,6 +654,7 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
         const GemmDesc *host;
         const GemmDesc *dev;
         long long abase, mbase;
+        GemmShape shape;
     };
     std::vector<GemmCall> gemms;
     std::vector<FinishEntry> fin;
@@ -686,7 +689,8 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
         } else {
             const SLaunch &L = s.L[r.k];
             if (L.type == LAUNCH_GEMM) {
-                gemms.push_back({&s.gemms[(size_t)L.gemm], (const GemmDesc *)(base + s.gemms_off) + L.gemm, abase, mbase});
+                gemms.push_back({&s.gemms[(size_t)L.gemm], (const GemmDesc *)(base + s.gemms_off) + L.gemm, abase, mbase,
+                                 s.gemm_shape});
             } else {
                 if (L.sblocks) {
                     w.tasks = (const StreamTask *)(base + L.tasks_off);
@@ -762,7 +766,7 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
                            (const ServeBlock *)(stp + o_b), (const ServeWave *)(stp + o_v), sblocks, nwaves, lwaves, arena,
                            meta);
     for (const GemmCall &g : gemms)
-        launch_gemm<T>(*g.host, g.dev, arena + g.abase, meta + g.mbase, st);
+        launch_gemm<T>(*g.host, g.dev, arena + g.abase, meta + g.mbase, st, SliceGroup{0, 0, 0}, 1, g.shape);
     ServeRes *res = (ServeRes *)(v->dev + v->off_res);
     if (!fin.empty()) {
         hipLaunchKernelGGL(k_finish_serve<T>, dim3((unsigned)((fin.size() + 255) / 256)), dim3(256), 0, st,
