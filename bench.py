@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 KERNEL_NAMES = ["k_begin", "k_leaves", "k_nodes", "k_gemm_p", "k_gemm", "k_stream_mfma", "k_stream2",
-                "k_stream2_split", "k_finish"]
-NODE_KERNELS = {2, 3, 4, 5, 6, 7}
+                "k_stream2_split", "k_finish", "k_stream2_vec"]
+NODE_KERNELS = {2, 3, 4, 5, 6, 7, 9}
 
 
 def workload(name: str):
@@ -255,6 +255,9 @@ def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_g
         ms += m
     ms /= reps
     n_slices = st["n_slices"]
+    # slices run G at a time (grid dimension z), so a launch entry of the
+    # per-slice schedule is ceil(n_slices / G) launches per solve
+    n_groups = -(-n_slices // max(1, st["slice_group"]))
     by_kernel = {}
     for k in range(len(bytes_l)):
         kn = KERNEL_NAMES[int(kern_l[k])]
@@ -262,7 +265,7 @@ def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_g
         e["ms"] += float(ms[k])
         e["bytes"] += float(bytes_l[k]) * n_slices
         e["flops"] += float(flops_l[k]) * n_slices
-        e["launches"] += n_slices
+        e["launches"] += n_groups
     total_ms = float(ms.sum())
     peak_tf = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
     table = {}
@@ -465,7 +468,8 @@ def profile_only(W, torch, args):
         a @ b
         torch.cuda.synchronize()
         print(f"gemm calibration: {2 * m ** 3} flops ({dt})", flush=True)
-    print(f"profile-only: {args.steps} solves, W = {v.mantissa} * 2^{v.exp2}", flush=True)
+    print(f"profile-only: {args.steps} solves, W = {v.mantissa} * 2^{v.exp2}, tuning {W.tuning_get(args.precision)}",
+          flush=True)
 
 
 def log(msg):
@@ -521,7 +525,8 @@ def main():
     torch.cuda.synchronize()
     first_s = time.perf_counter() - t0
     init = {"torch_context_s": round(context_s, 3), "first_solve_s": round(first_s, 3),
-            "process_to_first_result_s": round(time.perf_counter() - T_PROCESS0, 3)}
+            "process_to_first_result_s": round(time.perf_counter() - T_PROCESS0, 3),
+            "tuning": {"fp64": W.tuning_get("fp64"), "fp32": W.tuning_get("fp32")}}
 
     if args.workload == "batch512":
         print(json.dumps({"batch512": batch_leg(W, torch, args.steps, args.warmup)}), flush=True)

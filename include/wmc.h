@@ -329,7 +329,8 @@ enum {
     WMC_KERNEL_STREAM_MFMA = 5,   /* k_stream_mfma: streaming node on 16x16 MFMA blocks */
     WMC_KERNEL_STREAM2 = 6,       /* k_stream2: register-tiled streaming node */
     WMC_KERNEL_STREAM2_SPLIT = 7, /* k_stream2_split: summed index split over lane groups */
-    WMC_KERNEL_FINISH = 8         /* k_finish: slice accumulation */
+    WMC_KERNEL_FINISH = 8,        /* k_finish: slice accumulation */
+    WMC_KERNEL_STREAM2_VEC = 9    /* k_stream2_vec: K = 1 streaming node, output pairs per thread */
 };
 wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, int64_t cap, int64_t *n_out);
 
@@ -487,7 +488,9 @@ typedef struct {
                                         which a wave computes two row tiles; 0 = never */
     int32_t gemm_orient;             /* matrix nodes: 0 = transposed tiles when the output's lowest
                                         address bit is a row bit, 1 = always, 2 = never */
-    int32_t reserved[6];
+    int32_t stream2_vec;             /* K = 1 streaming nodes: 1 = each thread owns output bit 0 and
+                                        reads and writes entry pairs (k_stream2_vec), 0 = no */
+    int32_t reserved[5];
 } wmc_tuning;
 
 /* The current table for a precision (a copy). */

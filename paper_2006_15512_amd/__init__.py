@@ -67,7 +67,7 @@ class wmc_tuning(ctypes.Structure):
                 ("stream2_min_thread_bits", ctypes.c_int32), ("stream2_low_bits", ctypes.c_int32),
                 ("split_lanes", ctypes.c_int32), ("multi_min_rank", ctypes.c_int32),
                 ("gemm_tpw_max_nt", ctypes.c_int32), ("gemm_orient", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("stream2_vec", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 TUNING_FIELDS = [name for name, _ in wmc_tuning._fields_ if name != "reserved"]
@@ -537,7 +537,7 @@ def plan_launches(plan: Plan):
 
 
 KERNEL_NAMES = ["k_begin", "k_leaves", "k_nodes", "k_gemm_p", "k_gemm", "k_stream_mfma", "k_stream2",
-                "k_stream2_split", "k_finish"]
+                "k_stream2_split", "k_finish", "k_stream2_vec"]
 
 
 def plan_kernels(plan: Plan) -> np.ndarray:

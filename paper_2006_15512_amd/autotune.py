@@ -122,20 +122,21 @@ DEFAULT_RATES = {
 
 
 def _device_name() -> Optional[str]:
-    """cuda:0 as '<name> (<gfx arch>)', the key of the tuning tables."""
+    """cuda:0's architecture (e.g. 'gfx950'), the key of the tuning tables."""
     try:
         import torch
         if torch.cuda.is_available():
             prop = torch.cuda.get_device_properties(0)
             arch = getattr(prop, "gcnArchName", "").split(":")[0]
-            return f"{prop.name} ({arch})" if arch else prop.name
+            return arch or prop.name
     except Exception:  # noqa: BLE001 - no device, no table
         return None
     return None
 
 
 def load_table(path: str = TUNING_PATH, device: Optional[str] = None) -> Optional[Dict]:
-    """The tuning table stored for ``device`` (default: cuda:0's name)."""
+    """The tuning table stored for ``device`` (default: cuda:0's
+    architecture)."""
     device = device or _device_name()
     if not device or not os.path.exists(path):
         return None
@@ -198,10 +199,11 @@ SEARCH_SPACE = {
     "fp64": {"stream2_grid_cap": [2048, 4096, 8192, 16384], "stream_mfma_grid_cap": [1024, 2048, 4096, 8192],
              "stream_mfma_min_bits": [0, 3, 4], "stream2_low_bits": [4, 6, 8], "split_lanes": [0, 4],
              "stream2_tile_bits": [1, 2], "stream2_min_thread_bits": [12, 14, 16],
-             "gemm_tpw_max_nt": [0, 1, 2, 4], "gemm_orient": [0, 1, 2]},
+             "gemm_tpw_max_nt": [0, 1, 2, 4], "gemm_orient": [0, 1, 2], "stream2_vec": [0, 1]},
     "fp32": {"stream2_grid_cap": [768, 1536, 3072, 6144, 12288], "stream_mfma_grid_cap": [1024, 2048, 4096, 8192],
              "stream_mfma_min_bits": [0, 3, 4], "stream2_low_bits": [4, 6, 8], "stream2_tile_bits": [1, 2],
-             "stream2_min_thread_bits": [12, 14, 16], "gemm_tpw_max_nt": [0, 1, 2, 4], "gemm_orient": [0, 1, 2]},
+             "stream2_min_thread_bits": [12, 14, 16], "gemm_tpw_max_nt": [0, 1, 2, 4], "gemm_orient": [0, 1, 2],
+             "stream2_vec": [0, 1]},
 }
 
 

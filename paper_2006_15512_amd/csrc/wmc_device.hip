@@ -51,8 +51,10 @@ static int solo_kernel(const wmc_plan_t &P, size_t k, Stream2Args *sa, StreamMfm
         const NodeDesc &d = P.nodes[(size_t)Ln.first];
         const wmc_tuning &tu = P.tune;
         if (tu.stream_mfma_min_bits > 0 && stream_mfma_args(d, ma, tu.stream_mfma_min_bits)) return WMC_KERNEL_STREAM_MFMA;
-        if (stream2_args(d, sa, tu.stream2_tile_bits, tu.stream2_min_thread_bits, tu.stream2_low_bits))
-            return split_lanes_of<T>(P, d.nk) > 0 ? WMC_KERNEL_STREAM2_SPLIT : WMC_KERNEL_STREAM2;
+        if (stream2_args(d, sa, tu.stream2_tile_bits, tu.stream2_min_thread_bits, tu.stream2_low_bits,
+                         tu.stream2_vec != 0))
+            return sa->vec ? WMC_KERNEL_STREAM2_VEC
+                           : split_lanes_of<T>(P, d.nk) > 0 ? WMC_KERNEL_STREAM2_SPLIT : WMC_KERNEL_STREAM2;
     }
     return WMC_KERNEL_NODES;
 }
@@ -99,7 +101,7 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
             else if (kern == WMC_KERNEL_STREAM_MFMA)
                 launch_stream_mfma<T>(ma, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
                                       (unsigned)P.tune.stream_mfma_grid_cap, sg, nz);
-            else if ((kern == WMC_KERNEL_STREAM2 || kern == WMC_KERNEL_STREAM2_SPLIT) &&
+            else if ((kern == WMC_KERNEL_STREAM2 || kern == WMC_KERNEL_STREAM2_SPLIT || kern == WMC_KERNEL_STREAM2_VEC) &&
                      launch_stream2<T>(sa, P.nodes[(size_t)Ln.first].nk, arena, meta, st,
                                       kern == WMC_KERNEL_STREAM2_SPLIT ? split_lanes_of<T>(P, P.nodes[(size_t)Ln.first].nk) : 0,
                                       sg, nz, (unsigned)P.tune.stream2_grid_cap)) {

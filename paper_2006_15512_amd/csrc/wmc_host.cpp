@@ -1363,6 +1363,7 @@ static wmc_tuning default_tuning(int32_t precision) {
     t.multi_min_rank = 12;
     t.gemm_tpw_max_nt = precision == WMC_FP64 ? 2 : 0;
     t.gemm_orient = 0;
+    t.stream2_vec = precision == WMC_FP64 ? 1 : 0;  // FP64 pairs: 16-byte accesses; FP32 pairs measured slower
     return t;
 }
 
@@ -1387,7 +1388,7 @@ extern "C" wmc_status wmc_tuning_set(int32_t precision, const wmc_tuning *t) {
         !in(v.stream2_min_thread_bits, 0, 30) || !in(v.stream2_low_bits, 0, 16) ||
         !(v.split_lanes == 0 || v.split_lanes == 4) || !in(v.multi_min_rank, 4, 30) ||
         !(v.gemm_tpw_max_nt == 0 || v.gemm_tpw_max_nt == 1 || v.gemm_tpw_max_nt == 2 || v.gemm_tpw_max_nt == 4) ||
-        !in(v.gemm_orient, 0, 2))
+        !in(v.gemm_orient, 0, 2) || !in(v.stream2_vec, 0, 1))
         WMC_FAIL(WMC_ERR_INVALID_ARGUMENT, "wmc_tuning_set: a field is outside its range");
     std::memset(v.reserved, 0, sizeof v.reserved);
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -741,6 +741,7 @@ struct Stream2Args {
     unsigned orun[STREAM2_RUNS];       // C address -> O row
     int ro;                            // storage rank of O, summed bits included
     int o_lds;                         // O staged in LDS
+    int vec;                           // K = 1: output bit 0 handled inside the thread (k_stream2_vec)
 };
 
 // Bit extraction along at most MAX runs (unrolled with static indices, so
@@ -782,6 +783,10 @@ __device__ __forceinline__ void load_chunk(const T *__restrict__ p, double *v) {
         for (int k = 0; k < KC; ++k) v[k] = (double)p[k];
     }
 }
+
+// Two neighbouring outputs with one store (p is 2-element aligned).
+__device__ __forceinline__ void store_pair(double *p, double a, double b) { *(double2 *)p = make_double2(a, b); }
+__device__ __forceinline__ void store_pair(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
 
 // NP and NQ are compile-time so that the tile loops are straight-line code:
 // all loads issue before the first wait and no store waits on another.
@@ -995,11 +1000,93 @@ __global__ void __launch_bounds__(256) k_stream2_split(const Stream2Args args, T
     if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
 }
 
+// Elementwise and outer products (K = 1) with output bit 0 inside the
+// thread: each thread owns the two neighbouring outputs r and r | 1 of every
+// (p, q) of its P x Q tile, so S and O are read two entries at a time where
+// bit 0 is theirs (operands store their bits in C's order, so it is their
+// bit 0 too) and the outputs are stored in pairs (8 bytes in FP32, 16 in
+// FP64).  Products and rounding are those of k_stream2.
+template <typename T, int NP, int NQ>
+__global__ void __launch_bounds__(256) k_stream2_vec(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta,
+                                                     const SliceGroup sg) {
+    WMC_ENTER_SLICE(arena, meta, sg);
+    constexpr int P = 1 << NP, Q = 1 << NQ;
+    const int sS = scale_exp(meta[args.ts].maxbits);
+    const int sO = scale_exp(meta[args.to].maxbits);
+    const T *__restrict__ S = arena + args.s;
+    const T *__restrict__ O = arena + args.o;
+    T *__restrict__ C = arena + args.c;
+    // does output bit 0 belong to S, to O (either or both)
+    const bool s0b = apply_runs<STREAM2_RUNS>(1ull, args.srun, args.nsrun) != 0;
+    const bool o0b = apply_runs<STREAM2_RUNS>(1ull, args.orun, args.norun) != 0;
+    unsigned long long cP[P], sP[P], cQ[Q], oQ[Q];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) c |= (unsigned long long)((i >> t) & 1) << args.pbit[t];
+        cP[i] = uniform64(c);
+        sP[i] = uniform64(apply_runs<STREAM2_RUNS>(c, args.srun, args.nsrun));
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) c |= (unsigned long long)((j >> t) & 1) << args.qbit[t];
+        cQ[j] = uniform64(c);
+        oQ[j] = uniform64(apply_runs<STREAM2_RUNS>(c, args.orun, args.norun));
+    }
+    const int se = -(sS + sO);
+    const unsigned long long threads = 1ull << (args.rc - 1 - NP - NQ);
+    const unsigned G = gridDim.x;
+    const unsigned lb = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
+    double vmax = 0.0;
+    for (unsigned long long u = (unsigned long long)lb * blockDim.x + threadIdx.x; u < threads;
+         u += (unsigned long long)G * blockDim.x) {
+        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);  // bit 0 clear
+        const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
+        const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
+        double sv[P][2], ov[Q][2];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const T *p = S + (s0 | sP[i]);
+            if (s0b) {
+                load_chunk<T, 2>(p, sv[i]);
+            } else {
+                sv[i][0] = (double)p[0];
+                sv[i][1] = sv[i][0];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            const T *p = O + (o0 | oQ[j]);
+            if (o0b) {
+                load_chunk<T, 2>(p, ov[j]);
+            } else {
+                ov[j][0] = (double)p[0];
+                ov[j][1] = ov[j][0];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                const T v0 = (T)ldexp(fma(sv[i][0], ov[j][0], 0.0), se);
+                const T v1 = (T)ldexp(fma(sv[i][1], ov[j][1], 0.0), se);
+                store_pair(C + (r0 | cP[i] | cQ[j]), v0, v1);
+                vmax = fmax(vmax, fmax(fabs((double)v0), fabs((double)v1)));
+            }
+    }
+    publish_max_block(meta, args.tc, vmax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
+}
+
 // Arguments of the register-tiled streaming kernel for a single-node launch,
 // if the node fits it (at most 2^5 summed entries, run lists that fit).
 static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each = 2, int min_thread_bits = 14,
-                                int low = -1) {
+                                int low = -1, bool vec = false) {
     if (d.rc < 2 || d.nk > 5) return false;
+    vec = vec && d.nk == 0 && d.rc >= 8;
     auto bits_of = [&](const unsigned *runs, int nr, std::vector<int> &in) {
         int n = 0;
         for (int q = 0; q < nr; ++q) {
@@ -1048,7 +1135,7 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each 
     // operand row then run close together in time, so the row comes from
     // HBM once and from the L2 cache for its other readers.
     std::vector<int> rest;
-    for (int p = 0; p < d.rc; ++p) {
+    for (int p = vec ? 1 : 0; p < d.rc; ++p) {
         bool used = false;
         for (int t = 0; t < a->np; ++t) used |= a->pbit[t] == p;
         for (int t = 0; t < a->nq; ++t) used |= a->qbit[t] == p;
@@ -1077,7 +1164,8 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each 
     if (nl < 0) nl = make_runs(rest);
     if (nl < 0) return false;
     a->nlrun = nl;
-    a->o_lds = (1 << a->ro) <= STREAM2_O_LDS && d.rc >= 16;
+    a->o_lds = (1 << a->ro) <= STREAM2_O_LDS && d.rc >= 16 && !vec;
+    a->vec = vec ? 1 : 0;
     return true;
 }
 
@@ -1137,9 +1225,6 @@ __device__ __forceinline__ void load_row(const T *__restrict__ p, T *v) {
     }
 }
 
-// Two neighbouring outputs with one store (p is 2-element aligned).
-__device__ __forceinline__ void store_pair(double *p, double a, double b) { *(double2 *)p = make_double2(a, b); }
-__device__ __forceinline__ void store_pair(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
 
 template <typename T, int NK>
 __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, T *__restrict__ arena,
@@ -1166,17 +1251,20 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
     const unsigned long long aR = apply_runs<STREAM2_RUNS>(rowc, args.arun, args.nar);
     const unsigned long long bC = apply_runs<STREAM2_RUNS>(colc, args.brun, args.nbr);
     // write-out: element e of the tile (T bits ascending) sits at LDS index
-    // lds(e) and C offset off(e).  T's lowest bit is C bit 0, so elements
-    // 2p and 2p + 1 are neighbours in C: a thread stores such a pair with
-    // one instruction; bits 1..8 of e are this thread's
+    // lds(e) and C offset off(e).  T's lowest bits are C bits 0 and 1, so
+    // elements of one group of V (2 for FP64, 4 for FP32: 16 bytes either
+    // way) are neighbours in C: a thread stores such a group with one
+    // instruction; the next 8 bits of e are this thread's
+    constexpr int VB = sizeof(T) == 8 ? 1 : 2;  // in-thread bits of e
     unsigned lds_lo = 0;
     unsigned long long off_lo = 0;
-    for (int q = 1; q < args.nt && q < 9; ++q)
-        if ((threadIdx.x >> (q - 1)) & 1) {
+    for (int q = VB; q < args.nt && q < VB + 8; ++q)
+        if ((threadIdx.x >> (q - VB)) & 1) {
             lds_lo |= 1u << args.tdst[q];
             off_lo |= 1ull << args.tpos[q];
         }
     const unsigned lds_pair = 1u << args.tdst[0];
+    const unsigned lds_b1 = VB == 2 ? 1u << args.tdst[1] : 0u;
     const int nblk = 1 << args.nbt;
     const int mine = nblk > wave ? (nblk - wave + 3) / 4 : 0;  // blocks wave, wave + 4, ...
     // this wave's blocks: their C bits and operand row bits (uniform)
@@ -1191,15 +1279,15 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
         ablk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.arun, args.nar));
         bblk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.brun, args.nbr));
     }
-    // T bits 9..11 of the write-out index (uniform per iteration)
+    // T bits VB + 8 .. 11 of the write-out index (uniform per iteration)
     unsigned hdst[3];
     unsigned long long hoff[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        hdst[q] = 9 + q < args.nt ? 1u << args.tdst[9 + q] : 0u;
-        hoff[q] = 9 + q < args.nt ? 1ull << args.tpos[9 + q] : 0ull;
+        hdst[q] = VB + 8 + q < args.nt ? 1u << args.tdst[VB + 8 + q] : 0u;
+        hoff[q] = VB + 8 + q < args.nt ? 1ull << args.tpos[VB + 8 + q] : 0ull;
     }
-    const unsigned npair = 1u << (args.nt - 1);
+    const unsigned npair = 1u << (args.nt - VB);  // groups of V elements
     const unsigned nit = npair > 256u ? npair >> 8 : 1u;
     const unsigned long long tiles = 1ull << (args.rc - args.nt);
     const unsigned G = gridDim.x;
@@ -1248,13 +1336,21 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
             if (threadIdx.x < npair) {
                 // columns are stored XOR-ed with row and block (fewer bank
                 // conflicts whichever of them the lanes walk)
-                unsigned l1 = li | lds_pair;
-                li ^= ((li >> 4) ^ (li >> 8)) & 15u;
-                l1 ^= ((l1 >> 4) ^ (l1 >> 8)) & 15u;
-                const T v0 = (T)ldexp((double)tile[li], se);
-                const T v1 = (T)ldexp((double)tile[l1], se);
-                store_pair(C + off, v0, v1);
-                vmax = fmax(vmax, fmax(fabs((double)v0), fabs((double)v1)));
+                auto at = [](unsigned l) { return l ^ (((l >> 4) ^ (l >> 8)) & 15u); };
+                if constexpr (VB == 1) {
+                    const T v0 = (T)ldexp((double)tile[at(li)], se);
+                    const T v1 = (T)ldexp((double)tile[at(li | lds_pair)], se);
+                    store_pair(C + off, v0, v1);
+                    vmax = fmax(vmax, fmax(fabs((double)v0), fabs((double)v1)));
+                } else {
+                    const T v0 = (T)ldexp((double)tile[at(li)], se);
+                    const T v1 = (T)ldexp((double)tile[at(li | lds_pair)], se);
+                    const T v2 = (T)ldexp((double)tile[at(li | lds_b1)], se);
+                    const T v3 = (T)ldexp((double)tile[at(li | lds_pair | lds_b1)], se);
+                    *(float4 *)(C + off) = make_float4(v0, v1, v2, v3);
+                    vmax = fmax(vmax, fmax(fmax(fabs((double)v0), fabs((double)v1)),
+                                           fmax(fabs((double)v2), fabs((double)v3))));
+                }
             }
         }
         __syncthreads();
@@ -1385,7 +1481,8 @@ static void launch_stream_mfma(const StreamMfmaArgs &a, int nk, T *arena, wmc_me
 template <typename T>
 static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st, int lg = 0,
                            const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1, unsigned grid_cap = 0) {
-    const unsigned long long threads = (1ull << (sa.rc - sa.np - sa.nq)) * (unsigned long long)(lg > 0 ? lg : 1);
+    const unsigned long long threads =
+        (1ull << (sa.rc - sa.np - sa.nq - (sa.vec ? 1 : 0))) * (unsigned long long)(lg > 0 ? lg : 1);
     unsigned long long blocks = (threads + 255) / 256;
     // grid cap (measured on the sliced banded formula): FP32 runs fastest
     // with about one resident round of workgroups looping over the outputs,
@@ -1403,6 +1500,18 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
     if (a.o_lds && outs_per_wg < (16ull << sa.ro)) a.o_lds = 0;
     const size_t lds = a.o_lds ? sizeof(double) << a.ro : 0;
     const dim3 g((unsigned)blocks, 1, nz), b(256);
+    if (a.vec) {
+        if (nk != 0) return false;
+#define WMC_S2V(NPV, NQV)                                                                     \
+    if (a.np == NPV && a.nq == NQV) {                                                          \
+        hipLaunchKernelGGL((k_stream2_vec<T, NPV, NQV>), g, b, 0, st, a, arena, meta, sg);    \
+        return true;                                                                           \
+    }
+        WMC_S2V(0, 0) WMC_S2V(0, 1) WMC_S2V(0, 2) WMC_S2V(1, 0) WMC_S2V(1, 1) WMC_S2V(1, 2) WMC_S2V(2, 0)
+        WMC_S2V(2, 1) WMC_S2V(2, 2)
+#undef WMC_S2V
+        return false;
+    }
     if constexpr (sizeof(T) == 8) {
         if (lg > 0) {
 #define WMC_S2X(NKV, LGV, NPV, NQV)                                                                    \

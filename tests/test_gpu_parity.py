@@ -472,6 +472,31 @@ def test_banded300_all_slices_in_one_group_vs_golden(precision, tol):
     assert rel(value_fraction(v), ref) <= tol
 
 
+# ------------------------------------------------------------------ executor tuning
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_paired_k1_kernel_is_bit_identical(precision):
+    """K = 1 streaming nodes with output bit 0 inside the thread (entry pairs)
+    round exactly as the one-output-per-thread kernel: the same plan with the
+    tuning switched either way gives the same bits, and the oracle's value."""
+    f = wl.banded_3cnf(200, 700, 26, seed=6)
+    net = W.Network.from_formula(f)
+    saved = W.tuning_get(precision)
+    try:
+        vals = []
+        for vec in (0, 1):
+            W.tuning_set(precision, {"stream2_vec": vec, "stream_mfma_min_bits": 0})
+            p = W.Plan(net, seed=0, block=3, precision=precision)
+            kinds = set(W.KERNEL_NAMES[k] for k in W.plan_kernels(p))
+            assert ("k_stream2_vec" in kinds) == bool(vec), kinds
+            vals.append(W.wmc_contract(p))
+    finally:
+        W.tuning_set(precision, saved)
+    assert (vals[0].mantissa, vals[0].exp2) == (vals[1].mantissa, vals[1].exp2)
+    m, e = oracle.bucket(f)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert rel(value_fraction(vals[1]), Fraction(m) * Fraction(2) ** e) <= tol
+
+
 # ------------------------------------------------------------------ Algorithm 1's anytime loop
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_anytime_plan_on_device_vs_oracle(precision, tol):
