@@ -76,9 +76,11 @@ def workload(name: str):
 
 
 def source_digest() -> str:
+    """Digest of what decides the launched kernels: their sources, the
+    per-node kernel choice and the tuning table."""
     h = hashlib.sha256()
-    for s in ("wmc_kernels.h", "wmc_desc.h"):
-        with open(os.path.join(ROOT, "paper_2006_15512_amd", "csrc", s), "rb") as fh:
+    for s in ("csrc/wmc_kernels.h", "csrc/wmc_desc.h", "csrc/wmc_device.hip", "tuning.json"):
+        with open(os.path.join(ROOT, "paper_2006_15512_amd", s), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
