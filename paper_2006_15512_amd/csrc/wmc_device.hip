@@ -43,7 +43,7 @@ static inline int split_lanes_of(const wmc_plan_t &P, int nk) {
 // solo plan, with the streaming kernels' arguments filled in when one of
 // them is chosen.  The executor and wmc_plan_kernels share this choice.
 template <typename T>
-static int solo_kernel(const wmc_plan_t &P, size_t k, Stream2Args *sa, StreamMfmaArgs *ma) {
+static int solo_kernel(const wmc_plan_t &P, size_t k, Stream2Tab *tb, StreamMfmaArgs *ma) {
     const Launch &Ln = P.launches[k];
     if (Ln.type == LAUNCH_GEMM)
         return gemm_persistent<T>(P.gemms[(size_t)Ln.pad]) ? WMC_KERNEL_GEMM_P : WMC_KERNEL_GEMM;
@@ -51,10 +51,13 @@ static int solo_kernel(const wmc_plan_t &P, size_t k, Stream2Args *sa, StreamMfm
         const NodeDesc &d = P.nodes[(size_t)Ln.first];
         const wmc_tuning &tu = P.tune;
         if (tu.stream_mfma_min_bits > 0 && stream_mfma_args(d, ma, tu.stream_mfma_min_bits)) return WMC_KERNEL_STREAM_MFMA;
-        if (stream2_args(d, sa, tu.stream2_tile_bits, tu.stream2_min_thread_bits, tu.stream2_low_bits,
-                         tu.stream2_vec != 0))
-            return sa->vec ? WMC_KERNEL_STREAM2_VEC
-                           : split_lanes_of<T>(P, d.nk) > 0 ? WMC_KERNEL_STREAM2_SPLIT : WMC_KERNEL_STREAM2;
+        if (stream2_args(d, &tb->a, tu.stream2_tile_bits, tu.stream2_min_thread_bits, tu.stream2_low_bits,
+                         tu.stream2_vec != 0)) {
+            const int lg = tb->a.vec ? 0 : split_lanes_of<T>(P, d.nk);
+            // work items per workgroup: 256 threads, or 256 / lg lane groups
+            if (stream2_tab(tb, lg > 0 ? 8 - (lg == 4 ? 2 : lg == 2 ? 1 : 3) : 8))
+                return tb->a.vec ? WMC_KERNEL_STREAM2_VEC : lg > 0 ? WMC_KERNEL_STREAM2_SPLIT : WMC_KERNEL_STREAM2;
+        }
     }
     return WMC_KERNEL_NODES;
 }
@@ -92,7 +95,7 @@ static wmc_status run_slices(const wmc_plan_t &P, char *ws, hipStream_t st, long
         if (tm) tm->mark();
         for (size_t k = 1; k < P.launches.size(); ++k) {
             const Launch &Ln = P.launches[k];
-            Stream2Args sa;
+            Stream2Tab sa;
             StreamMfmaArgs ma;
             const int kern = solo_kernel<T>(P, k, &sa, &ma);
             if (kern == WMC_KERNEL_GEMM_P || kern == WMC_KERNEL_GEMM)
@@ -329,7 +332,7 @@ extern "C" wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, 
     kernel[0] = WMC_KERNEL_BEGIN;
     kernel[1] = WMC_KERNEL_LEAVES;
     for (size_t k = 1; k < P.launches.size(); ++k) {
-        Stream2Args sa;
+        Stream2Tab sa;
         StreamMfmaArgs ma;
         kernel[k + 1] = P.precision == WMC_FP64 ? solo_kernel<double>(P, k, &sa, &ma) : solo_kernel<float>(P, k, &sa, &ma);
     }

@@ -744,6 +744,55 @@ struct Stream2Args {
     int vec;                           // K = 1: output bit 0 handled inside the thread (k_stream2_vec)
 };
 
+// The solo kernels' thread-index maps as tables.  A thread's work item u is
+// (uh << lbits) | ul, uh uniform in the workgroup (its tile round) and ul
+// the lane's part; the C address r0 = lmap(u) and the operand rows
+// smap(r0), omap(r0) are bit deposits onto disjoint bits, hence linear in
+// the bits of u: each is hi(uh) | lo(ul).  hi is an OR over 4-bit chunks of
+// uh, looked up with scalar loads from the kernel arguments; lo is read once
+// per thread.  This replaces three run expansions per work item (dozens of
+// 64-bit shifts, and spills of the run words) with a few scalar loads.
+#define STREAM2_NCH 7
+
+struct Stream2Tab {
+    Stream2Args a;
+    int lbits, nch, pad0, pad1;
+    unsigned long long hr[STREAM2_NCH][16], hs[STREAM2_NCH][16], ho[STREAM2_NCH][16];
+    unsigned long long lr[2][16], ls[2][16], lo[2][16];
+};
+
+// Tables of t->a for lane parts of lbits bits; false if the uniform part
+// needs more than STREAM2_NCH chunks.
+static inline bool stream2_tab(Stream2Tab *t, int lbits) {
+    const Stream2Args &a = t->a;
+    auto runs = [](unsigned long long r, const unsigned *rn, int n) {
+        unsigned long long out = 0;
+        for (int i = 0; i < n; ++i)
+            out |= ((r >> (rn[i] & 255u)) & ((1ull << ((rn[i] >> 8) & 255u)) - 1ull)) << (rn[i] >> 16);
+        return out;
+    };
+    const int ubits = a.rc - a.np - a.nq - (a.vec ? 1 : 0);
+    const int hbits = ubits > lbits ? ubits - lbits : 0;
+    t->lbits = lbits;
+    t->nch = (hbits + 3) / 4;
+    if (t->nch > STREAM2_NCH || lbits > 8) return false;
+    auto fill = [&](unsigned long long u, unsigned long long *r, unsigned long long *sr, unsigned long long *orow) {
+        const unsigned long long c = runs(u, a.lrun, a.nlrun);
+        *r = c;
+        *sr = runs(c, a.srun, a.nsrun);
+        *orow = runs(c, a.orun, a.norun);
+    };
+    for (unsigned v = 0; v < 16; ++v) {
+        for (int c = 0; c < t->nch; ++c)
+            fill((unsigned long long)v << (lbits + 4 * c), &t->hr[c][v], &t->hs[c][v], &t->ho[c][v]);
+        for (int c = 0; c < 2; ++c) {
+            const unsigned long long u = ((unsigned long long)v << (4 * c)) & ((1ull << lbits) - 1ull);
+            fill(u, &t->lr[c][v], &t->ls[c][v], &t->lo[c][v]);
+        }
+    }
+    return true;
+}
+
 // Bit extraction along at most MAX runs (unrolled with static indices, so
 // run words passed in kernel arguments stay in scalar registers).
 template <int MAX, typename RP>
@@ -791,9 +840,10 @@ __device__ __forceinline__ void store_pair(float *p, float a, float b) { *(float
 // NP and NQ are compile-time so that the tile loops are straight-line code:
 // all loads issue before the first wait and no store waits on another.
 template <typename T, int NK, int NP, int NQ>
-__global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta,
+__global__ void __launch_bounds__(256) k_stream2(const Stream2Tab tab, T *__restrict__ arena, wmc_meta *meta,
                                                  const SliceGroup sg) {
     WMC_ENTER_SLICE(arena, meta, sg);
+    const Stream2Args &args = tab.a;
     extern __shared__ char smem_raw[];
     double *Os = (double *)smem_raw;  // 2^ro entries when O is staged, else none
     constexpr int K = 1 << NK;
@@ -836,11 +886,21 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Args args, T *__re
     const unsigned G = gridDim.x;
     const unsigned lb = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
     double vmax = 0.0;
-    for (unsigned long long u = (unsigned long long)lb * blockDim.x + threadIdx.x; u < threads;
-         u += (unsigned long long)G * blockDim.x) {
-        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);
-        const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
-        const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
+    const unsigned ul = threadIdx.x;
+    const unsigned long long rl = tab.lr[0][ul & 15u] | tab.lr[1][(ul >> 4) & 15u];
+    const unsigned long long sl = tab.ls[0][ul & 15u] | tab.ls[1][(ul >> 4) & 15u];
+    const unsigned long long ol = tab.lo[0][ul & 15u] | tab.lo[1][(ul >> 4) & 15u];
+    for (unsigned long long uh = lb; (uh << 8) < threads; uh += G) {
+        if (((uh << 8) | ul) >= threads) continue;
+        unsigned long long r0 = rl, s0 = sl, o0 = ol;
+#pragma unroll
+        for (int c = 0; c < STREAM2_NCH; ++c)
+            if (c < tab.nch) {
+                const unsigned v = (unsigned)(uh >> (4 * c)) & 15u;
+                r0 |= tab.hr[c][v];
+                s0 |= tab.hs[c][v];
+                o0 |= tab.ho[c][v];
+            }
         double acc[P][Q];
 #pragma unroll
         for (int i = 0; i < P; ++i)
@@ -920,9 +980,10 @@ __device__ __forceinline__ void group_reduce_scatter(double *v, int lane, int &f
 }
 
 template <typename T, int NK, int NP, int NQ, int LG>
-__global__ void __launch_bounds__(256) k_stream2_split(const Stream2Args args, T *__restrict__ arena,
+__global__ void __launch_bounds__(256) k_stream2_split(const Stream2Tab tab, T *__restrict__ arena,
                                                        wmc_meta *meta, const SliceGroup sg) {
     WMC_ENTER_SLICE(arena, meta, sg);
+    const Stream2Args &args = tab.a;
     constexpr int K = 1 << NK;
     constexpr int KL = K / LG;  // summed entries per lane and row
     constexpr int P = 1 << NP, Q = 1 << NQ, PQ = P * Q;
@@ -957,11 +1018,22 @@ __global__ void __launch_bounds__(256) k_stream2_split(const Stream2Args args, T
     double vmax = 0.0;
     // a group's lanes share u, so every lane of a group runs the same
     // iterations and the exchanges below stay inside active groups
-    for (unsigned long long u = (unsigned long long)lb * GPB + threadIdx.x / LG; u < groups;
-         u += (unsigned long long)G * GPB) {
-        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);
-        const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
-        const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
+    // work item u = uh * GPB + ul (tables for lane parts of log2 GPB bits)
+    const unsigned ul = threadIdx.x / LG;
+    const unsigned long long rl = tab.lr[0][ul & 15u] | tab.lr[1][(ul >> 4) & 15u];
+    const unsigned long long sl = tab.ls[0][ul & 15u] | tab.ls[1][(ul >> 4) & 15u];
+    const unsigned long long ol = tab.lo[0][ul & 15u] | tab.lo[1][(ul >> 4) & 15u];
+    for (unsigned long long uh = lb; uh * GPB < groups; uh += G) {
+        if (uh * GPB + ul >= groups) continue;
+        unsigned long long r0 = rl, s0 = sl, o0 = ol;
+#pragma unroll
+        for (int c = 0; c < STREAM2_NCH; ++c)
+            if (c < tab.nch) {
+                const unsigned v = (unsigned)(uh >> (4 * c)) & 15u;
+                r0 |= tab.hr[c][v];
+                s0 |= tab.hs[c][v];
+                o0 |= tab.ho[c][v];
+            }
         double sv[P][KL], ov[Q][KL];
 #pragma unroll
         for (int i = 0; i < P; ++i) load_chunk<T, KL>(S + (((s0 | sP[i]) << NK) + lane * KL), sv[i]);
@@ -1007,9 +1079,10 @@ __global__ void __launch_bounds__(256) k_stream2_split(const Stream2Args args, T
 // bit 0 too) and the outputs are stored in pairs (8 bytes in FP32, 16 in
 // FP64).  Products and rounding are those of k_stream2.
 template <typename T, int NP, int NQ>
-__global__ void __launch_bounds__(256) k_stream2_vec(const Stream2Args args, T *__restrict__ arena, wmc_meta *meta,
+__global__ void __launch_bounds__(256) k_stream2_vec(const Stream2Tab tab, T *__restrict__ arena, wmc_meta *meta,
                                                      const SliceGroup sg) {
     WMC_ENTER_SLICE(arena, meta, sg);
+    const Stream2Args &args = tab.a;
     constexpr int P = 1 << NP, Q = 1 << NQ;
     const int sS = scale_exp(meta[args.ts].maxbits);
     const int sO = scale_exp(meta[args.to].maxbits);
@@ -1041,11 +1114,21 @@ __global__ void __launch_bounds__(256) k_stream2_vec(const Stream2Args args, T *
     const unsigned G = gridDim.x;
     const unsigned lb = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
     double vmax = 0.0;
-    for (unsigned long long u = (unsigned long long)lb * blockDim.x + threadIdx.x; u < threads;
-         u += (unsigned long long)G * blockDim.x) {
-        const unsigned long long r0 = apply_runs<STREAM2_LRUNS>(u, args.lrun, args.nlrun);  // bit 0 clear
-        const unsigned long long s0 = apply_runs<STREAM2_RUNS>(r0, args.srun, args.nsrun);
-        const unsigned long long o0 = apply_runs<STREAM2_RUNS>(r0, args.orun, args.norun);
+    const unsigned ul = threadIdx.x;
+    const unsigned long long rl = tab.lr[0][ul & 15u] | tab.lr[1][(ul >> 4) & 15u];
+    const unsigned long long sl = tab.ls[0][ul & 15u] | tab.ls[1][(ul >> 4) & 15u];
+    const unsigned long long ol = tab.lo[0][ul & 15u] | tab.lo[1][(ul >> 4) & 15u];
+    for (unsigned long long uh = lb; (uh << 8) < threads; uh += G) {
+        if (((uh << 8) | ul) >= threads) continue;
+        unsigned long long r0 = rl, s0 = sl, o0 = ol;  // r0: bit 0 clear
+#pragma unroll
+        for (int c = 0; c < STREAM2_NCH; ++c)
+            if (c < tab.nch) {
+                const unsigned v = (unsigned)(uh >> (4 * c)) & 15u;
+                r0 |= tab.hr[c][v];
+                s0 |= tab.hs[c][v];
+                o0 |= tab.ho[c][v];
+            }
         double sv[P][2], ov[Q][2];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
@@ -1185,6 +1268,7 @@ static inline bool stream2_args(const NodeDesc &d, Stream2Args *a, int max_each 
 // segments.  The remaining output bits number the workgroup tiles,
 // one-operand bits first, so tiles sharing operand rows run together.
 #define SMFMA_MAX_T 12
+#define SMFMA_NCH 7  // 4-bit chunks of the tile index (tiles < 2^28)
 
 struct StreamMfmaArgs {
     long long a, b, c;                 // element offsets: row operand, column operand, C
@@ -1201,6 +1285,17 @@ struct StreamMfmaArgs {
     unsigned wbrun[STREAM2_LRUNS];     // tile index -> B row bits
     unsigned arun[STREAM2_RUNS];       // C address -> A row
     unsigned brun[STREAM2_RUNS];       // C address -> B row
+    // the three tile-index maps by 4-bit chunk: map(wt) = OR over chunks c of
+    // tab[c][(wt >> 4c) & 15] (each map deposits disjoint bits, so it is
+    // linear in the chunks); the tile index is uniform in a workgroup, so a
+    // lookup is one scalar load from the kernel arguments
+    int nch;
+    unsigned long long tabc[SMFMA_NCH][16];  // C bits outside T
+    unsigned long long taba[SMFMA_NCH][16];  // A row bits
+    unsigned long long tabb[SMFMA_NCH][16];  // B row bits
+    // a lane's row (column) inside a block and a block's batch value, as
+    // operand row bits: A rows by lane l % 16, B rows by lane, and both by block
+    unsigned long long lane_a[16], lane_b[16], blk_a[16], blk_b[16];
 };
 
 // N consecutive entries of a row in the storage type (N a multiple of 4).
@@ -1243,13 +1338,8 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
     const T *__restrict__ B = arena + args.b;
     T *__restrict__ C = arena + args.c;
     // this lane's row and column inside a block, as operand row offsets
-    unsigned long long rowc = 0, colc = 0;
-    for (int t = 0; t < args.nrb; ++t)
-        if ((l16 >> t) & 1) rowc |= 1ull << args.rbit[t];
-    for (int t = 0; t < args.ncb; ++t)
-        if ((l16 >> t) & 1) colc |= 1ull << args.cbit[t];
-    const unsigned long long aR = apply_runs<STREAM2_RUNS>(rowc, args.arun, args.nar);
-    const unsigned long long bC = apply_runs<STREAM2_RUNS>(colc, args.brun, args.nbr);
+    const unsigned long long aR = args.lane_a[l16];
+    const unsigned long long bC = args.lane_b[l16];
     // write-out: element e of the tile (T bits ascending) sits at LDS index
     // lds(e) and C offset off(e).  T's lowest bits are C bits 0 and 1, so
     // elements of one group of V (2 for FP64, 4 for FP32: 16 bytes either
@@ -1271,13 +1361,9 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
     unsigned long long ablk[NBW], bblk[NBW];
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
-        const int bt = wave + 4 * i;
-        unsigned long long cb = 0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            if (t < args.nbt && ((bt >> t) & 1)) cb |= 1ull << args.tbit[t];
-        ablk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.arun, args.nar));
-        bblk[i] = uniform64(apply_runs<STREAM2_RUNS>(cb, args.brun, args.nbr));
+        const int bt = (wave + 4 * i) & 15;
+        ablk[i] = uniform64(args.blk_a[bt]);
+        bblk[i] = uniform64(args.blk_b[bt]);
     }
     // T bits VB + 8 .. 11 of the write-out index (uniform per iteration)
     unsigned hdst[3];
@@ -1295,9 +1381,16 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
     T av[NBW][KG], bv[NBW][KG];
     // operands of tile wt, issued one tile ahead so that their latency
     // overlaps the previous tile's write-out
+    auto tile_map = [&](unsigned long long wt, const unsigned long long (*tab)[16]) {
+        unsigned long long r = 0;
+#pragma unroll
+        for (int c = 0; c < SMFMA_NCH; ++c)
+            if (c < args.nch) r |= tab[c][(unsigned)(wt >> (4 * c)) & 15u];
+        return r;
+    };
     auto load_tile = [&](unsigned long long wt) {
-        const unsigned long long ab = apply_runs<STREAM2_LRUNS>(wt, args.warun, args.nwarun);
-        const unsigned long long bb = apply_runs<STREAM2_LRUNS>(wt, args.wbrun, args.nwbrun);
+        const unsigned long long ab = tile_map(wt, args.taba);
+        const unsigned long long bb = tile_map(wt, args.tabb);
 #pragma unroll
         for (int i = 0; i < NBW; ++i)
             if (i < mine) {
@@ -1308,7 +1401,7 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
     double vmax = 0.0;
     if (lb < tiles) load_tile(lb);
     for (unsigned long long wt = lb; wt < tiles; wt += G) {
-        const unsigned long long base = apply_runs<STREAM2_LRUNS>(wt, args.wrun, args.nwrun);
+        const unsigned long long base = tile_map(wt, args.tabc);
 #pragma unroll
         for (int i = 0; i < NBW; ++i)
             if (i < mine) {
@@ -1461,6 +1554,36 @@ static inline bool stream_mfma_args(const NodeDesc &d, StreamMfmaArgs *a, int mi
     a->nbr = d.nrb;
     for (int q = 0; q < d.nra; ++q) a->arun[q] = d.ra[q];
     for (int q = 0; q < d.nrb; ++q) a->brun[q] = d.rb[q];
+    // chunk tables of the tile-index maps
+    const int nbits = d.rc - a->nt;
+    a->nch = (nbits + 3) / 4;
+    if (a->nch > SMFMA_NCH) return false;
+    auto host_runs = [](unsigned long long r, const unsigned *runs, int n) {
+        unsigned long long out = 0;
+        for (int i = 0; i < n; ++i)
+            out |= ((r >> (runs[i] & 255u)) & ((1ull << ((runs[i] >> 8) & 255u)) - 1ull)) << (runs[i] >> 16);
+        return out;
+    };
+    for (int c = 0; c < a->nch; ++c)
+        for (unsigned v = 0; v < 16; ++v) {
+            const unsigned long long w = (unsigned long long)v << (4 * c);
+            a->tabc[c][v] = host_runs(w, a->wrun, a->nwrun);
+            a->taba[c][v] = host_runs(w, a->warun, a->nwarun);
+            a->tabb[c][v] = host_runs(w, a->wbrun, a->nwbrun);
+        }
+    for (unsigned v = 0; v < 16; ++v) {
+        unsigned long long rowc = 0, colc = 0, cb = 0;
+        for (int t = 0; t < a->nrb; ++t)
+            if ((v >> t) & 1) rowc |= 1ull << a->rbit[t];
+        for (int t = 0; t < a->ncb; ++t)
+            if ((v >> t) & 1) colc |= 1ull << a->cbit[t];
+        for (int t = 0; t < a->nbt; ++t)
+            if ((v >> t) & 1) cb |= 1ull << a->tbit[t];
+        a->lane_a[v] = host_runs(rowc, a->arun, a->nar);
+        a->lane_b[v] = host_runs(colc, a->brun, a->nbr);
+        a->blk_a[v] = host_runs(cb, a->arun, a->nar);
+        a->blk_b[v] = host_runs(cb, a->brun, a->nbr);
+    }
     return true;
 }
 
@@ -1479,8 +1602,9 @@ static void launch_stream_mfma(const StreamMfmaArgs &a, int nk, T *arena, wmc_me
 
 // Returns false (nothing launched) if no instance covers the arguments.
 template <typename T>
-static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *meta, hipStream_t st, int lg = 0,
+static bool launch_stream2(const Stream2Tab &tb, int nk, T *arena, wmc_meta *meta, hipStream_t st, int lg = 0,
                            const SliceGroup sg = SliceGroup{0, 0, 0}, unsigned nz = 1, unsigned grid_cap = 0) {
+    const Stream2Args &sa = tb.a;
     const unsigned long long threads =
         (1ull << (sa.rc - sa.np - sa.nq - (sa.vec ? 1 : 0))) * (unsigned long long)(lg > 0 ? lg : 1);
     unsigned long long blocks = (threads + 255) / 256;
@@ -1495,7 +1619,8 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
     if (blocks >= 64) blocks = (blocks + 7) & ~7ull;  // whole XCD rounds; threads past the end idle
     // stage O in LDS only where each workgroup reuses it at least 16 times
     // over; smaller reuse is served by the caches without the staging pass
-    Stream2Args a = sa;
+    Stream2Tab t = tb;
+    Stream2Args &a = t.a;
     const unsigned long long outs_per_wg = (1ull << sa.rc) / blocks;
     if (a.o_lds && outs_per_wg < (16ull << sa.ro)) a.o_lds = 0;
     const size_t lds = a.o_lds ? sizeof(double) << a.ro : 0;
@@ -1504,7 +1629,7 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
         if (nk != 0) return false;
 #define WMC_S2V(NPV, NQV)                                                                     \
     if (a.np == NPV && a.nq == NQV) {                                                          \
-        hipLaunchKernelGGL((k_stream2_vec<T, NPV, NQV>), g, b, 0, st, a, arena, meta, sg);    \
+        hipLaunchKernelGGL((k_stream2_vec<T, NPV, NQV>), g, b, 0, st, t, arena, meta, sg);    \
         return true;                                                                           \
     }
         WMC_S2V(0, 0) WMC_S2V(0, 1) WMC_S2V(0, 2) WMC_S2V(1, 0) WMC_S2V(1, 1) WMC_S2V(1, 2) WMC_S2V(2, 0)
@@ -1516,7 +1641,7 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
         if (lg > 0) {
 #define WMC_S2X(NKV, LGV, NPV, NQV)                                                                    \
     if (nk == NKV && lg == LGV && a.np == NPV && a.nq == NQV) {                                        \
-        hipLaunchKernelGGL((k_stream2_split<T, NKV, NPV, NQV, LGV>), g, b, 0, st, a, arena, meta, sg);  \
+        hipLaunchKernelGGL((k_stream2_split<T, NKV, NPV, NQV, LGV>), g, b, 0, st, t, arena, meta, sg);  \
         return true;                                                                                   \
     }
 #define WMC_S2X_PQ(NKV, LGV)                                                                          \
@@ -1531,7 +1656,7 @@ static bool launch_stream2(const Stream2Args &sa, int nk, T *arena, wmc_meta *me
     }
 #define WMC_S2(NKV, NPV, NQV)                                                                  \
     if (nk == NKV && a.np == NPV && a.nq == NQV) {                                             \
-        hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, lds, st, a, arena, meta, sg);  \
+        hipLaunchKernelGGL((k_stream2<T, NKV, NPV, NQV>), g, b, lds, st, t, arena, meta, sg);  \
         return true;                                                                           \
     }
 #define WMC_S2_PQ(NKV)                                                                         \
