@@ -278,13 +278,12 @@ def tune_executor(cases: Sequence[Tuple], precisions: Sequence[str] = ("fp64", "
     for prec in precisions:
         tuning_set(prec, None)
         cur = tuning_get(prec)
-        # objective: mean time relative to the built-in table, so that every
-        # case counts alike whatever its length
+        # objective: mean over the cases of a candidate's time relative to
+        # the current table's, both timed back to back (the device's clocks
+        # drift over a tuning run, so a baseline timed once at the start
+        # would favour whatever ran first); best_t is the product of the
+        # accepted ratios, i.e. the time relative to the built-in table
         base = _time_plans(cases, prec, reps)
-
-        def score(ts):
-            return sum(t / b for t, b in zip(ts, base)) / len(base)
-
         best_t = 1.0
         trace = [{"table": dict(cur), "s": base}]
         for _ in range(passes):
@@ -296,13 +295,16 @@ def tune_executor(cases: Sequence[Tuple], precisions: Sequence[str] = ("fp64", "
                     trial = dict(cur, **{field: v})
                     tuning_set(prec, trial)
                     ts = _time_plans(cases, prec, reps)
-                    t = score(ts)
-                    trace.append({field: v, "s": ts})
+                    tuning_set(prec, cur)
+                    tb = _time_plans(cases, prec, reps)
+                    r = sum(t / b for t, b in zip(ts, tb)) / len(tb)
+                    trace.append({field: v, "s": ts, "current": tb})
                     if log:
-                        log(f"{prec} {field}={v}: relative {t:.4f} (best {best_t:.4f}) "
-                            f"[{', '.join(f'{x * 1e3:.2f}' for x in ts)} ms]")
-                    if t < best_t * 0.995:
-                        best_t, cur, changed = t, trial, True
+                        log(f"{prec} {field}={v}: {r:.4f} of the current table "
+                            f"[{', '.join(f'{x * 1e3:.2f}' for x in ts)} vs "
+                            f"{', '.join(f'{x * 1e3:.2f}' for x in tb)} ms]")
+                    if r < 0.995:
+                        best_t, cur, changed = best_t * r, trial, True
                 tuning_set(prec, cur)
             if not changed:
                 break
