@@ -45,7 +45,7 @@ typedef enum {
     WMC_ERR_DEVICE = 4,           /* a HIP call failed; message in wmc_last_error() */
     WMC_ERR_BUSY = 5,             /* server queue full */
     WMC_ERR_UNSUPPORTED = 6,      /* rank too large, supplied tree over factored clauses,
-                                     sliced plan in a server */
+                                     more than 16 sliced variables in a served plan */
     WMC_ERR_CANCELLED = 7         /* serving: the request was cancelled or passed its deadline */
 } wmc_status;
 
@@ -386,8 +386,13 @@ wmc_status wmc_batch_image(const wmc_batch *b, void *dst, uint64_t dst_bytes, ui
  * admitted ones.
  * A server owns a caller-supplied device buffer: two staging areas for step
  * descriptors (2 * step_bytes), a result table, and the request regions (at
- * most hbm_budget_bytes).  Registered structures are unsliced plans of the
- * server's precision.  A request (structure, weight vector) waits in a FIFO
+ * most hbm_budget_bytes).  Registered structures are plans of the server's
+ * precision.  A sliced plan (at most 16 sliced variables) serves each request
+ * as one part per slice of Algorithm 3, every part queued, admitted and
+ * stepped like a request of its own; the request answers once, with the
+ * parts' values summed in slice order as wmc_contract sums them, or with
+ * WMC_ERR_CANCELLED if any part was cancelled or passed its deadline (a
+ * full queue is judged by the parts).  A request (structure, weight vector) waits in a FIFO
  * queue until a slot is free and a region of its footprint (its plan's meta
  * table + arena) fits in the budget: admission by HBM footprint.  Each step
  * runs the next launch of every admitted request's plan in shared kernels;

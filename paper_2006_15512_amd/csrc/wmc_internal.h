@@ -3,6 +3,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <cmath>
+
 #include <string>
 #include <vector>
 
@@ -97,3 +99,40 @@ struct wmc_plan_t {
 };
 
 void wmc_set_error(const char *fmt, ...);
+
+// Running sum (s + c) * 2^e of normalised slice values m * 2^e, Neumaier
+// compensated, renormalised after every add: the arithmetic of the solo
+// executor's finish kernel, so a batch of slices gives the solo result.
+struct SliceSum {
+    double s = 0.0, c = 0.0;
+    long long e = 0;
+    void add(double v, long long ev) {
+        if (v == 0.0) return;
+        if (s == 0.0 && c == 0.0) {
+            s = v;
+            c = 0.0;
+            e = ev;
+            return;
+        }
+        if (ev > e) {
+            const long long d = e - ev;
+            const int di = d < -4000 ? -4000 : (int)d;
+            s = std::ldexp(s, di);
+            c = std::ldexp(c, di);
+            e = ev;
+        }
+        const long long d = ev - e;
+        const double t = std::ldexp(v, d < -4000 ? -4000 : (int)d);
+        const double r = s + t;
+        if (std::fabs(s) >= std::fabs(t)) c += (s - r) + t;
+        else c += (t - r) + s;
+        s = r;
+        if (s != 0.0) {
+            int k;
+            s = std::frexp(s, &k);
+            c = std::ldexp(c, -k);
+            e += k;
+        }
+    }
+};
+

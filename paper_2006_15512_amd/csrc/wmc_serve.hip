@@ -1,7 +1,7 @@
 // Serving: weight-vector queries against registered formula structures, with
 // continuous batching.
 //
-// Every registered structure is an unsliced plan whose descriptors (leaves,
+// Every registered structure is a plan whose descriptors (leaves,
 // nodes, streaming tasks, matrix nodes and the lookup tables of the merged
 // kernels) are uploaded once, at registration, into the server's buffer and
 // stay there.  A request (structure, weights) is admitted when a slot is
@@ -19,7 +19,11 @@
 // frees its slot and region.  Each request's descriptors are its plan's, read
 // relative to its region, so its arithmetic is the same alone or in any mix.
 // A request can be cancelled, or given a deadline; either ends it with
-// WMC_ERR_CANCELLED.
+// WMC_ERR_CANCELLED.  A request on a sliced structure runs as one part per
+// slice (Algorithm 3), each admitted, stepped and released like a request
+// of its own with the slice's bits in its leaf fill; the parts' values are
+// summed in slice order with the finish kernel's arithmetic once the last
+// one is done, so the request's value is wmc_contract's.
 #include <chrono>
 #include <deque>
 #include <map>
@@ -68,6 +72,7 @@ struct SStruct {
     uint64_t meta_bytes = 0, arena_bytes = 0, footprint = 0;
     int64_t leaf_work = 0;
     uint64_t max_step_bytes = 0;  // largest staging contribution of one request in one step
+    int64_t nslices = 1;          // slices of the plan: parts per request
 };
 
 struct SReq {
@@ -80,6 +85,20 @@ struct SReq {
     double t_arrive = 0, t_admit = 0;
     double deadline = 0;          // server clock, 0 = none
     bool cancelled = false;
+    uint64_t slice = 0;           // sliced structures: this part's slice bits
+    int64_t agg = -1;             // sliced structures: key of the request's parts record
+};
+
+// The parts of a request on a sliced structure: their values by slice,
+// and how many are still to complete.
+struct SAgg {
+    uint64_t id = 0;
+    int32_t s = 0;
+    double t_arrive = 0, t_admit = -1;
+    int64_t left = 0;
+    bool cancelled = false;
+    std::vector<double> m;
+    std::vector<long long> e;
 };
 
 struct FinishEntry {
@@ -102,6 +121,7 @@ struct ClearRange {
 struct ServeWork {
     unsigned sb0, sn;
     long long abase, mbase;
+    unsigned long long eta;  // slice bits of the request's part (sliced structures)
     const double *w;
     const StreamTask *tasks;
     const int *block_task;
@@ -168,7 +188,7 @@ __global__ void __launch_bounds__(256) k_step_serve(const ServeWork *__restrict_
                          meta + w.mbase);
         else
             leaf_item<T>(const_desc<LeafDesc>(rec.desc), (long long)rec.item + (long long)lane, w.w, arena + w.abase,
-                         meta + w.mbase, 0ull);
+                         meta + w.mbase, w.eta);
         return;
     }
     const ServeBlock &b = blocks[bx];
@@ -238,6 +258,8 @@ struct wmc_server {
     int parity = 0;                              // parity of the step in flight
     std::vector<SReq> finishing;                 // requests whose last launch is in flight
     std::vector<wmc_response> done;
+    std::map<int64_t, SAgg> aggs;                // requests on sliced structures with parts left
+    int64_t next_agg = 0;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -355,8 +377,8 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
         wmc_set_error("wmc_serve_register: plan precision differs from the server's");
         return WMC_ERR_INVALID_ARGUMENT;
     }
-    if (!plan->sliced.empty()) {
-        wmc_set_error("wmc_serve_register: sliced plans are not served");
+    if (plan->sliced.size() > 16) {
+        wmc_set_error("wmc_serve_register: %zu sliced variables (at most 16 are served)", plan->sliced.size());
         return WMC_ERR_UNSUPPORTED;
     }
     try {
@@ -374,6 +396,7 @@ extern "C" wmc_status wmc_serve_register(wmc_server *v, const wmc_plan_t *plan, 
         s.footprint = s.meta_bytes + s.arena_bytes;
         s.leaf_work = plan->leaf_work;
         s.nleaves = (int32_t)plan->leaves.size();
+        s.nslices = (int64_t)1 << plan->sliced.size();
         // image, offsets relative to its start
         std::vector<uint8_t> img;
         auto put = [&](const void *src, size_t bytes) {
@@ -470,11 +493,11 @@ static wmc_status serve_submit_at(wmc_server *v, int32_t structure, const double
         wmc_set_error("wmc_serve_submit: unknown structure %d", structure);
         return WMC_ERR_INVALID_ARGUMENT;
     }
-    if ((int64_t)v->queue.size() >= v->opt.max_queue) {
+    const SStruct &s = v->S[(size_t)structure];
+    if ((int64_t)v->queue.size() + s.nslices > v->opt.max_queue) {
         wmc_set_error("wmc_serve_submit: queue full (%d)", v->opt.max_queue);
         return WMC_ERR_BUSY;
     }
-    const SStruct &s = v->S[(size_t)structure];
     SReq r;
     r.id = request_id;
     r.s = structure;
@@ -495,7 +518,24 @@ static wmc_status serve_submit_at(wmc_server *v, int32_t structure, const double
     r.w.insert(r.w.end(), s.w_aux.begin(), s.w_aux.end());
     if (deadline > 0.0) {
         v->next_deadline = v->queued_deadlines ? std::min(v->next_deadline, deadline) : deadline;
-        ++v->queued_deadlines;
+        v->queued_deadlines += s.nslices;
+    }
+    if (s.nslices > 1) {
+        SAgg a;
+        a.id = request_id;
+        a.s = structure;
+        a.t_arrive = t_arrive;
+        a.left = s.nslices;
+        a.m.assign((size_t)s.nslices, 0.0);
+        a.e.assign((size_t)s.nslices, 0);
+        r.agg = v->next_agg++;
+        v->aggs.emplace(r.agg, std::move(a));
+        for (int64_t q = 0; q < s.nslices; ++q) {
+            SReq part = r;
+            part.slice = (uint64_t)q;
+            v->queue.push_back(std::move(part));
+        }
+        return WMC_OK;
     }
     v->queue.push_back(std::move(r));
     return WMC_OK;
@@ -524,36 +564,74 @@ extern "C" wmc_status wmc_serve_submit_deadline(wmc_server *v, int32_t structure
     return serve_submit_at(v, structure, weights, request_id, t, t + timeout_s);
 }
 
-static void respond_cancelled(wmc_server *v, const SReq &r) {
+// A request (or one part of a request on a sliced structure) is done:
+// with its value (m * 2^e) or cancelled.  A request answers once: a sliced
+// one when its last part is done, cancelled if any part was.
+static void complete(wmc_server *v, const SReq &r, bool ok, double m, long long e) {
     wmc_response resp;
     std::memset(&resp, 0, sizeof resp);
     resp.request_id = r.id;
     resp.structure = r.s;
-    resp.status = WMC_ERR_CANCELLED;
-    resp.value = make_value(0.0, 0);
     resp.t_arrive = r.t_arrive;
     resp.t_admit = r.t_admit;
     resp.t_done = v->now();
+    if (r.agg < 0) {
+        resp.status = ok ? WMC_OK : WMC_ERR_CANCELLED;
+        resp.value = ok ? make_value(m, e) : make_value(0.0, 0);
+        v->done.push_back(resp);
+        return;
+    }
+    auto it = v->aggs.find(r.agg);
+    if (it == v->aggs.end()) return;
+    SAgg &a = it->second;
+    if (ok) {
+        a.m[(size_t)r.slice] = m;
+        a.e[(size_t)r.slice] = e;
+    } else {
+        a.cancelled = true;
+    }
+    if (r.t_admit > 0 && (a.t_admit < 0 || r.t_admit < a.t_admit)) a.t_admit = r.t_admit;
+    if (--a.left > 0) return;
+    resp.t_arrive = a.t_arrive;
+    resp.t_admit = a.t_admit < 0 ? 0.0 : a.t_admit;
+    if (a.cancelled) {
+        resp.status = WMC_ERR_CANCELLED;
+        resp.value = make_value(0.0, 0);
+    } else {
+        SliceSum acc;  // slice order, as the solo executor sums them
+        for (size_t q = 0; q < a.m.size(); ++q) acc.add(a.m[q], a.e[q]);
+        resp.status = WMC_OK;
+        resp.value = (acc.s == 0.0 && acc.c == 0.0) ? make_value(0.0, 0) : make_value(acc.s + acc.c, acc.e);
+    }
     v->done.push_back(resp);
+    v->aggs.erase(it);
 }
+
+static void respond_cancelled(wmc_server *v, const SReq &r) { complete(v, r, false, 0.0, 0); }
 
 extern "C" wmc_status wmc_serve_cancel(wmc_server *v, uint64_t request_id) {
     if (!v) {
         wmc_set_error("wmc_serve_cancel: server is NULL");
         return WMC_ERR_INVALID_ARGUMENT;
     }
-    for (auto it = v->queue.begin(); it != v->queue.end(); ++it)
+    // every part of the request (one unless its structure is sliced)
+    bool found = false;
+    for (auto it = v->queue.begin(); it != v->queue.end();) {
         if (it->id == request_id) {
             respond_cancelled(v, *it);
             if (it->deadline > 0.0) --v->queued_deadlines;
-            v->queue.erase(it);
-            return WMC_OK;
+            it = v->queue.erase(it);
+            found = true;
+            continue;
         }
+        ++it;
+    }
     for (SReq &r : v->active)
         if (r.id == request_id && !r.cancelled) {
             r.cancelled = true;  // released once no step in flight can touch its region
-            return WMC_OK;
+            found = true;
         }
+    if (found) return WMC_OK;
     wmc_set_error("wmc_serve_cancel: request %llu is not queued or running", (unsigned long long)request_id);
     return WMC_ERR_INVALID_ARGUMENT;
 }
@@ -574,16 +652,9 @@ static wmc_status serve_collect(wmc_server *v) {
             v->free_slots.push_back(r.slot);
             continue;
         }
-        wmc_response resp;
-        std::memset(&resp, 0, sizeof resp);
-        resp.request_id = r.id;
-        resp.structure = r.s;
-        resp.status = WMC_OK;
-        resp.value = s.root < 0 ? make_value(1.0, 0) : make_value(res[r.slot].m, res[r.slot].e);
-        resp.t_arrive = r.t_arrive;
-        resp.t_admit = r.t_admit;
-        resp.t_done = t;
-        v->done.push_back(resp);
+        (void)t;
+        if (s.root < 0) complete(v, r, true, 0.5, 1);  // the empty product: 1
+        else complete(v, r, true, res[r.slot].m, res[r.slot].e);
         region_free(v, r.region, s.footprint);
         v->free_slots.push_back(r.slot);
     }
@@ -678,6 +749,7 @@ static wmc_status serve_issue_t(wmc_server *v, int h, std::vector<SReq> &finishi
         std::memset(&w, 0, sizeof w);
         w.abase = abase;
         w.mbase = mbase;
+        w.eta = r.slice;
         long long woff = -1;
         bool used = false;
         if (r.k == 0) {

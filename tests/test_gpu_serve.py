@@ -252,3 +252,87 @@ def test_serve_deadlines_and_wait(structures):
     assert all(by[q].status == W.CANCELLED for q in range(2, 8))
     m, e = oracle.bucket(structures[0].with_weights(w[0]))
     assert rel(frac(by[0].value), Fraction(m) * Fraction(2) ** e) <= 1e-12
+
+
+def _sliced_structure(precision):
+    """A banded formula whose plan (rank 12) is sliced to rank 11: 8 slices."""
+    f = wl.banded_3cnf(80, 280, 16, seed=2)
+    p = W.Plan(W.Network.from_formula(f), seed=0, rank_cap=11, precision=precision)
+    assert p.stats()["n_slices"] >= 4
+    return f, p
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_serve_sliced_structure_in_a_mix(structures, precision, tol):
+    """Requests on a sliced structure run as one part per slice among
+    requests on unsliced ones: each answers once, equal to wmc_contract on
+    the same plan (bit for bit in FP64) and to the oracle, and the same
+    served alone."""
+    f, sp = _sliced_structure(precision)
+    srv, plans, ids = make_server(structures, precision, max_slots=12, buffer_bytes=1 << 29)
+    sid = srv.register(sp)
+    rng = np.random.default_rng(31)
+    reqs = []
+    for q in range(16):
+        if q % 3 == 0:
+            w = rng.uniform(0.1, 0.9, size=f.n)
+            reqs.append((None, np.stack([1 - w, w], axis=1)))
+            srv.submit(sid, reqs[-1][1], q)
+        else:
+            s = int(rng.integers(0, len(structures)))
+            w = rng.uniform(0.1, 0.9, size=structures[s].n)
+            reqs.append((s, np.stack([1 - w, w], axis=1)))
+            srv.submit(ids[s], reqs[-1][1], q)
+    say(f"sliced serve {precision}: submitted")
+    out = srv.drain()
+    assert sorted(r.request_id for r in out) == list(range(16))  # one answer per request
+    got = {r.request_id: r for r in out}
+    for q, (s, Wt) in enumerate(reqs):
+        assert got[q].status == 0, q
+        form = f if s is None else structures[s]
+        m, e = oracle.bucket(form.with_weights(Wt))
+        assert rel(frac(got[q].value), Fraction(m) * Fraction(2) ** e) <= tol, q
+        if s is None:
+            solo = W.wmc_contract(sp, Wt)
+            if precision == "fp64":
+                assert (solo.mantissa, solo.exp2) == (got[q].value.mantissa, got[q].value.exp2), q
+            else:
+                assert rel(frac(solo), frac(got[q].value)) <= tol, q
+            alone = W.Server(precision=precision, max_slots=2, buffer_bytes=1 << 27)
+            aid = alone.register(sp)
+            alone.submit(aid, Wt, 0)
+            (r,) = alone.drain()
+            assert (r.value.mantissa, r.value.exp2) == (got[q].value.mantissa, got[q].value.exp2), q
+    st = srv.stats()
+    assert st["n_active"] == 0 and st["used_bytes"] == 0
+
+
+def test_serve_sliced_cancel_and_deadline(structures):
+    """Cancelling a sliced request while some parts run and others wait, or
+    letting its deadline pass, gives exactly one CANCELLED answer; regions
+    and slots come back and the other requests are untouched."""
+    f, sp = _sliced_structure("fp64")
+    srv, plans, ids = make_server(structures, max_slots=3, buffer_bytes=1 << 28)
+    sid = srv.register(sp)
+    rng = np.random.default_rng(32)
+    w = rng.uniform(0.1, 0.9, size=f.n)
+    Wt = np.stack([1 - w, w], axis=1)
+    srv.submit(sid, Wt, 0)                       # parts beyond 3 slots wait
+    srv.submit_deadline(sid, Wt, 1, 1e-9)        # passes at once
+    srv.submit(sid, Wt, 2)
+    x = rng.uniform(0.1, 0.9, size=structures[0].n)
+    W3 = np.stack([1 - x, x], axis=1)
+    srv.submit(ids[0], W3, 3)
+    srv.step()
+    srv.step()
+    srv.cancel(0)                                # some parts running, some queued
+    out = srv.drain()
+    assert sorted(r.request_id for r in out) == [0, 1, 2, 3]
+    got = {r.request_id: r for r in out}
+    assert got[0].status == W.CANCELLED and got[1].status == W.CANCELLED
+    m, e = oracle.bucket(f.with_weights(Wt))
+    assert got[2].status == 0 and rel(frac(got[2].value), Fraction(m) * Fraction(2) ** e) <= 1e-12
+    m, e = oracle.bucket(structures[0].with_weights(W3))
+    assert got[3].status == 0 and rel(frac(got[3].value), Fraction(m) * Fraction(2) ** e) <= 1e-12
+    st = srv.stats()
+    assert st["n_active"] == 0 and st["n_queued"] == 0 and st["used_bytes"] == 0
