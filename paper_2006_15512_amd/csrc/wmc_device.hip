@@ -340,6 +340,105 @@ extern "C" wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, 
     return WMC_OK;
 }
 
+// Largest value a run list can deposit (every source bit set).
+static unsigned long long deposit_all(const unsigned *runs, int n) {
+    unsigned long long out = 0;
+    for (int i = 0; i < n; ++i) out |= ((1ull << ((runs[i] >> 8) & 255u)) - 1ull) << (runs[i] >> 16);
+    return out;
+}
+
+// Every index map of the kernels is a bit deposit, so the largest address a
+// launch can form is the map of all ones: the OR of its table entries and
+// tile bits.  Checked for every launch against the ranks of the tensors it
+// reads and writes; every tensor against the arena.
+template <typename T>
+static bool validate_t(const wmc_plan_t &P, std::string *why) {
+    char buf[160];
+    auto fail = [&](size_t k, const char *what) {
+        std::snprintf(buf, sizeof buf, "launch %zu: %s", k, what);
+        *why = buf;
+        return false;
+    };
+    auto rank = [&](int t) { return (int)P.T[(size_t)t].layout.size(); };
+    auto fits = [](unsigned long long mx, int bits) { return bits >= 64 || (mx >> bits) == 0; };
+    const uint64_t arena_elems = P.arena_bytes / (uint64_t)P.elem;
+    for (size_t t = 0; t < P.T.size(); ++t)
+        if (P.T[t].off < 0 || (uint64_t)P.T[t].off + (1ull << rank((int)t)) > arena_elems) {
+            std::snprintf(buf, sizeof buf, "tensor %zu outside the arena", t);
+            *why = buf;
+            return false;
+        }
+    for (size_t k = 1; k < P.launches.size(); ++k) {
+        const Launch &Ln = P.launches[k];
+        Stream2Tab tb;
+        StreamMfmaArgs ma;
+        const int kern = solo_kernel<T>(P, k, &tb, &ma);
+        if (kern == WMC_KERNEL_GEMM_P || kern == WMC_KERNEL_GEMM) {
+            const GemmDesc &g = P.gemms[(size_t)Ln.pad];
+            int top[GR_N] = {0};
+            for (int q = 0; q < GR_N; ++q)
+                for (int r = 0; r < g.nrun[q]; ++r) top[q] = std::max(top[q], (int)g.run[q][r][2] + (int)g.run[q][r][1]);
+            const int ra = rank(g.ta), rb = rank(g.tb), rc = rank(g.tc);
+            if (top[GR_MU_A] > ra - 4 - g.nk || top[GR_BETA_A] > ra - 4 - g.nk || top[GR_NU_B] > rb - g.nk ||
+                top[GR_BETA_B] > rb - g.nk || top[GR_MU_C] > rc || top[GR_NU_C] > rc || top[GR_BETA_C] > rc ||
+                ra != g.nk + g.nb + g.nm || rb != g.nk + g.nb + g.nn || rc != g.nb + g.nm + g.nn)
+                return fail(k, "matrix node maps exceed its operands");
+        } else if (kern == WMC_KERNEL_STREAM_MFMA) {
+            unsigned long long c = 0, a = 0, b = 0;
+            for (int q = 0; q < ma.nch; ++q)
+                for (int v = 0; v < 16; ++v) {
+                    c |= ma.tabc[q][v];
+                    a |= ma.taba[q][v];
+                    b |= ma.tabb[q][v];
+                }
+            for (int v = 0; v < 16; ++v) {
+                a |= ma.lane_a[v] | ma.blk_a[v];
+                b |= ma.lane_b[v] | ma.blk_b[v];
+            }
+            for (int t = 0; t < ma.nt; ++t) c |= 1ull << ma.tpos[t];
+            const int nk = P.nodes[(size_t)Ln.first].nk;
+            if (!fits(c, ma.rc) || ma.rc != rank(ma.tc) || !fits(a, rank(ma.ta) - nk) || !fits(b, rank(ma.tb) - nk))
+                return fail(k, "matrix-core streaming tables exceed the node's tensors");
+        } else if (kern == WMC_KERNEL_STREAM2 || kern == WMC_KERNEL_STREAM2_SPLIT || kern == WMC_KERNEL_STREAM2_VEC) {
+            const Stream2Args &a = tb.a;
+            unsigned long long c = 0, so = 0, oo = 0;
+            for (int q = 0; q < tb.nch; ++q)
+                for (int v = 0; v < 16; ++v) {
+                    c |= tb.hr[q][v];
+                    so |= tb.hs[q][v];
+                    oo |= tb.ho[q][v];
+                }
+            for (int q = 0; q < 2; ++q)
+                for (int v = 0; v < 16; ++v) {
+                    c |= tb.lr[q][v];
+                    so |= tb.ls[q][v];
+                    oo |= tb.lo[q][v];
+                }
+            unsigned long long pq = 0;
+            for (int t = 0; t < a.np; ++t) pq |= 1ull << a.pbit[t];
+            for (int t = 0; t < a.nq; ++t) pq |= 1ull << a.qbit[t];
+            c |= pq | (a.vec ? 1ull : 0ull);
+            so |= deposit_all(a.srun, a.nsrun);
+            oo |= deposit_all(a.orun, a.norun);
+            const int nk = P.nodes[(size_t)Ln.first].nk;
+            if (!fits(c, a.rc) || a.rc != rank(a.tc) || !fits(so, rank(a.ts) - nk) || !fits(oo, rank(a.to) - nk))
+                return fail(k, "streaming tables exceed the node's tensors");
+        } else {
+            for (int32_t q = 0; q < Ln.count; ++q) {
+                const NodeDesc &d = P.nodes[(size_t)(Ln.first + q)];
+                if (d.rc != rank(d.tc) || !fits(deposit_all(d.ra, d.nra), rank(d.ta) - d.nk) ||
+                    !fits(deposit_all(d.rb, d.nrb), rank(d.tb) - d.nk))
+                    return fail(k, "node maps exceed the node's tensors");
+            }
+        }
+    }
+    return true;
+}
+
+bool wmc_validate_launches(const wmc_plan_t &P, std::string *why) {
+    return P.precision == WMC_FP64 ? validate_t<double>(P, why) : validate_t<float>(P, why);
+}
+
 // ---------------------------------------------------------------------------
 // Contraction without any device allocation: the workspace is a static
 // device array of WMC_NOALLOC_SCRATCH_BYTES.  Host code never passes the

@@ -1338,6 +1338,9 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
     I.workspace_bytes = P.workspace_bytes;
     I.n_launches = (int64_t)P.launches.size() + 2;  // + begin and finish kernels
     I.slice_group = P.group;
+    std::string why;
+    if (!wmc_validate_launches(P, &why))
+        WMC_FAIL(WMC_ERR_UNSUPPORTED, "wmc_plan: internal bounds check failed: %s", why.c_str());
     return WMC_OK;
 }
 

@@ -99,6 +99,10 @@ struct wmc_plan_t {
 };
 
 void wmc_set_error(const char *fmt, ...);
+// Bounds of every launch of a finished plan, proved on the host before
+// anything runs (built with the device code, which owns the kernels'
+// argument builders); false with a description at the first violation.
+bool wmc_validate_launches(const wmc_plan_t &P, std::string *why);
 
 // Running sum (s + c) * 2^e of normalised slice values m * 2^e, Neumaier
 // compensated, renormalised after every add: the arithmetic of the solo

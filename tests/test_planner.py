@@ -530,3 +530,34 @@ def test_checkpoint_refuses_other_weights_precision_or_formula(tmp_path):
         with pytest.raises(ValueError):
             W.contract_checkpointed(pg, path)
     assert W.checkpoint_identity(pg)["clauses_sha256"] != W.checkpoint_identity(p)["clauses_sha256"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_launch_is_bounds_checked(precision):
+    """wmc_plan proves on the host, for every launch, that the largest
+    address each kernel's index maps can form lies inside the tensors it
+    reads and writes (and every tensor inside the arena).  Driven through
+    every kernel family by varying the tuning fields that choose kernels and
+    tiles; a plan that failed the check would raise."""
+    import bench
+    f = wl.banded_3cnf(200, 700, 26, seed=6)
+    g = wl.grid_cnf(8, 16, 0.1, seed=2)
+    saved = W.tuning_get(precision)
+    variants = [{}, {"stream2_vec": 1 - saved["stream2_vec"]}, {"stream_mfma_min_bits": 0},
+                {"stream2_tile_bits": 1}, {"stream2_min_thread_bits": 0, "stream2_low_bits": 0},
+                {"split_lanes": 4 if precision == "fp64" else 0}, {"gemm_orient": 2}]
+    kinds = set()
+    try:
+        for v in variants:
+            W.tuning_set(precision, dict(saved, **v))
+            for net, kw in ((W.Network.from_formula(f), dict(block=4)), (W.Network.from_formula(f), dict(block=1)),
+                            (W.Network.from_formula(f), dict(block=3, rank_cap=17, slice_group=3)),
+                            (W.Network.from_formula(g), dict(kind="order", order=wl.row_major_order(8, 16), block=5))):
+                p = W.Plan(net, seed=0, precision=precision, **kw)
+                kinds |= {W.KERNEL_NAMES[k] for k in W.plan_kernels(p)}
+    finally:
+        W.tuning_set(precision, saved)
+    expect = {"k_nodes", "k_stream2", "k_stream_mfma", "k_gemm_p", "k_stream2_vec"}
+    if precision == "fp64":
+        expect.add("k_stream2_split")
+    assert expect <= kinds, kinds
