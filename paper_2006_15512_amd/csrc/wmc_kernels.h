@@ -1764,13 +1764,6 @@ __device__ __forceinline__ void stream_multi_body(TP tasks, int ntasks,
     if (lb == 0 && threadIdx.x == 0) meta[args.tc].exp = meta[args.ts].exp + meta[args.to].exp + sS + sO;
 }
 
-template <typename T, int NK>
-__global__ void __launch_bounds__(256) k_stream_multi(const StreamTask *__restrict__ tasks, int ntasks,
-                                                      T *__restrict__ arena, wmc_meta *meta,
-                                                      const int *__restrict__ block_task = nullptr) {
-    stream_multi_body<T, NK>(tasks, ntasks, arena, meta, block_task, blockIdx.x);
-}
-
 // One merged step of a batch or a server in a single launch: workgroups
 // [0, sblocks) run the streaming tasks (their summed-index groups
 // concatenated in nk order, group k starting at workgroup gblock[k] and task
@@ -1867,26 +1860,6 @@ static inline void block_task_table(const std::vector<StreamTask> &tasks, const 
             const unsigned long long e = stream_multi_blocks(tasks.data(), f, t + 1);  // end of task t
             const unsigned long long b = (unsigned long long)tasks[(size_t)t].block_begin;
             for (unsigned long long x = b; x < e; ++x) out.push_back(t - f);
-        }
-    }
-}
-
-template <typename T>
-static void launch_stream_multi(const StreamTask *dev_tasks, const StreamTask *host_tasks, const int *nk_first,
-                                T *arena, wmc_meta *meta, hipStream_t st, const int *dev_block_task = nullptr) {
-    // nk_first[k] .. nk_first[k+1] is the group of tasks with nk == k
-    unsigned long long toff = 0;  // offset of the group's entries in the block table
-    for (int k = 0; k < 4; ++k) {
-        const int f = nk_first[k], l = nk_first[k + 1];
-        if (f == l) continue;
-        const unsigned g = (unsigned)stream_multi_blocks(host_tasks, f, l);
-        const int *bt = dev_block_task ? dev_block_task + toff : nullptr;
-        toff += g;
-        switch (k) {
-        case 0: hipLaunchKernelGGL((k_stream_multi<T, 0>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
-        case 1: hipLaunchKernelGGL((k_stream_multi<T, 1>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
-        case 2: hipLaunchKernelGGL((k_stream_multi<T, 2>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
-        default: hipLaunchKernelGGL((k_stream_multi<T, 3>), dim3(g), dim3(256), 0, st, dev_tasks + f, l - f, arena, meta, bt); break;
         }
     }
 }
