@@ -329,6 +329,32 @@ def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_g
     return out
 
 
+def graph_replay_leg(W, torch, name, steps, warmup):
+    """One plan replayed from a HIP graph (a batch of one instance with its
+    descriptors resident): latency per solve, and equality with the solo
+    executor's result."""
+    f, pkw, desc, _ = workload(name)
+    pkw = dict(pkw)
+    blk = pkw.pop("block", 1)
+    plan = W.Plan(W.Network.from_formula(f), block=blk, **pkw)
+    b = W.Batch([plan])
+    ws = b.workspace()
+    stream = torch.cuda.current_stream()
+    flags = W.BATCH_GRAPH | W.BATCH_RESIDENT
+    b.contract(None, ws, stream, 0)  # descriptors into the workspace
+    for _ in range(max(warmup, 2)):
+        v = b.contract(None, ws, stream, flags)[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        v = b.contract(None, ws, stream, flags)[0]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solo_v = W.wmc_contract(plan)
+    return {"latency_ms_per_solve": round(dt / steps * 1e3, 4), "solves_s": round(steps / dt, 1),
+            "equals_solo_bitwise": (v.mantissa, v.exp2) == (solo_v.mantissa, solo_v.exp2)}
+
+
 def batch_leg(W, torch, steps, warmup):
     """512 small banded 3-CNF instances (n 30-150, ratio 3.0-4.2, window 20)
     contracted as one batch (merged launches, HIP graph replay), FP64 and
@@ -567,6 +593,7 @@ def main():
     c1 = solo(W, torch, "config1", "fp64", 20 * args.steps, args.warmup, 0, None)
     c1 = {k: c1[k] for k in ("workload", "solves_s", "ms_per_step", "steps", "max_rank", "n_nodes", "result")}
     c1["latency_ms_per_solve"] = c1.pop("ms_per_step")
+    c1["graph_replay"] = graph_replay_leg(W, torch, "config1", 20 * args.steps, args.warmup)
     log("batch of 512")
     batch = batch_leg(W, torch, args.steps, args.warmup)
     log("serving")

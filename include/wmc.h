@@ -352,7 +352,9 @@ wmc_status wmc_plan_kernels(const wmc_plan_t *plan, int32_t *kernel, int64_t cap
  * serialised internally). */
 typedef struct wmc_batch wmc_batch;
 
-#define WMC_BATCH_RESIDENT 1u /* descriptors already in this workspace from an earlier call */
+#define WMC_BATCH_RESIDENT 1u /* descriptors already in this workspace from an earlier call (the
+                                 first call of a batch on a workspace uploads them regardless; the
+                                 caller must not overwrite them between calls) */
 #define WMC_BATCH_GRAPH 2u    /* capture the launch sequence once per workspace as a HIP graph
                                  and replay it (captured on a private stream) */
 

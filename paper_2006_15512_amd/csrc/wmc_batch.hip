@@ -89,6 +89,7 @@ struct wmc_batch {
     std::vector<uint8_t> image;  // [off_leaf, off_arena) of the workspace
     std::mutex mu;
     void *graph_ws = nullptr;
+    void *image_ws = nullptr;  // workspace the descriptor image was last uploaded to
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
     ~wmc_batch() {
@@ -398,8 +399,13 @@ extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, vo
     }
     if (B.n_vars_total > 0)
         HIP_TRY(hipMemcpyAsync(ws + B.off_w, w, sizeof(double) * 2 * (size_t)B.n_vars_total, hipMemcpyHostToDevice, st));
-    if (!(flags & WMC_BATCH_RESIDENT))
+    // the image goes up unless the caller says it is there already and this
+    // batch did put it into this workspace (a first call on a workspace
+    // always uploads, whatever the flags say)
+    if (!(flags & WMC_BATCH_RESIDENT) || B.image_ws != workspace) {
         HIP_TRY(hipMemcpyAsync(ws + B.off_leaf, B.image.data(), B.desc_bytes, hipMemcpyHostToDevice, st));
+        B.image_ws = workspace;
+    }
     if (flags & WMC_BATCH_GRAPH) {
         if (B.exec && B.graph_ws != workspace) {
             HIP_TRY(hipGraphExecDestroy(B.exec));

@@ -202,3 +202,24 @@ def test_batch_with_big_nodes_vs_oracle():
             assert rel(frac(v), Fraction(m) * Fraction(2) ** e) <= 1e-12, q
             solo = W.wmc_contract(p)
             assert (solo.mantissa, solo.exp2) == (v.mantissa, v.exp2), q
+
+
+def test_batch_resident_flag_on_a_new_workspace():
+    """The first call of a batch on a workspace uploads the descriptors even
+    when the caller passes RESIDENT (they cannot be there yet), with or
+    without graph replay, and so does the first call on a second workspace:
+    every result equals the solo one bit for bit (FP64)."""
+    import torch
+    fs = [wl.batch_instance(i) for i in range(4)]
+    plans = [W.Plan(W.Network.from_formula(f), seed=i) for i, f in enumerate(fs)]
+    solo = [W.wmc_contract(p) for p in plans]
+    b = W.Batch(plans)
+    for flags in (W.BATCH_RESIDENT, W.BATCH_GRAPH | W.BATCH_RESIDENT):
+        for _ in range(2):  # a fresh workspace each time
+            ws = b.workspace()
+            ws.zero_()
+            torch.cuda.synchronize()
+            for rep in range(2):
+                got = b.contract(ws=ws, flags=flags)
+                for g, s in zip(got, solo):
+                    assert (g.mantissa, g.exp2) == (s.mantissa, s.exp2), (flags, rep)
