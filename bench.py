@@ -395,6 +395,20 @@ def batch_leg(W, torch, steps, warmup):
                "algorithmic_gbs": round(total_bytes / (ms_step * 1e-3) / 1e9, 1),
                "contraction_tflops": round(total_flops / (ms_step * 1e-3) / 1e12, 3),
                "zero_fraction": sum(1 for v in vals if v.mantissa == 0.0) / n_inst}
+        # the persistent form (one cooperative launch walks the merged steps)
+        pflags = W.BATCH_PERSISTENT | W.BATCH_RESIDENT
+        pv = b.contract(ws=ws, stream=stream, flags=W.BATCH_PERSISTENT)
+        for _ in range(warmup):
+            pv = b.contract(ws=ws, stream=stream, flags=pflags)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pv = b.contract(ws=ws, stream=stream, flags=pflags)
+        torch.cuda.synchronize()
+        pdt = (time.perf_counter() - t0) / steps
+        ent["persistent"] = {"ms_per_batch": round(pdt * 1e3, 4), "solves_s": round(n_inst / pdt, 1),
+                             "equals_graph_bitwise": [(v.mantissa, v.exp2) for v in pv] ==
+                             [(v.mantissa, v.exp2) for v in vals]}
         if gold is not None:
             errs = [rel_err((v.mantissa, v.exp2), g) for v, g in zip(vals, gold)]
             ent["max_rel_err_vs_oracle"] = max(errs)

@@ -357,6 +357,15 @@ typedef struct wmc_batch wmc_batch;
                                  caller must not overwrite them between calls) */
 #define WMC_BATCH_GRAPH 2u    /* capture the launch sequence once per workspace as a HIP graph
                                  and replay it (captured on a private stream) */
+#define WMC_BATCH_PERSISTENT 4u /* every merged step in one cooperative launch: one workgroup
+                                   per compute unit walks the steps, a grid-wide barrier
+                                   between them; results as without it, bit for bit. Batches
+                                   with matrix nodes run as without it. Takes precedence over
+                                   WMC_BATCH_GRAPH. Slower than graph replay on batches of
+                                   small formulas (the barriers and the low occupancy cost
+                                   more than the launches saved); WMC_ERR_UNSUPPORTED on a
+                                   device without cooperative launches, WMC_ERR_DEVICE if a
+                                   barrier wait times out (20 s) */
 
 wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n, wmc_batch **out);
 wmc_status wmc_batch_info(const wmc_batch *b, uint64_t *workspace_bytes, int64_t *n_launches,

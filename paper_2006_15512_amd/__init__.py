@@ -573,12 +573,14 @@ def version() -> str:
 # ---------------------------------------------------------------------------
 # batches
 # ---------------------------------------------------------------------------
-BATCH_RESIDENT = 1
-BATCH_GRAPH = 2
+BATCH_RESIDENT = 1  # descriptors already in this workspace from an earlier call
+BATCH_GRAPH = 2  # capture the launches once per workspace and replay the HIP graph
+BATCH_PERSISTENT = 4  # every merged step in one cooperative launch (exact; slower on small formulas)
 
 
 class Batch:
-    """wmc_batch_create over a list of unsliced plans of one precision."""
+    """wmc_batch_create over a list of plans of one precision (sliced plans
+    enter as one instance per slice)."""
 
     def __init__(self, plans: Sequence[Plan]):
         arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])

@@ -90,6 +90,11 @@ struct wmc_batch {
     std::mutex mu;
     void *graph_ws = nullptr;
     void *image_ws = nullptr;  // workspace the descriptor image was last uploaded to
+    // persistent form: the merged steps' arguments (absolute pointers into a
+    // workspace, so kept after the arena and rebuilt for a new workspace)
+    uint64_t off_steps = 0;
+    std::vector<StepArgs> steps_host;
+    void *steps_ws = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
     ~wmc_batch() {
@@ -281,7 +286,9 @@ extern "C" wmc_status wmc_batch_create(const wmc_plan_t *const *plans, int64_t n
         off += bal(sizeof(int) * std::max<size_t>(B->tables.size(), 1), 256);
         B->off_arena = off;
         B->arena_bytes = (uint64_t)arena_elems * (uint64_t)B->elem;
-        B->workspace_bytes = off + bal(B->arena_bytes, 256);
+        B->off_steps = off + bal(B->arena_bytes, 256);
+        // [barrier counter, flag][step arguments]
+        B->workspace_bytes = B->off_steps + 256 + bal(sizeof(StepArgs) * B->launches.size(), 256);
         B->desc_bytes = B->off_arena - B->off_leaf;
         B->image.assign(B->desc_bytes, 0);
         uint8_t *img = B->image.data();
@@ -318,12 +325,30 @@ extern "C" wmc_status wmc_batch_info(const wmc_batch *b, uint64_t *workspace_byt
 
 extern "C" void wmc_batch_destroy(wmc_batch *b) { delete b; }
 
+// Arguments of merged step k (a node launch) on workspace ws.
+static StepArgs step_args(const wmc_batch &B, char *ws, size_t k) {
+    const Launch &Ln = B.launches[k];
+    const int *tabs = (const int *)(ws + B.off_tables);
+    StepArgs a{};
+    const int tf = B.task_first[k];
+    if (B.task_nk[k][4] > 0)
+        step_stream_part(a, (const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf, B.task_nk[k].data(),
+                         tabs + B.btask_off[k]);
+    if (Ln.count) {
+        a.nodes = (const NodeDesc *)(ws + B.off_node) + Ln.first;
+        a.nnodes = Ln.count;
+        a.node_work = Ln.work;
+        a.wave_node = tabs + B.wave_off[k];
+        a.nblocks = grid_for(Ln.work);
+    }
+    return a;
+}
+
 template <typename T>
 static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
     wmc_meta *meta = (wmc_meta *)(ws + B.off_meta);
     const double *w = (const double *)(ws + B.off_w);
     const LeafDesc *L = (const LeafDesc *)(ws + B.off_leaf);
-    const NodeDesc *D = (const NodeDesc *)(ws + B.off_node);
     const GemmDesc *G = (const GemmDesc *)(ws + B.off_gemm);
     T *arena = (T *)(ws + B.off_arena);
     const int nt = (int)B.meta_total;
@@ -341,24 +366,74 @@ static void batch_launches(const wmc_batch &B, char *ws, hipStream_t st) {
             continue;
         }
         // the merged step's small nodes and streaming tasks in one launch
-        const int *tabs = (const int *)(ws + B.off_tables);
-        StepArgs a{};
-        const int tf = B.task_first[k];
-        if (B.task_nk[k][4] > 0)
-            step_stream_part(a, (const StreamTask *)(ws + B.off_tasks) + tf, B.tasks.data() + tf, B.task_nk[k].data(),
-                             tabs + B.btask_off[k]);
-        if (Ln.count) {
-            a.nodes = D + Ln.first;
-            a.nnodes = Ln.count;
-            a.node_work = Ln.work;
-            a.wave_node = tabs + B.wave_off[k];
-            a.nblocks = grid_for(Ln.work);
-        }
-        launch_step<T>(a, arena, meta, st);
+        launch_step<T>(step_args(B, ws, k), arena, meta, st);
     }
     hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n_inst + 255) / 256)), dim3(256), 0, st, arena,
                        (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n_inst,
                        (BatchRes *)(ws + B.off_res));
+}
+
+// Every merged step in one cooperative launch (batches without matrix
+// nodes): begin, leaves, the persistent step kernel on a grid the device
+// holds at once, finish.  Each step's work is k_step's, so the results are
+// the fused launches' bit for bit.
+template <typename T>
+static wmc_status batch_persistent(wmc_batch &B, char *ws, hipStream_t st, bool resident) {
+    // the step arguments go up with the descriptors (unless the caller says
+    // they are resident and this batch put them into this workspace)
+    if (B.steps_ws != (void *)ws) {
+        B.steps_host.clear();
+        for (size_t k = 1; k < B.launches.size(); ++k) B.steps_host.push_back(step_args(B, ws, k));
+    }
+    if ((B.steps_ws != (void *)ws || !resident) && !B.steps_host.empty())
+        HIP_TRY(hipMemcpyAsync(ws + B.off_steps + 256, B.steps_host.data(), sizeof(StepArgs) * B.steps_host.size(),
+                               hipMemcpyHostToDevice, st));
+    B.steps_ws = ws;
+    wmc_meta *meta = (wmc_meta *)(ws + B.off_meta);
+    const double *w = (const double *)(ws + B.off_w);
+    T *arena = (T *)(ws + B.off_arena);
+    const int nt = (int)B.meta_total;
+    hipLaunchKernelGGL(k_begin, dim3((nt + WMC_BLOCK - 1) / WMC_BLOCK), dim3(WMC_BLOCK), 0, st, meta, nt,
+                       (wmc_acc *)nullptr, 0);
+    if (!B.leaves.empty())
+        hipLaunchKernelGGL(k_leaves<T>, dim3(grid_for(B.leaf_work)), dim3(WMC_BLOCK), 0, st,
+                           (const LeafDesc *)(ws + B.off_leaf), (int)B.leaves.size(), (long long)B.leaf_work, w, arena,
+                           meta, SliceGroup{0, 0, 0}, 0ull, (const int *)(ws + B.off_tables) + B.leaf_tab_off,
+                           (const unsigned long long *)(ws + B.off_leaf_eta));
+    if (!B.steps_host.empty()) {
+        unsigned most = 1;
+        for (const StepArgs &a : B.steps_host) most = std::max(most, a.sblocks + a.nblocks + a.lblocks);
+        int dev = 0, ncu = 0, per = 0, coop = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        if (!coop) {
+            wmc_set_error("wmc_batch_contract: the device has no cooperative launches (WMC_BATCH_PERSISTENT)");
+            return WMC_ERR_UNSUPPORTED;
+        }
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_steps_persistent<T>, 256, 0));
+        if (per < 1 || ncu < 1) {
+            wmc_set_error("wmc_batch_contract: the persistent step kernel cannot be resident");
+            return WMC_ERR_DEVICE;
+        }
+        // one workgroup per compute unit: fewer workgroups starve the
+        // gathers, more make every barrier dearer (measured 128 to 1024)
+        const unsigned grid = std::min<unsigned>(most, (unsigned)ncu);
+        const StepArgs *steps = (const StepArgs *)(ws + B.off_steps + 256);
+        unsigned *bar = (unsigned *)(ws + B.off_steps);
+        int nsteps = (int)B.steps_host.size();
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 2);
+        int khz = 0;
+        HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        unsigned long long wait_ticks = (unsigned long long)std::max(khz, 1) * 1000ull * 20ull;  // 20 s
+        void *args[] = {(void *)&steps, (void *)&nsteps, (void *)&arena, (void *)&meta, (void *)&bar,
+                        (void *)&wait_ticks};
+        HIP_TRY(hipLaunchCooperativeKernel((const void *)k_steps_persistent<T>, dim3(grid), dim3(256), args, 0, st));
+    }
+    hipLaunchKernelGGL(k_finish_batch<T>, dim3((unsigned)((B.n_inst + 255) / 256)), dim3(256), 0, st, arena,
+                       (const long long *)(ws + B.off_rootoff), (const int *)(ws + B.off_roots), meta, (int)B.n_inst,
+                       (BatchRes *)(ws + B.off_res));
+    return WMC_OK;
 }
 
 extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, void *workspace,
@@ -406,7 +481,13 @@ extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, vo
         HIP_TRY(hipMemcpyAsync(ws + B.off_leaf, B.image.data(), B.desc_bytes, hipMemcpyHostToDevice, st));
         B.image_ws = workspace;
     }
-    if (flags & WMC_BATCH_GRAPH) {
+    const bool persistent = (flags & WMC_BATCH_PERSISTENT) && B.gemms.empty() && B.launches.size() > 1;
+    if (persistent) {
+        const bool resident = (flags & WMC_BATCH_RESIDENT) != 0;
+        const wmc_status ps = B.precision == WMC_FP64 ? batch_persistent<double>(B, ws, st, resident)
+                                                      : batch_persistent<float>(B, ws, st, resident);
+        if (ps != WMC_OK) return ps;
+    } else if (flags & WMC_BATCH_GRAPH) {
         if (B.exec && B.graph_ws != workspace) {
             HIP_TRY(hipGraphExecDestroy(B.exec));
             B.exec = nullptr;
@@ -435,7 +516,13 @@ extern "C" wmc_status wmc_batch_contract(wmc_batch *b, const double *weights, vo
     HIP_TRY(hipGetLastError());
     std::vector<BatchRes> h((size_t)B.n_inst);
     HIP_TRY(hipMemcpyAsync(h.data(), ws + B.off_res, sizeof(BatchRes) * (size_t)B.n_inst, hipMemcpyDeviceToHost, st));
+    unsigned gave_up = 0;
+    if (persistent) HIP_TRY(hipMemcpyAsync(&gave_up, ws + B.off_steps + 4, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (gave_up) {
+        wmc_set_error("wmc_batch_contract: a grid barrier of the persistent launch timed out");
+        return WMC_ERR_DEVICE;
+    }
     for (int64_t i = 0; i < B.n; ++i) {
         const int64_t j0 = B.inst_first[(size_t)i], j1 = B.inst_first[(size_t)i + 1];
         if (j1 - j0 == 1) {

@@ -1791,28 +1791,93 @@ struct StepArgs {
     unsigned lblocks;
 };
 
+// Workgroup bx of merged step a (every thread of the workgroup runs it).  A
+// macro rather than a function, so that both kernels keep the descriptor
+// reads on the scalar path: the compiler proves them unclobbered only in a
+// kernel's own body.
+#define WMC_STEP_BLOCK(T, a, bx, arena, meta)                                                                 \
+    do {                                                                                                      \
+        if ((bx) < (a).sblocks) {                                                                             \
+            int k_ = 0;                                                                                       \
+            while (k_ < 3 && (long long)(bx) >= (a).gblock[k_ + 1]) ++k_;                                     \
+            const StreamTask *t_ = (a).tasks + (a).gtask[k_];                                                 \
+            const int nt_ = (a).gtask[k_ + 1] - (a).gtask[k_];                                                \
+            const int *bt_ = (a).block_task ? (a).block_task + (a).gblock[k_] : nullptr;                      \
+            const unsigned blk_ = (bx) - (unsigned)(a).gblock[k_];                                            \
+            switch (k_) {                                                                                     \
+            case 0: stream_multi_body<T, 0>(t_, nt_, arena, meta, bt_, blk_); break;                          \
+            case 1: stream_multi_body<T, 1>(t_, nt_, arena, meta, bt_, blk_); break;                          \
+            case 2: stream_multi_body<T, 2>(t_, nt_, arena, meta, bt_, blk_); break;                          \
+            default: stream_multi_body<T, 3>(t_, nt_, arena, meta, bt_, blk_); break;                         \
+            }                                                                                                 \
+        } else if ((bx) < (a).sblocks + (a).nblocks) {                                                        \
+            nodes_body<T>((a).nodes, (a).nnodes, (a).node_work, arena, meta, (a).wave_node, (bx) - (a).sblocks, \
+                          (a).nblocks);                                                                       \
+        } else {                                                                                              \
+            leaves_body<T>((a).leaves, (a).nleaves, (a).leaf_work, (a).w, arena, meta, 0ull, (a).wave_leaf,   \
+                           (a).leaf_eta, (bx) - (a).sblocks - (a).nblocks, (a).lblocks);                      \
+        }                                                                                                     \
+    } while (0)
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_step(const StepArgs a, T *__restrict__ arena, wmc_meta *meta) {
-    const unsigned bx = blockIdx.x;
-    if (bx < a.sblocks) {
-        int k = 0;
-        while (k < 3 && (long long)bx >= a.gblock[k + 1]) ++k;
-        const StreamTask *t = a.tasks + a.gtask[k];
-        const int nt = a.gtask[k + 1] - a.gtask[k];
-        const int *bt = a.block_task ? a.block_task + a.gblock[k] : nullptr;
-        const unsigned blk = bx - (unsigned)a.gblock[k];
-        switch (k) {
-        case 0: stream_multi_body<T, 0>(t, nt, arena, meta, bt, blk); break;
-        case 1: stream_multi_body<T, 1>(t, nt, arena, meta, bt, blk); break;
-        case 2: stream_multi_body<T, 2>(t, nt, arena, meta, bt, blk); break;
-        default: stream_multi_body<T, 3>(t, nt, arena, meta, bt, blk); break;
+    WMC_STEP_BLOCK(T, a, blockIdx.x, arena, meta);
+}
+
+// Grid-wide barrier number n (1, 2, ...) of a launch whose counter bar[0]
+// starts at zero and whose workgroups are all resident: every thread
+// releases its writes at agent scope (all XCDs), one thread per workgroup
+// counts the arrival and waits for n * gridDim.x of them, and every thread
+// acquires before going on.  A wait longer than wait_ticks of the constant
+// wall clock gives up and sets bar[1] (the host reports it as an error), and
+// later barriers then wait no more, so that a broken launch ends instead of
+// hanging.
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned n, unsigned long long wait_ticks) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned target = n * gridDim.x;
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > wait_ticks) {
+                    __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
         }
-    } else if (bx < a.sblocks + a.nblocks) {
-        nodes_body<T>(a.nodes, a.nnodes, a.node_work, arena, meta, a.wave_node, bx - a.sblocks, a.nblocks);
-    } else {
-        leaves_body<T>(a.leaves, a.nleaves, a.leaf_work, a.w, arena, meta, 0ull, a.wave_leaf, a.leaf_eta,
-                       bx - a.sblocks - a.nblocks, a.lblocks);
     }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Persistent form: one cooperative launch walks every merged step of a
+// batch.  A step's workgroups are dealt to the resident grid (workgroup b
+// takes b, b + gridDim.x, ...), and a grid-wide barrier separates the steps,
+// so step k + 1 reads what step k wrote.  Every workgroup runs every step
+// and reaches every barrier; the work of a workgroup index is k_step's.  A
+// block barrier follows each index, since a workgroup may take several.
+template <typename T>
+__global__ void __launch_bounds__(256) k_steps_persistent(const StepArgs *__restrict__ steps, int nsteps,
+                                                          T *__restrict__ arena, wmc_meta *meta, unsigned *bar,
+                                                          unsigned long long wait_ticks) {
+    for (int k = 0; k < nsteps; ++k) {
+        const StepArgs &a = steps[k];
+        const unsigned total = a.sblocks + a.nblocks + a.lblocks;
+        for (unsigned bx = blockIdx.x; bx < total; bx += gridDim.x) {
+            WMC_STEP_BLOCK(T, a, bx, arena, meta);
+            __syncthreads();  // the block's max reduction reuses its LDS slots
+        }
+        grid_barrier(bar, (unsigned)k + 1, wait_ticks);
+    }
+}
+
+// Zeroes n words (the persistent launch's barrier counter and flag).
+static __global__ __attribute__((unused)) void k_zero_u32(unsigned *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 static inline bool stream_task(const NodeDesc &d, StreamTask *t) {

@@ -223,3 +223,35 @@ def test_batch_resident_flag_on_a_new_workspace():
                 got = b.contract(ws=ws, flags=flags)
                 for g, s in zip(got, solo):
                     assert (g.mantissa, g.exp2) == (s.mantissa, s.exp2), (flags, rep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_persistent_equals_launch_per_step(instances, precision):
+    """The persistent form (every merged step in one cooperative launch)
+    gives the launch-per-step results bit for bit, for unsliced and sliced
+    instances, on a first and a second workspace, with RESIDENT, and after
+    the workspace was overwritten (a call without RESIDENT); a batch with
+    matrix nodes, which runs the launch-per-step form under the flag, too."""
+    fs, _ = instances
+    plans = [W.Plan(W.Network.from_formula(f), seed=i, precision=precision) for i, f in enumerate(fs)]
+    for i, f in enumerate(fs[:6]):
+        r0 = W.Plan(W.Network.from_formula(f), seed=i).stats()["max_rank"]
+        plans.append(W.Plan(W.Network.from_formula(f), seed=i, rank_cap=r0 - 2, precision=precision))
+    b = W.Batch(plans)
+    want = [(v.mantissa, v.exp2) for v in b.contract()]
+    for k in range(2):
+        ws = b.workspace()
+        for flags in (W.BATCH_PERSISTENT, W.BATCH_PERSISTENT | W.BATCH_RESIDENT,
+                      W.BATCH_PERSISTENT | W.BATCH_GRAPH | W.BATCH_RESIDENT):
+            say(f"persistent {precision} workspace {k} flags {flags}")
+            got = b.contract(ws=ws, flags=flags)
+            assert [(v.mantissa, v.exp2) for v in got] == want, (k, flags)
+    # without RESIDENT the step arguments go up again with the descriptors
+    ws.zero_()
+    got = b.contract(ws=ws, flags=W.BATCH_PERSISTENT)
+    assert [(v.mantissa, v.exp2) for v in got] == want
+    big = [wl.banded_3cnf(120, 400, 24, seed=0)] + [wl.batch_instance(i) for i in range(3)]
+    bb = W.Batch([W.Plan(W.Network.from_formula(f), seed=s, precision=precision) for s, f in enumerate(big)])
+    say(f"persistent {precision} with matrix nodes")
+    want = [(v.mantissa, v.exp2) for v in bb.contract()]
+    assert [(v.mantissa, v.exp2) for v in bb.contract(flags=W.BATCH_PERSISTENT)] == want
