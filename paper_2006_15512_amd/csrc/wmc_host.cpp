@@ -922,6 +922,58 @@ static double rank_excess(const std::vector<TNode> &T, const std::vector<uint8_t
     return e;
 }
 
+// Fewest sliced variables that bring every storage rank to the cap, sets of
+// exactly k variables: the greedy growth of Algorithm 3 ranks candidates by
+// MemCost, not by how many over-cap tensors they reach, and can end with
+// more variables than the cap needs (every one doubles the slices).  Each
+// sliced variable lowers a tensor's rank by at most one, so a set must hold
+// at least (rank - cap) variables of every tensor; the search branches on
+// the variables of the tensor furthest above the cap and drops a branch as
+// soon as some tensor is further above it than the variables left.  The
+// distinct sets found (at most max_sets, within max_visits search steps)
+// go to `accept`, which returns false to stop.
+template <typename Accept>
+static void slice_sets_of_size(const std::vector<const TNode *> &hot, int32_t n, int32_t cap, int32_t k,
+                               long max_visits, size_t max_sets, Accept accept) {
+    std::vector<uint8_t> s((size_t)n + 1, 0);
+    std::vector<int32_t> chosen;
+    std::vector<std::vector<int32_t>> seen;
+    long visits = 0;
+    bool stop = false;
+    std::vector<int32_t> left_vars;
+    auto dfs = [&](auto &&self, int32_t left) -> void {
+        if (stop || ++visits > max_visits) return;
+        int32_t worst = 0;
+        const TNode *w = nullptr;
+        for (const TNode *t : hot) {
+            const int32_t e = srank(*t, s) - cap;
+            if (e > worst) {
+                worst = e;
+                w = t;
+            }
+        }
+        if (worst == 0) {
+            std::vector<int32_t> I = chosen;
+            std::sort(I.begin(), I.end());
+            if (std::find(seen.begin(), seen.end(), I) != seen.end()) return;
+            seen.push_back(I);
+            if (!accept(I) || seen.size() >= max_sets) stop = true;
+            return;
+        }
+        if (worst > left) return;
+        for (int32_t v : w->vars) {
+            if (s[(size_t)v]) continue;
+            s[(size_t)v] = 1;
+            chosen.push_back(v);
+            self(self, left - 1);
+            chosen.pop_back();
+            s[(size_t)v] = 0;
+            if (stop) return;
+        }
+    };
+    dfs(dfs, k);
+}
+
 static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &o, wmc_plan_t &P) {
     std::vector<TNode> &T = P.T;
     const size_t NT = T.size();
@@ -1034,6 +1086,36 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
                     return std::ldexp(flops_of(T, s2), (int)I.size());
                 };
                 if (work(I1) < work(I0)) I0.swap(I1);
+            }
+        }
+        if (o.rank_cap > 0 && (int32_t)I0.size() > rank0 - o.rank_cap) {
+            // fewer variables may meet the caps: the smallest size with a
+            // set that does, its sets ranked by the growth's own criterion
+            std::vector<const TNode *> hot;
+            for (const TNode &t : T)
+                if (srank(t, sl) > o.rank_cap) hot.push_back(&t);
+            std::vector<uint8_t> s2((size_t)n + 1, 0);
+            for (int32_t k = rank0 - o.rank_cap; k < (int32_t)I0.size(); ++k) {
+                std::vector<int32_t> best;
+                double best_key = 0, best_tie = 0;
+                slice_sets_of_size(hot, n, o.rank_cap, k, 200000, 64, [&](const std::vector<int32_t> &I) {
+                    for (int32_t v : I) s2[(size_t)v] = 1;
+                    if (!over(s2)) {
+                        const double key = objective == 1 ? flops_of(T, s2) : peak_live_aligned(T, s2, P.elem, P.root);
+                        const double tie = objective == 1 ? peak_live_aligned(T, s2, P.elem, P.root) : flops_of(T, s2);
+                        if (best.empty() || key < best_key || (key == best_key && tie < best_tie)) {
+                            best = I;
+                            best_key = key;
+                            best_tie = tie;
+                        }
+                    }
+                    for (int32_t v : I) s2[(size_t)v] = 0;
+                    return true;
+                });
+                if (!best.empty()) {
+                    I0 = best;
+                    break;
+                }
             }
         }
         P.sliced = I0;
