@@ -49,10 +49,11 @@ def workload(name: str):
     """(formula, plan kwargs, description, golden key) for a named workload."""
     if name == "banded300":
         f = wl.banded_3cnf(300, 1050, 37, seed=0)
-        return f, dict(kind="minfill", seed=0, rank_cap=27, block=4, slice_group=8), \
+        return f, dict(kind="minfill", tree_seeds=16, rank_cap=27, block=4, slice_group=8), \
             "banded random 3-CNF, 300 vars, 1050 clauses (ratio 3.5), window 37, w~U(0.05,0.95), seed 0; " \
-            "seeded min-fill order (max storage rank 30; 29 once blocked by 4) sliced to rank 27, 8 slices, " \
-            "all 8 side by side in every launch", \
+            "seeded min-fill tree (intermediates up to rank 30 unblocked, 29 once blocked by 4), the seed of " \
+            "0-15 with the least predicted time (TimeCost on the measured class rates, no device timing), " \
+            "sliced to rank 27, all slices side by side in every launch", \
             "banded300_m1050_W37_s0"
     if name == "grid24":
         f = wl.grid_cnf(24, 24, 0.10, seed=0)
@@ -75,6 +76,28 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def make_plan(W, f, precision: str, block: int, pkw: dict):
+    """The workload's plan.  With "tree_seeds" in its options, the min-fill
+    seed is chosen among seeds 0 .. tree_seeds-1 by the planner's cost model
+    (time_cost: TimeCost of Algorithm 1 over the device's measured class
+    rates); nothing is timed on the device.  Returns (plan, report or None)."""
+    pkw = dict(pkw)
+    nseeds = int(pkw.pop("tree_seeds", 0))
+    net = W.Network.from_formula(f)
+    if not nseeds:
+        return W.Plan(net, precision=precision, block=block, **pkw), None
+    from paper_2006_15512_amd.autotune import time_cost
+    t0 = time.perf_counter()
+    best = None
+    for seed in range(nseeds):
+        p = W.Plan(net, precision=precision, block=block, seed=seed, **pkw)
+        c = time_cost(p)
+        if best is None or c < best[0]:
+            best = (c, seed, p)
+    return best[2], {"candidates": nseeds, "seed": best[1], "n_slices": best[2].n_slices,
+                     "predicted_ms": round(best[0] * 1e3, 2), "plan_seconds": round(time.perf_counter() - t0, 2)}
+
+
 def source_digest() -> str:
     """Digest of what decides the launched kernels: their sources, the
     per-node kernel choice and the tuning table."""
@@ -85,16 +108,16 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(wname: str, precision: str, block: int, kernel: str):
+def traffic_for(wname: str, precision: str, block: int, kernel: str, tree_seed=None):
     """Counter-derived HBM bytes per launch of `kernel`, if the committed
-    profile was taken from the current kernel sources."""
+    profile was taken from the current kernel sources on the same tree."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
     ent = data.get(f"{wname}/{precision}/block{block}")
-    if not ent or ent.get("kernel_sources") != source_digest():
+    if not ent or ent.get("kernel_sources") != source_digest() or ent.get("tree_seed") != tree_seed:
         return None
     return ent.get("hbm_bytes_per_launch", {}).get(kernel)
 
@@ -219,19 +242,21 @@ def achievable(torch):
     return out
 
 
-def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_group=0):
+def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_group=0, tree_seed=None):
     """Time `steps` whole solves of one workload, then attribute per-launch
     HIP-event time to kernels; returns a dict with the throughput, the
     roofline of the dominant kernel and the error against the oracle."""
     f, pkw, desc, gkey = workload(name)
     pkw = dict(pkw)
-    net = W.Network.from_formula(f)
     blk = block if block > 0 else pkw.pop("block", 1)
     pkw.pop("block", None)
     if slice_group > 0:
         pkw["slice_group"] = slice_group
+    if tree_seed is not None:
+        pkw.pop("tree_seeds", None)
+        pkw["seed"] = tree_seed
     t0 = time.perf_counter()
-    plan = W.Plan(net, precision=precision, block=blk, **pkw)
+    plan, tree = make_plan(W, f, precision, blk, pkw)
     plan_s = time.perf_counter() - t0
     st = plan.stats()
     ws = W.workspace(plan)
@@ -288,7 +313,7 @@ def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_g
     ach_gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     ach_tf = d["flops"] / (d["ms"] * 1e-3) / 1e12
     bound = "hbm" if ach_gbs / HBM_PEAK_GBS >= ach_tf / peak_tf else "mfma"
-    traffic = traffic_for(name, precision, blk, dom)
+    traffic = traffic_for(name, precision, blk, dom, tree["seed"] if tree else pkw.get("seed"))
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -316,7 +341,7 @@ def solo(W, torch, name, precision, steps, warmup, block=0, probes=None, slice_g
         "algorithmic_gbs": round(total_bytes / (ms_step * 1e-3) / 1e9, 1),
         "max_rank": st["max_rank"], "max_rank_unsliced": st["max_rank_unsliced"], "n_nodes": st["n_nodes"],
         "n_slices": n_slices, "slice_group": st["slice_group"], "class_hist": st["class_hist"],
-        "plan_seconds": round(plan_s, 3),
+        "plan_seconds": round(plan_s, 3), "tree": tree,
         "workspace_bytes": st["workspace_bytes"],
         "result": {"mantissa": v.mantissa, "exp2": v.exp2, "log2": v.log2_abs},
         "roofline": roof, "kernels": table,
@@ -489,7 +514,7 @@ def profile_only(W, torch, args):
     pkw.pop("block", None)
     if args.slice_group > 0:
         pkw["slice_group"] = args.slice_group
-    plan = W.Plan(W.Network.from_formula(f), precision=args.precision, block=block, **pkw)
+    plan, _ = make_plan(W, f, args.precision, block, pkw)
     ws = W.workspace(plan)
     stream = torch.cuda.current_stream()
     for _ in range(max(args.steps, 1)):
@@ -600,6 +625,11 @@ def main():
                                       (head["result"]["mantissa"], head["result"]["exp2"]))
     fp32["speedup_vs_fp64"] = round(fp32["solves_s"] / head["solves_s"], 3)
     log(f"  {fp32['solves_s']} solves/s")
+    log("config 3 FP64 on the seed-0 tree (no tree choice)")
+    s0 = solo(W, torch, "banded300", "fp64", max(3, args.steps // 2), 1, 0, probes, tree_seed=0)
+    seed0 = {"solves_s": s0["solves_s"], "ms_per_step": s0["ms_per_step"], "n_slices": s0["n_slices"],
+             "algorithmic_gbs": s0["algorithmic_gbs"], "roofline_frac": s0["roofline"]["frac"],
+             "roofline_kernel": s0["roofline"]["kernel"], "rel_err_vs_oracle": s0.get("rel_err_vs_oracle")}
     log("config 2 (row-major sweep, min-fill sliced)")
     c2 = solo(W, torch, "grid24", "fp64", args.steps, args.warmup, 0, probes)
     c2m = solo(W, torch, "grid24_minfill", "fp64", max(3, args.steps // 4), 1, 0, probes)
@@ -627,7 +657,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": head["workload"], "precision": "fp64", "block": head["block"],
                    "max_rank_unsliced": head["max_rank_unsliced"], "max_rank": head["max_rank"],
-                   "n_slices": head["n_slices"], "n_nodes": head["n_nodes"]},
+                   "n_slices": head["n_slices"], "n_nodes": head["n_nodes"], "tree": head["tree"]},
         "contraction_tflops": head["contraction_tflops"],
         "algorithmic_gbs": head["algorithmic_gbs"],
         "rel_err_vs_oracle": head.get("rel_err_vs_oracle"),
@@ -635,6 +665,7 @@ def main():
         "roofline": head["roofline"],
         "kernels": head["kernels"],
         "fp32": fp32,
+        "seed0_tree": seed0,
         "config2": c2,
         "config2_minfill": c2m,
         "config1": c1,
