@@ -32,3 +32,25 @@ def test_traffic_entries_are_well_formed():
             assert bench.traffic_for(wname, prec, int(blk[5:]), "k_begin", other) is None
         else:
             assert got is None
+
+
+def test_headline_tree_is_the_least_time_cost_seed():
+    """The banded formula's benchmark plan is the min-fill tree whose seed,
+    among the candidates, has the least TimeCost; the seed-0 comparison
+    plans exactly seed 0; both meet the rank cap (host only: no device
+    timing enters the choice)."""
+    from paper_2006_15512_amd.autotune import time_cost
+    f, pkw, _, _ = bench.workload("banded300")
+    pkw = dict(pkw)
+    blk = pkw.pop("block")
+    plan, tree = bench.make_plan(W, f, "fp64", blk, pkw)
+    assert tree["candidates"] == pkw["tree_seeds"]
+    net = W.Network.from_formula(f)
+    opts = {k: v for k, v in pkw.items() if k != "tree_seeds"}
+    costs = [time_cost(W.Plan(net, precision="fp64", block=blk, seed=s, **opts)) for s in range(tree["candidates"])]
+    assert tree["seed"] == min(range(len(costs)), key=costs.__getitem__)
+    assert plan.stats()["max_rank"] <= pkw["rank_cap"] and plan.n_slices == tree["n_slices"]
+    fixed = dict(opts, seed=0)
+    p0, t0 = bench.make_plan(W, f, "fp64", blk, fixed)
+    assert t0 is None and p0.stats()["max_rank"] <= pkw["rank_cap"]
+    assert p0.n_slices >= plan.n_slices
