@@ -255,3 +255,25 @@ def test_batch_persistent_equals_launch_per_step(instances, precision):
     say(f"persistent {precision} with matrix nodes")
     want = [(v.mantissa, v.exp2) for v in bb.contract()]
     assert [(v.mantissa, v.exp2) for v in bb.contract(flags=W.BATCH_PERSISTENT)] == want
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_persistent_degenerate_instances(precision):
+    """The persistent form on batches whose plans have few or no node
+    launches (a single clause, a formula with an empty clause, a variable
+    in no clause, one tiny random formula): every value equals the
+    launch-per-step result bit for bit and the oracle's."""
+    from wmc_workloads import Formula
+    fs = [Formula(1, [[1]], np.array([[0.3, 0.7]])),
+          Formula(2, [[1, -2], []], np.array([[0.4, 0.6], [0.2, 0.8]])),
+          Formula(3, [[1, 2]], np.array([[0.5, 0.5], [0.1, 0.9], [0.25, 0.75]])),
+          wl.random_kcnf(6, 10, 3)]
+    for group in ([fs[0]], [fs[1]], fs[:3], fs):
+        plans = [W.Plan(W.Network.from_formula(f), precision=precision) for f in group]
+        b = W.Batch(plans)
+        want = b.contract()
+        got = b.contract(flags=W.BATCH_PERSISTENT)
+        assert [(v.mantissa, v.exp2) for v in got] == [(v.mantissa, v.exp2) for v in want]
+        for f, v in zip(group, got):
+            ref = Fraction(oracle.brute(f))
+            assert (frac(v) == 0) if ref == 0 else rel(frac(v), ref) <= (1e-12 if precision == "fp64" else 1e-5)
