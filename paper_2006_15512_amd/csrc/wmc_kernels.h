@@ -69,6 +69,26 @@ __device__ __forceinline__ void publish_max_block(wmc_meta *meta, int t, double 
     }
 }
 
+// Stores of a streaming node's output, marked non-temporal: a large output
+// is read back only by a later node, after far more data than the caches
+// hold has passed through them, so its lines need not be kept.  (The matrix
+// kernel's scattered 4- and 8-byte stores are not: they need the cache to
+// merge them into whole lines, and ran at half speed with the hint.)
+template <typename T>
+__device__ __forceinline__ void store_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_pair_nt(double *p, double a, double b) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(v2{a, b}, (v2 *)p);
+}
+__device__ __forceinline__ void store_pair_nt(float *p, float a, float b) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(v2{a, b}, (v2 *)p);
+}
+__device__ __forceinline__ void store_quad_nt(float *p, float a, float b, float c, float d) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(v4{a, b, c, d}, (v4 *)p);
+}
+
 // bit extraction of r along runs (src bit, length, dst bit)
 __device__ __forceinline__ unsigned long long pext_runs(unsigned long long r, const unsigned char (*runs)[3], int nr) {
     unsigned long long out = 0;
@@ -937,7 +957,7 @@ __global__ void __launch_bounds__(256) k_stream2(const Stream2Tab tab, T *__rest
 #pragma unroll
             for (int j = 0; j < Q; ++j) {
                 const T v = (T)ldexp(acc[i][j], se);
-                C[r0 | cP[i] | cQ[j]] = v;
+                store_nt(C + (r0 | cP[i] | cQ[j]), v);
                 vmax = fmax(vmax, fabs((double)v));
             }
     }
@@ -1063,7 +1083,7 @@ __global__ void __launch_bounds__(256) k_stream2_split(const Stream2Tab tab, T *
                 for (int b = 0; b < NP; ++b)
                     if ((f >> (NQ + b)) & 1) c |= 1ull << args.pbit[b];
                 const T v = (T)ldexp(acc[t], se);
-                C[c] = v;
+                store_nt(C + c, v);
                 vmax = fmax(vmax, fabs((double)v));
             }
         }
@@ -1156,7 +1176,7 @@ __global__ void __launch_bounds__(256) k_stream2_vec(const Stream2Tab tab, T *__
             for (int j = 0; j < Q; ++j) {
                 const T v0 = (T)ldexp(fma(sv[i][0], ov[j][0], 0.0), se);
                 const T v1 = (T)ldexp(fma(sv[i][1], ov[j][1], 0.0), se);
-                store_pair(C + (r0 | cP[i] | cQ[j]), v0, v1);
+                store_pair_nt(C + (r0 | cP[i] | cQ[j]), v0, v1);
                 vmax = fmax(vmax, fmax(fabs((double)v0), fabs((double)v1)));
             }
     }
@@ -1433,14 +1453,14 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
                 if constexpr (VB == 1) {
                     const T v0 = (T)ldexp((double)tile[at(li)], se);
                     const T v1 = (T)ldexp((double)tile[at(li | lds_pair)], se);
-                    store_pair(C + off, v0, v1);
+                    store_pair_nt(C + off, v0, v1);
                     vmax = fmax(vmax, fmax(fabs((double)v0), fabs((double)v1)));
                 } else {
                     const T v0 = (T)ldexp((double)tile[at(li)], se);
                     const T v1 = (T)ldexp((double)tile[at(li | lds_pair)], se);
                     const T v2 = (T)ldexp((double)tile[at(li | lds_b1)], se);
                     const T v3 = (T)ldexp((double)tile[at(li | lds_pair | lds_b1)], se);
-                    *(float4 *)(C + off) = make_float4(v0, v1, v2, v3);
+                    store_quad_nt(C + off, v0, v1, v2, v3);
                     vmax = fmax(vmax, fmax(fmax(fabs((double)v0), fabs((double)v1)),
                                            fmax(fabs((double)v2), fabs((double)v3))));
                 }
