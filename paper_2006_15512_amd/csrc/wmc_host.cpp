@@ -930,19 +930,19 @@ static double rank_excess(const std::vector<TNode> &T, const std::vector<uint8_t
 // at least (rank - cap) variables of every tensor; the search branches on
 // the variables of the tensor furthest above the cap and drops a branch as
 // soon as some tensor is further above it than the variables left.  The
-// distinct sets found (at most max_sets, within max_visits search steps)
-// go to `accept`, which returns false to stop.
+// distinct sets found (at most max_sets) go to `accept`, which returns false
+// to stop; every search step spends one unit of `budget` per over-cap
+// tensor it checks, and the search ends when the budget is gone.
 template <typename Accept>
 static void slice_sets_of_size(const std::vector<const TNode *> &hot, int32_t n, int32_t cap, int32_t k,
-                               long max_visits, size_t max_sets, Accept accept) {
+                               long long &budget, size_t max_sets, Accept accept) {
     std::vector<uint8_t> s((size_t)n + 1, 0);
     std::vector<int32_t> chosen;
     std::vector<std::vector<int32_t>> seen;
-    long visits = 0;
     bool stop = false;
-    std::vector<int32_t> left_vars;
     auto dfs = [&](auto &&self, int32_t left) -> void {
-        if (stop || ++visits > max_visits) return;
+        if (stop || budget <= 0) return;
+        budget -= (long long)hot.size();
         int32_t worst = 0;
         const TNode *w = nullptr;
         for (const TNode *t : hot) {
@@ -1088,17 +1088,21 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
                 if (work(I1) < work(I0)) I0.swap(I1);
             }
         }
-        if (o.rank_cap > 0 && (int32_t)I0.size() > rank0 - o.rank_cap) {
-            // fewer variables may meet the caps: the smallest size with a
-            // set that does, its sets ranked by the growth's own criterion
+        // (not past 24 variables: such plans run millions of slices either way)
+        if (o.rank_cap > 0 && (int32_t)I0.size() > rank0 - o.rank_cap && I0.size() <= 24) {
+            // fewer variables may meet the caps: sizes one below the current
+            // set's, downwards, each size's sets ranked by the growth's own
+            // criterion.  Slicing more never breaks a cap, so once a size has
+            // no set (or the search budget is gone) no smaller one has.
             std::vector<const TNode *> hot;
             for (const TNode &t : T)
                 if (srank(t, sl) > o.rank_cap) hot.push_back(&t);
             std::vector<uint8_t> s2((size_t)n + 1, 0);
-            for (int32_t k = rank0 - o.rank_cap; k < (int32_t)I0.size(); ++k) {
+            long long budget = 150000000;  // tensor checks over all sizes (about a second at most)
+            for (int32_t k = (int32_t)I0.size() - 1; k >= rank0 - o.rank_cap && budget > 0; --k) {
                 std::vector<int32_t> best;
                 double best_key = 0, best_tie = 0;
-                slice_sets_of_size(hot, n, o.rank_cap, k, 200000, 64, [&](const std::vector<int32_t> &I) {
+                slice_sets_of_size(hot, n, o.rank_cap, k, budget, 64, [&](const std::vector<int32_t> &I) {
                     for (int32_t v : I) s2[(size_t)v] = 1;
                     if (!over(s2)) {
                         const double key = objective == 1 ? flops_of(T, s2) : peak_live_aligned(T, s2, P.elem, P.root);
@@ -1112,10 +1116,8 @@ static wmc_status finalize_plan(const wmc_network &net, const wmc_plan_options &
                     for (int32_t v : I) s2[(size_t)v] = 0;
                     return true;
                 });
-                if (!best.empty()) {
-                    I0 = best;
-                    break;
-                }
+                if (best.empty()) break;
+                I0 = best;
             }
         }
         P.sliced = I0;
