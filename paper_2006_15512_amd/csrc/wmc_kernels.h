@@ -1393,6 +1393,15 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
         hdst[q] = VB + 8 + q < args.nt ? 1u << args.tdst[VB + 8 + q] : 0u;
         hoff[q] = VB + 8 + q < args.nt ? 1ull << args.tpos[VB + 8 + q] : 0ull;
     }
+    // columns are stored XOR-ed with row and block (fewer bank conflicts
+    // whichever of them the lanes walk): slot at(l).  at is linear over XOR
+    // (shifts, XORs and a mask), and the write-out index bits are disjoint,
+    // so at(x | y) = at(x) ^ at(y): the slots come from per-bit constants
+    auto at = [](unsigned l) { return l ^ (((l >> 4) ^ (l >> 8)) & 15u); };
+    const unsigned at_lo = at(lds_lo), at_pair = at(lds_pair), at_b1 = at(lds_b1);
+    unsigned at_h[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) at_h[q] = at(hdst[q]);
     const unsigned npair = 1u << (args.nt - VB);  // groups of V elements
     const unsigned nit = npair > 256u ? npair >> 8 : 1u;
     const unsigned long long tiles = 1ull << (args.rc - args.nt);
@@ -1438,28 +1447,27 @@ __global__ void __launch_bounds__(256) k_stream_mfma(const StreamMfmaArgs args, 
         if (wt + G < tiles) load_tile(wt + G);
         __syncthreads();
         for (unsigned it = 0; it < nit; ++it) {
-            unsigned li = lds_lo;
+            // LDS slot of the group's first element: at(lds_lo | bits of it),
+            // one XOR per bit with the tile-invariant slots above
+            unsigned a0 = at_lo;
             unsigned long long off = base | off_lo;
 #pragma unroll
             for (int q = 0; q < 3; ++q)
                 if ((it >> q) & 1u) {
-                    li |= hdst[q];
+                    a0 ^= at_h[q];
                     off |= hoff[q];
                 }
             if (threadIdx.x < npair) {
-                // columns are stored XOR-ed with row and block (fewer bank
-                // conflicts whichever of them the lanes walk)
-                auto at = [](unsigned l) { return l ^ (((l >> 4) ^ (l >> 8)) & 15u); };
                 if constexpr (VB == 1) {
-                    const T v0 = (T)ldexp((double)tile[at(li)], se);
-                    const T v1 = (T)ldexp((double)tile[at(li | lds_pair)], se);
+                    const T v0 = (T)ldexp((double)tile[a0], se);
+                    const T v1 = (T)ldexp((double)tile[a0 ^ at_pair], se);
                     store_pair_nt(C + off, v0, v1);
                     vmax = fmax(vmax, fmax(fabs((double)v0), fabs((double)v1)));
                 } else {
-                    const T v0 = (T)ldexp((double)tile[at(li)], se);
-                    const T v1 = (T)ldexp((double)tile[at(li | lds_pair)], se);
-                    const T v2 = (T)ldexp((double)tile[at(li | lds_b1)], se);
-                    const T v3 = (T)ldexp((double)tile[at(li | lds_pair | lds_b1)], se);
+                    const T v0 = (T)ldexp((double)tile[a0], se);
+                    const T v1 = (T)ldexp((double)tile[a0 ^ at_pair], se);
+                    const T v2 = (T)ldexp((double)tile[a0 ^ at_b1], se);
+                    const T v3 = (T)ldexp((double)tile[a0 ^ at_pair ^ at_b1], se);
                     store_quad_nt(C + off, v0, v1, v2, v3);
                     vmax = fmax(vmax, fmax(fmax(fabs((double)v0), fabs((double)v1)),
                                            fmax(fabs((double)v2), fabs((double)v3))));
