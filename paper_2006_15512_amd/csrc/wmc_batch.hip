@@ -400,6 +400,10 @@ static wmc_status batch_persistent(wmc_batch &B, char *ws, hipStream_t st, bool 
                            (const LeafDesc *)(ws + B.off_leaf), (int)B.leaves.size(), (long long)B.leaf_work, w, arena,
                            meta, SliceGroup{0, 0, 0}, 0ull, (const int *)(ws + B.off_tables) + B.leaf_tab_off,
                            (const unsigned long long *)(ws + B.off_leaf_eta));
+    // the barrier counter and the give-up flag start at zero (the host reads
+    // the flag after every persistent call)
+    unsigned *bar = (unsigned *)(ws + B.off_steps);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 2);
     if (!B.steps_host.empty()) {
         unsigned most = 1;
         for (const StepArgs &a : B.steps_host) most = std::max(most, a.sblocks + a.nblocks + a.lblocks);
@@ -420,9 +424,7 @@ static wmc_status batch_persistent(wmc_batch &B, char *ws, hipStream_t st, bool 
         // gathers, more make every barrier dearer (measured 128 to 1024)
         const unsigned grid = std::min<unsigned>(most, (unsigned)ncu);
         const StepArgs *steps = (const StepArgs *)(ws + B.off_steps + 256);
-        unsigned *bar = (unsigned *)(ws + B.off_steps);
         int nsteps = (int)B.steps_host.size();
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 2);
         int khz = 0;
         HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         unsigned long long wait_ticks = (unsigned long long)std::max(khz, 1) * 1000ull * 20ull;  // 20 s
